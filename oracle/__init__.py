@@ -1,0 +1,180 @@
+"""FP64 CPU oracle for the SPARKLING energy/gradient/projection path.
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, by the smoke check and by
+the CPU-baseline leg of the benchmark, never by the product package.  It is a
+thin ctypes wrapper over ``oracle.c`` (plain C99 + OpenMP, FP64), which
+computes every quantity straight from the paper's definitions; inputs in any
+float dtype are up-cast exactly to float64 before the call.
+
+Parity pins: closed forms, invariants, brute force and finite differences in
+``tests/test_oracle_pins.py``.  The one quantity without a pin is the cost
+value printed for the perturbation study (its inputs are not given): parity
+unpinned for that number only.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from pathlib import Path
+
+import numpy as np
+
+_HERE = Path(__file__).resolve().parent
+_SRC = _HERE / "oracle.c"
+_LIB = _HERE / "liboracle.so"
+_lib = None
+
+_i64 = ctypes.c_int64
+_dbl = ctypes.c_double
+_p = ctypes.c_void_p
+
+
+def build(force: bool = False) -> Path:
+    """Compile oracle.c into liboracle.so (gcc, -O2, OpenMP, no FMA contraction)."""
+    if force or not _LIB.exists() or _LIB.stat().st_mtime < _SRC.stat().st_mtime:
+        tmp = _LIB.with_suffix(".so.tmp%d" % os.getpid())
+        cmd = ["gcc", "-std=c99", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+               "-fPIC", "-shared", "-Wall", "-Wextra", "-o", str(tmp), str(_SRC), "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        build()
+        lib = ctypes.CDLL(str(_LIB))
+        for name, args in {
+            "orc_grad": [_i64, _p, _p, _p, _i64, _dbl, _p, _dbl, _i64, _p, _p, _p, _p, _p, _p],
+            "orc_energy": [_i64, _p, _p, _p, _i64, _dbl, _p, _dbl, _p],
+            "orc_rho_self_energy": [_i64, _dbl, _p, _dbl, _p],
+            "orc_alpha_beta": [_dbl] * 8 + [_p, _p],
+            "orc_project": [_i64, _i64, _p, _p, _p, _dbl, _dbl, _dbl, _i64, ctypes.c_int],
+            "orc_constraint_check": [_i64, _i64, _p, _p, _p, _dbl, _dbl, _dbl, _i64, _p],
+            "orc_step": [_i64, _i64, _p, _i64, _dbl, _p, _dbl, _dbl, _dbl, _i64, ctypes.c_int,
+                         _p, _p, _i64, _dbl, _p],
+            "orc_fd_directional": [_i64, _p, _p, _p, _i64, _dbl, _p, _dbl, _p, _dbl, _p],
+            "orc_num_threads": [],
+        }.items():
+            f = getattr(lib, name)
+            f.argtypes = args
+            f.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _check(rc: int, name: str):
+    if rc != 0:
+        raise ValueError(f"oracle {name} rejected its arguments (status {rc})")
+
+
+def num_threads() -> int:
+    return _load().orc_num_threads()
+
+
+def grad(K, rho, G: int, L: float, eps: float = 0.0, targets=None):
+    """Gradient of F at the listed targets (all if None).
+
+    Returns dict with dF, dFa, dFr of shape (3, n_t) and the unscaled
+    per-target potentials ua = sum_v rho_v H(K_i - x_v), ur = sum_j H(K_i - K_j).
+    """
+    K = _f64(K)
+    rho = _f64(rho)
+    p = K.shape[1]
+    if targets is None:
+        targets = np.arange(p, dtype=np.int64)
+    targets = np.ascontiguousarray(np.asarray(targets, dtype=np.int64))
+    n_t = targets.size
+    dF, dFa, dFr = (np.empty((3, n_t)) for _ in range(3))
+    ua, ur = np.empty(n_t), np.empty(n_t)
+    x, y, z = (np.ascontiguousarray(K[c]) for c in range(3))
+    rc = _load().orc_grad(p, _ptr(x), _ptr(y), _ptr(z), G, L, _ptr(rho), eps, n_t,
+                          _ptr(targets), _ptr(dF), _ptr(dFa), _ptr(dFr), _ptr(ua), _ptr(ur))
+    _check(rc, "grad")
+    return {"dF": dF, "dFa": dFa, "dFr": dFr, "ua": ua, "ur": ur, "targets": targets}
+
+
+def energy(K, rho, G: int, L: float, eps: float = 0.0):
+    """(F, Fa, Fr) of the objective."""
+    K = _f64(K)
+    rho = _f64(rho)
+    out = np.empty(3)
+    x, y, z = (np.ascontiguousarray(K[c]) for c in range(3))
+    rc = _load().orc_energy(K.shape[1], _ptr(x), _ptr(y), _ptr(z), G, L, _ptr(rho), eps, _ptr(out))
+    _check(rc, "energy")
+    return tuple(float(v) for v in out)
+
+
+def rho_self_energy(rho, G: int, L: float, eps: float = 0.0) -> float:
+    rho = _f64(rho)
+    out = np.empty(1)
+    _check(_load().orc_rho_self_energy(G, L, _ptr(rho), eps, _ptr(out)), "rho_self_energy")
+    return float(out[0])
+
+
+def alpha_beta(gmax, smax, raster_dt, dwell_dt, fov, kmax, gamma_bar, half_width):
+    a, b = np.empty(1), np.empty(1)
+    rc = _load().orc_alpha_beta(gmax, smax, raster_dt, dwell_dt, fov, kmax, gamma_bar,
+                                half_width, _ptr(a), _ptr(b))
+    _check(rc, "alpha_beta")
+    return float(a[0]), float(b[0])
+
+
+def project(K, n_shots: int, n_samples: int, L: float, a: float, b: float, te: int,
+            n_pit: int) -> np.ndarray:
+    """Per-shot projection of K (3, Nc*Ns); returns a new float64 array."""
+    K = _f64(K).copy()
+    rc = _load().orc_project(n_shots, n_samples, _ptr(K[0]), _ptr(K[1]), _ptr(K[2]),
+                             L, a, b, te, n_pit)
+    _check(rc, "project")
+    return K
+
+
+def constraint_check(K, n_shots: int, n_samples: int, L: float, a: float, b: float,
+                     te: int) -> np.ndarray:
+    K = _f64(K)
+    out = np.empty(4)
+    x, y, z = (np.ascontiguousarray(K[c]) for c in range(3))
+    rc = _load().orc_constraint_check(n_shots, n_samples, _ptr(x), _ptr(y), _ptr(z),
+                                      L, a, b, te, _ptr(out))
+    _check(rc, "constraint_check")
+    return out
+
+
+def step(K, rho, n_shots, n_samples, G, L, a, b, te, n_pit, k_prev, g_prev, it, eta_fixed,
+         eps: float = 0.0):
+    """One projected gradient step.  Returns (K_new, k_prev, g_prev, info dict)."""
+    K = _f64(K).copy()
+    k_prev = _f64(k_prev).copy()
+    g_prev = _f64(g_prev).copy()
+    rho = _f64(rho)
+    info = np.empty(10)
+    rc = _load().orc_step(n_shots, n_samples, _ptr(K), G, L, _ptr(rho), eps, a, b, te, n_pit,
+                          _ptr(k_prev), _ptr(g_prev), it, eta_fixed, _ptr(info))
+    _check(rc, "step")
+    d = {"eta": info[0], "F": info[1], "Fa": info[2], "Fr": info[3],
+         "viol": info[4:8].copy(), "bb_used": bool(info[8])}
+    return K, k_prev, g_prev, d
+
+
+def fd_directional(K, rho, G, L, delta, h, eps: float = 0.0) -> float:
+    """(F(K + h delta) - F(K - h delta)) / (2h), cancellation-free."""
+    K = _f64(K)
+    rho = _f64(rho)
+    delta = _f64(delta)
+    out = np.empty(1)
+    x, y, z = (np.ascontiguousarray(K[c]) for c in range(3))
+    rc = _load().orc_fd_directional(K.shape[1], _ptr(x), _ptr(y), _ptr(z), G, L, _ptr(rho),
+                                    eps, _ptr(delta), h, _ptr(out))
+    _check(rc, "fd_directional")
+    return float(out[0])

@@ -1,0 +1,409 @@
+"""Pins of the FP64 oracle against facts that do not come from the oracle itself.
+
+Each test targets a plausible mistake: a dropped 1/2 or 1/p factor, a wrong
+sign, a transposed difference, a wrong stencil, a mis-scaled bound.  Sources:
+closed forms, special cases with known answers, invariants of the
+definitions, brute force on tiny inputs, and the textbook mean distance in a
+cube.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2108_02991_amd import inputs
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+RNG = np.random.default_rng(1234)
+
+
+def grid_points(G, L):
+    ax = inputs.voxel_axis(G, L)
+    z, y, x = np.meshgrid(ax, ax, ax, indexing="ij")
+    return np.stack([x.ravel(), y.ravel(), z.ravel()])
+
+
+# --------------------------------------------------------------------------
+# Repulsion term: closed forms
+# --------------------------------------------------------------------------
+def test_two_points_closed_form():
+    K = np.array([[0.1, -0.2], [0.0, 0.3], [0.05, 0.0]])
+    d = K[:, 0] - K[:, 1]
+    u = d / np.linalg.norm(d)
+    r = oracle.grad(K, [1.0], 1, 0.5)
+    # grad_1 F^r = u/4, grad_2 F^r = -u/4 (1/p^2 with p = 2)
+    np.testing.assert_allclose(r["dFr"][:, 0], u / 4, rtol=0, atol=1e-16)
+    np.testing.assert_allclose(r["dFr"][:, 1], -u / 4, rtol=0, atol=1e-16)
+    _, _, Fr = oracle.energy(K, [1.0], 1, 0.5)
+    assert Fr == pytest.approx(np.linalg.norm(d) / 4, rel=1e-15)   # 1/(2p^2) * 2|d|
+
+
+def test_regular_octahedron_closed_form():
+    r0 = 0.3
+    K = np.zeros((3, 6))
+    for k in range(3):
+        K[k, 2 * k] = r0
+        K[k, 2 * k + 1] = -r0
+    g = oracle.grad(K, [1.0], 1, 0.5)["dFr"]
+    expect = (1 + 2 * math.sqrt(2)) / 36
+    np.testing.assert_allclose(g[:, 0], [expect, 0, 0], atol=1e-16)
+    np.testing.assert_allclose(g[:, 3], [0, -expect, 0], atol=1e-16)
+    _, _, Fr = oracle.energy(K, [1.0], 1, 0.5)
+    assert Fr == pytest.approx(r0 * (2 + 4 * math.sqrt(2)) / 12, rel=1e-15)
+
+
+def test_coincident_samples_contribute_zero_gradient():
+    K = np.array([[0.0, 0.0, 0.2], [0.0, 0.0, 0.0], [0.0, 0.0, 0.0]])
+    g = oracle.grad(K, [1.0], 1, 0.5)["dFr"]
+    # two samples at the origin: each sees only the third one
+    np.testing.assert_allclose(g[:, 0], [-1 / 9, 0, 0], atol=1e-17)
+    np.testing.assert_allclose(g[:, 2], [2 / 9, 0, 0], atol=1e-17)
+
+
+# --------------------------------------------------------------------------
+# Attraction <-> repulsion normalisation: samples at the voxel centres
+# --------------------------------------------------------------------------
+def test_equilibrium_uniform_density():
+    """p = M samples at the voxel centres, uniform rho: grad F = 0 and D = 0."""
+    G, L = 4, 0.5
+    K = grid_points(G, L)
+    rho = inputs.uniform_density(G)
+    r = oracle.grad(K, rho, G, L)
+    scale = np.abs(r["dFa"]).max()
+    assert scale > 1e-3
+    assert np.abs(r["dF"]).max() <= 1e-14 * scale
+    F, Fa, Fr = oracle.energy(K, rho, G, L)
+    Erho = oracle.rho_self_energy(rho, G, L)
+    assert abs(F - Erho) <= 1e-15 * Fa
+    assert Fa == pytest.approx(2 * Fr, rel=1e-14)
+
+
+def test_voxel_centres_nonuniform_density_closed_form():
+    """Samples at the voxel centres: grad_i F = (1/M) sum_v (rho_v - 1/M) u(x_i - x_v)."""
+    G, L = 3, 0.5
+    K = grid_points(G, L)
+    M = G ** 3
+    rho = RNG.uniform(0.2, 1.0, M)
+    rho /= rho.sum()
+    got = oracle.grad(K, rho, G, L)["dF"]
+    d = K[:, :, None] - K[:, None, :]                      # (3, i, v)
+    n = np.linalg.norm(d, axis=0)
+    u = np.where(n > 0, d / np.where(n > 0, n, 1), 0.0)
+    want = (u * (rho - 1.0 / M)[None, None, :]).sum(axis=2) / M
+    np.testing.assert_allclose(got, want, rtol=0, atol=1e-16)
+
+
+# --------------------------------------------------------------------------
+# Invariants of the repulsion gradient and of the objective
+# --------------------------------------------------------------------------
+def test_repulsion_gradient_sums_to_zero():
+    K = RNG.uniform(-0.5, 0.5, (3, 300))
+    g = oracle.grad(K, [1.0], 1, 0.5)["dFr"]
+    assert np.abs(g.sum(axis=1)).max() <= 1e-15 * np.abs(g).max() * 300 ** 0.5
+
+
+def test_repulsion_translation_and_reflection():
+    # dyadic coordinates and a dyadic shift: differences are exact
+    K = np.round(RNG.uniform(-0.5, 0.5, (3, 200)) * 2 ** 20) / 2 ** 20
+    shift = np.array([[0.125], [-0.25], [0.0625]])
+    a = oracle.grad(K, [1.0], 1, 0.5)
+    b = oracle.grad(K + shift, [1.0], 1, 0.5)
+    c = oracle.grad(-K, [1.0], 1, 0.5)
+    assert np.array_equal(a["dFr"], b["dFr"])
+    assert np.array_equal(a["ur"], b["ur"])
+    assert np.array_equal(a["dFr"], -c["dFr"])
+    perm = RNG.permutation(200)
+    d = oracle.grad(K[:, perm], [1.0], 1, 0.5)
+    np.testing.assert_allclose(d["dFr"], a["dFr"][:, perm], rtol=1e-15, atol=1e-18)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_discrepancy_nonnegative(seed):
+    rng = np.random.default_rng(seed)
+    G, L = 4, 0.5
+    K = rng.uniform(-L, L, (3, 50)) * rng.uniform(0.1, 1.0)
+    rho = rng.uniform(0, 1, G ** 3) ** 3
+    rho /= rho.sum()
+    F, _, _ = oracle.energy(K, rho, G, L)
+    assert F - oracle.rho_self_energy(rho, G, L) > 0
+
+
+def test_mean_distance_in_cube():
+    """F^r of a fine uniform grid -> 1/2 * mean distance in the cube (Robbins 0.6617...)."""
+    G, L = 16, 0.5
+    K = grid_points(G, L)
+    _, Fa, Fr = oracle.energy(K, inputs.uniform_density(G), G, L)
+    robbins = 0.6617071822671762 * 2 * L
+    assert Fr == pytest.approx(0.5 * robbins, rel=5e-3)
+    assert Fa == pytest.approx(robbins, rel=5e-3)
+
+
+# --------------------------------------------------------------------------
+# Brute force from the definitions, tiny inputs, pure Python
+# --------------------------------------------------------------------------
+def _brute_energy(K, rho, G, L):
+    p = K.shape[1]
+    ax = [-L + (i + 0.5) * (2 * L / G) for i in range(G)]
+    fa = 0.0
+    for i in range(p):
+        for iz in range(G):
+            for iy in range(G):
+                for ix in range(G):
+                    w = rho[ix + G * (iy + G * iz)]
+                    fa += w * math.dist((K[0, i], K[1, i], K[2, i]), (ax[ix], ax[iy], ax[iz]))
+    fr = 0.0
+    for i in range(p):
+        for j in range(p):
+            fr += math.dist(K[:, i], K[:, j])
+    return fa / p - fr / (2 * p * p), fa / p, fr / (2 * p * p)
+
+
+def test_energy_brute_force():
+    G, L = 3, 0.5
+    K = RNG.uniform(-L, L, (3, 7))
+    rho = RNG.uniform(0, 1, G ** 3)
+    rho /= rho.sum()
+    got = oracle.energy(K, rho, G, L)
+    want = _brute_energy(K, rho, G, L)
+    np.testing.assert_allclose(got, want, rtol=1e-13)
+
+
+def test_gradient_matches_brute_force_differences():
+    """Oracle gradient vs central differences of the brute-force energy."""
+    G, L = 2, 0.5
+    K = RNG.uniform(-L, L, (3, 5))
+    rho = RNG.uniform(0, 1, G ** 3)
+    rho /= rho.sum()
+    g = oracle.grad(K, rho, G, L)["dF"]
+    h = 1e-6
+    for c in range(3):
+        for i in range(5):
+            Kp, Km = K.copy(), K.copy()
+            Kp[c, i] += h
+            Km[c, i] -= h
+            fd = (_brute_energy(Kp, rho, G, L)[0] - _brute_energy(Km, rho, G, L)[0]) / (2 * h)
+            assert fd == pytest.approx(g[c, i], abs=1e-8)
+
+
+def test_fd_directional_matches_brute_force():
+    G, L = 2, 0.5
+    K = RNG.uniform(-L, L, (3, 6))
+    rho = RNG.uniform(0, 1, G ** 3)
+    rho /= rho.sum()
+    delta = inputs.rademacher((3, 6), 7)
+    h = 1e-4
+    got = oracle.fd_directional(K, rho, G, L, delta, h)
+    want = (_brute_energy(K + h * delta, rho, G, L)[0]
+            - _brute_energy(K - h * delta, rho, G, L)[0]) / (2 * h)
+    assert got == pytest.approx(want, rel=1e-9, abs=1e-13)
+
+
+def test_fd_sparse_direction_equals_dense_formula():
+    """Skipping pairs where nothing moves is exact: compare with an all-moving tiny shift."""
+    G, L = 3, 0.5
+    K = RNG.uniform(-L, L, (3, 40))
+    rho = RNG.uniform(0, 1, G ** 3)
+    rho /= rho.sum()
+    delta = np.zeros((3, 40))
+    delta[:, [3, 17, 29]] = inputs.rademacher((3, 3), 9)
+    h = 1e-4
+    sparse = oracle.fd_directional(K, rho, G, L, delta, h)
+    dense = (oracle.energy(K + h * delta, rho, G, L)[0]
+             - oracle.energy(K - h * delta, rho, G, L)[0]) / (2 * h)
+    assert sparse == pytest.approx(dense, rel=1e-7)
+
+
+@pytest.mark.parametrize("eps", [0.0, 1e-3])
+def test_fd_agrees_with_gradient(eps):
+    G, L = 4, 0.5
+    K = inputs.radial_spokes(8, 16, L, seed=3, jitter=0.05)
+    rho = inputs.radial_density(G, L, 0.1, 2.0)
+    g = oracle.grad(K, rho, G, L, eps)["dF"]
+    for k in range(5):
+        delta = inputs.rademacher(K.shape, 100 + k)
+        fd = oracle.fd_directional(K, rho, G, L, delta, 1e-5, eps)
+        assert fd == pytest.approx(float((g * delta).sum()), rel=1e-5, abs=1e-12)
+
+
+def test_regularised_kernel_diagonal():
+    """H(0) = eps enters F^r through the i = j terms: F^r = eps/(2p) for one point."""
+    eps = 0.01
+    K = np.zeros((3, 1))
+    _, _, Fr = oracle.energy(K, [1.0], 1, 0.5, eps)
+    assert Fr == pytest.approx(eps / 2, rel=1e-15)
+
+
+# --------------------------------------------------------------------------
+# Normalised speed/slew bounds (printed scanner constants)
+# --------------------------------------------------------------------------
+def test_alpha_beta_golden():
+    with open(os.path.join(GOLDEN, "alpha_beta.json")) as f:
+        gold = json.load(f)
+    for case in gold["cases"]:
+        a, b = oracle.alpha_beta(*case["args"])
+        assert a == pytest.approx(case["a"], rel=1e-5), case["name"]
+        assert b == pytest.approx(case["b"], rel=1e-5), case["name"]
+
+
+def test_samples_per_shot_printed():
+    # T_obs = 20.48 ms at a 10 us raster gives 2048 samples per shot
+    assert math.floor(20.48e-3 / 10e-6 + 1e-9) == 2048
+
+
+# --------------------------------------------------------------------------
+# Projection
+# --------------------------------------------------------------------------
+def test_projection_two_samples_te0():
+    a, b, L = 0.1, 0.05, 0.5
+    for seed in range(4):
+        k = np.random.default_rng(seed).uniform(-0.3, 0.3, (3, 2))
+        s = oracle.project(k, 1, 2, L, a, b, 0, 10000)
+        k1 = k[:, 1]
+        want = k1 * min(1.0, a / np.linalg.norm(k1))
+        assert np.array_equal(s[:, 0], [0, 0, 0])
+        np.testing.assert_allclose(s[:, 1], want, atol=1e-10)
+
+
+def test_projection_two_samples_free_ends():
+    a, b, L = 0.1, 0.05, 0.5
+    for seed in range(4):
+        k = np.random.default_rng(seed).uniform(-0.3, 0.3, (3, 2))
+        s = oracle.project(k, 1, 2, L, a, b, -1, 10000)
+        m, d = (k[:, 0] + k[:, 1]) / 2, k[:, 1] - k[:, 0]
+        f = min(1.0, a / np.linalg.norm(d))
+        np.testing.assert_allclose(s[:, 0], m - d / 2 * f, atol=1e-10)
+        np.testing.assert_allclose(s[:, 1], m + d / 2 * f, atol=1e-10)
+
+
+def test_projection_three_samples_slew_only():
+    a, b, L = 10.0, 0.02, 0.5
+    for seed in range(4):
+        k = np.random.default_rng(seed).uniform(-0.2, 0.2, (3, 3))
+        s = oracle.project(k, 1, 3, L, a, b, -1, 10000)
+        Mk = k[:, 0] - 2 * k[:, 1] + k[:, 2]
+        nrm = np.linalg.norm(Mk)
+        assert nrm > b
+        corr = Mk * (1 - b / nrm) / 6
+        want = k - np.outer(corr, [1.0, -2.0, 1.0])
+        np.testing.assert_allclose(s, want, atol=1e-10)
+
+
+def _feasible_shot(rng, Ns, a, b, L, te):
+    """A random smooth shot well inside Q (speed <= a/2, slew <= b/2)."""
+    acc = rng.normal(size=(3, Ns))
+    acc *= (0.5 * b) / np.linalg.norm(acc, axis=0).max()
+    vel = np.cumsum(acc, axis=1)
+    vmax = np.linalg.norm(vel, axis=0).max()
+    if vmax > 0.5 * a:
+        vel *= 0.5 * a / vmax
+    s = np.concatenate([np.zeros((3, 1)), np.cumsum(vel, axis=1)[:, :-1]], axis=1)
+    if te >= 0:
+        s = s - s[:, [te]]
+    assert np.abs(s).max() < L
+    return s
+
+
+def test_projection_feasible_is_fixed_point_bitwise():
+    rng = np.random.default_rng(5)
+    a, b, L = 0.05, 0.004, 0.5
+    shots = [_feasible_shot(rng, 40, a, b, L, 0) for _ in range(6)]
+    K = np.concatenate(shots, axis=1)
+    s = oracle.project(K, 6, 40, L, a, b, 0, 200)
+    assert np.array_equal(s, K)
+
+
+def test_projection_large_bounds_is_box_clamp_and_te():
+    rng = np.random.default_rng(6)
+    K = rng.uniform(-0.8, 0.8, (3, 5 * 30))
+    s = oracle.project(K, 5, 30, 0.5, 1e3, 1e3, 4, 50)
+    want = np.clip(K, -0.5, 0.5)
+    want[:, 4::30] = 0.0
+    assert np.array_equal(s, want)
+
+
+def test_projection_box_te_exact_and_violation_small():
+    from paper_2108_02991_amd import configs
+    w = configs.C5
+    K = inputs.radial_spokes(16, 256, w.half_width, seed=11, jitter=0.05)
+    a, b = oracle.alpha_beta(configs.GMAX, configs.SMAX, configs.RASTER_DT, configs.DWELL_DT,
+                             w.fov, w.kmax, configs.GAMMA_BAR, w.half_width)
+    s = oracle.project(K, 16, 256, 0.5, a, b, 0, 200)
+    v = oracle.constraint_check(s, 16, 256, 0.5, a, b, 0)
+    assert v[2] <= 1.0 and v[3] == 0.0
+    assert np.all(s[:, ::256] == 0.0)
+    assert v[0] < 1.05 and v[1] < 1.25
+    v0 = oracle.constraint_check(K, 16, 256, 0.5, a, b, 0)
+    assert v0[0] > 2 and v0[1] > 10          # the input was far outside Q
+
+
+def test_projection_variational_inequality():
+    """Converged output satisfies <k - s*, z - s*> <= 0 for feasible z."""
+    rng = np.random.default_rng(8)
+    a, b, L, Ns = 0.05, 0.004, 0.5, 24
+    k = rng.uniform(-0.3, 0.3, (3, Ns))
+    s = oracle.project(k, 1, Ns, L, a, b, 0, 100000)
+    v = oracle.constraint_check(s, 1, Ns, L, a, b, 0)
+    assert v[0] <= 1 + 1e-6 and v[1] <= 1 + 1e-6 and v[1] >= 1 - 1e-6   # slew bound active
+    for _ in range(20):
+        z = _feasible_shot(rng, Ns, a, b, L, 0)
+        assert float(((k - s) * (z - s)).sum()) <= 1e-7
+    # and it is closer to k than any of those feasible points
+    assert np.linalg.norm(k - s) <= min(np.linalg.norm(k - _feasible_shot(rng, Ns, a, b, L, 0))
+                                        for _ in range(20))
+
+
+def test_constraint_check_simple_values():
+    K = np.zeros((3, 4))
+    K[0] = [0.0, 0.1, 0.3, 0.3]
+    v = oracle.constraint_check(K, 1, 4, 0.5, 0.2, 0.1, 1)
+    assert v[0] == pytest.approx(1.0)                # |0.3 - 0.1| / 0.2
+    assert v[1] == pytest.approx(2.0)                # |0 - 0.2 + 0.0| ... max is 0.2/0.1
+    assert v[2] == pytest.approx(0.6)
+    assert v[3] == pytest.approx(0.1)
+
+
+# --------------------------------------------------------------------------
+# Step-size policy
+# --------------------------------------------------------------------------
+def _small_problem():
+    from paper_2108_02991_amd import configs
+    w = configs.C1
+    K = inputs.radial_spokes(4, 16, 0.5, seed=21, jitter=0.0)
+    rho = inputs.radial_density(4, 0.5, 0.05, 2.0)
+    a, b = oracle.alpha_beta(configs.GMAX, configs.SMAX, configs.RASTER_DT, configs.DWELL_DT,
+                             w.fov, w.kmax, configs.GAMMA_BAR, 0.5)
+    return K, rho, a, b
+
+
+def test_step_fixed_then_fallback():
+    K, rho, a, b = _small_problem()
+    z = np.zeros_like(K)
+    K1, kp, gp, info = oracle.step(K, rho, 4, 16, 4, 0.5, a, b, 0, 50, z, z, 0, 3.0)
+    assert info["eta"] == 3.0 and not info["bb_used"]
+    assert np.array_equal(kp, K)
+    g = oracle.grad(K, rho, 4, 0.5)["dF"]
+    assert np.array_equal(gp, g)
+    want = oracle.project(K - 3.0 * g, 4, 16, 0.5, a, b, 0, 50)
+    assert np.array_equal(K1, want)
+    # iteration >= 20 with k_prev = K: s = 0, s.y = 0 -> fall back to eta_fixed
+    _, _, _, info = oracle.step(K, rho, 4, 16, 4, 0.5, a, b, 0, 50, K, g, 20, 3.0)
+    assert info["eta"] == 3.0 and not info["bb_used"]
+
+
+def test_step_barzilai_borwein():
+    K, rho, a, b = _small_problem()
+    z = np.zeros_like(K)
+    K1, kp, gp, _ = oracle.step(K, rho, 4, 16, 4, 0.5, a, b, 0, 50, z, z, 0, 3.0)
+    _, _, _, info = oracle.step(K1, rho, 4, 16, 4, 0.5, a, b, 0, 50, kp, gp, 25, 3.0)
+    s = K1 - kp
+    y = oracle.grad(K1, rho, 4, 0.5)["dF"] - gp
+    sy = float((s * y).sum())
+    if sy > 0:
+        want = min(max(float((s * s).sum()) / sy, 0.3), 30.0)
+        assert info["bb_used"]
+        assert info["eta"] == pytest.approx(want, rel=1e-12)
+    else:
+        assert not info["bb_used"]
