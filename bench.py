@@ -1,0 +1,238 @@
+"""Benchmark: projected-gradient SPARKLING steps at 8.4 M samples on one MI355X.
+
+A step is one pass of the whole hot path through the C ABI (sparkling_step):
+all-pairs repulsion sweep, attraction sweep against the 192^3 density,
+slab combines, gradient and energies, the step-size policy, the descent
+update, the per-shot projection and the constraint check.  Inputs are
+synthetic (seeded jittered radial spokes, radial density) and resident in HBM
+before the timed region.
+
+Prints one JSON line.  `value` is pair interactions per second over the whole
+step (p^2 repulsion + p*G^3 attraction per step); the roofline object is for
+the dominant kernel (the repulsion sweep), timed live with HIP events on the
+stream it runs on.  The CPU baseline is the FP64 oracle timed on a bounded
+sample of targets of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# Published MI355X FP32 vector peak (packed FP32, 256 CU x 2.4 GHz).
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+# Algorithmic flops per pair of the sweeps with energy: 3 subtractions, 5 for
+# |d|^2, 1 reciprocal square root, 6 for the three force FMAs, 2 for the
+# energy FMA (repulsion); the attraction adds 1 for the density weight.
+FLOP_PER_PAIR_REPULSION = 17
+FLOP_PER_PAIR_ATTRACTION = 18
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=0)
+    ap.add_argument("--workload", default="c3_fp32_comp_8p4M")
+    ap.add_argument("--precision", default=None)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="approximate CPU time budget of the oracle baseline (0 = skip)")
+    ap.add_argument("--fp64-fraction", type=float, default=1.0 / 16,
+                    help="fraction of targets of the plain-FP64 comparison run (0 = skip)")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on one GPU only; multi-GPU runs are not supported "
+              f"(asked for {args.gpus})", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2108_02991_amd as spk
+    from paper_2108_02991_amd import configs
+
+    w = configs.WORKLOADS[args.workload]
+    precision = args.precision or w.precision
+    dev = torch.device("cuda:0")
+    spk.load_library()
+    a, b = spk.alpha_beta(configs.GMAX, configs.SMAX, configs.RASTER_DT, configs.DWELL_DT,
+                          w.fov, w.kmax, configs.GAMMA_BAR, w.half_width)
+    prm = spk.Params(w.n_shots, w.n_samples, w.grid, precision=precision,
+                     half_width=w.half_width, a_max=a, b_max=b, te_index=0, n_pit=w.n_pit)
+    p, M = prm.p, w.n_voxels
+
+    log(f"workload {w.name}: p={p} G={w.grid} precision={precision}")
+    K_host = w.trajectory()
+    rho_host = w.density()
+    K = torch.tensor(K_host, dtype=prm.dtype, device=dev)
+    rho = torch.tensor(rho_host, dtype=prm.dtype, device=dev)
+    state = spk.StepState(prm, dev)
+    spk.workspace(prm, dev)
+
+    # module load and first-launch costs, on a tiny problem (not a step)
+    tiny = spk.Params(2, 8, 2, precision=precision, a_max=a, b_max=b, n_pit=2)
+    Kt = torch.zeros((3, 16), dtype=prm.dtype, device=dev)
+    spk.step_(Kt, torch.full((8,), 0.125, dtype=prm.dtype, device=dev), tiny,
+              spk.StepState(tiny, dev), 0, 1.0)
+    torch.cuda.synchronize()
+    log("inputs resident, kernels loaded")
+
+    it = 0
+    for _ in range(args.warmup):
+        spk.step_(K, rho, prm, state, it, w.eta_fixed)
+        it += 1
+        log(f"warmup step done")
+    torch.cuda.synchronize()
+
+    spk.timing_reset()
+    spk.timing_enable(True)
+    infos = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        infos.append(spk.step_(K, rho, prm, state, it, w.eta_fixed))
+        it += 1
+        log(f"step {it} done: F={infos[-1]['F']:.9e} eta={infos[-1]['eta']:.4g}")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    spk.timing_enable(False)
+
+    kern = {}
+    for name, kind in (("repulsion", spk.KIND_REPULSION), ("attraction", spk.KIND_ATTRACTION),
+                       ("projection", spk.KIND_PROJECTION), ("other", spk.KIND_OTHER)):
+        ms, n, pairs = spk.timing_query(kind)
+        kern[name] = {"ms": ms, "launches": n, "pairs": pairs}
+
+    pairs_per_step = float(p) * p + float(p) * M
+    ms_per_step = 1e3 * elapsed / args.steps
+    value = pairs_per_step * args.steps / elapsed
+
+    rep = kern["repulsion"]
+    rep_avg_ms = rep["ms"] / max(rep["launches"], 1)
+    rep_pairs_per_launch = rep["pairs"] / max(rep["launches"], 1)
+    achieved = FLOP_PER_PAIR_REPULSION * rep_pairs_per_launch / (rep_avg_ms * 1e-3) / 1e12
+    att = kern["attraction"]
+    att_tflops = (FLOP_PER_PAIR_ATTRACTION * att["pairs"] / (att["ms"] * 1e-3) / 1e12
+                  if att["ms"] > 0 else None)
+    grad_ms = (rep["ms"] + att["ms"] + kern["other"]["ms"]) / args.steps
+
+    result = {
+        "metric": "pair-interactions/s & sec per gradient eval at 8.4M samples, FP32-comp vs FP64",
+        "value": value,
+        "unit": "pair-interactions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if precision == "plain_fp64" else "f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "n_shots": w.n_shots, "n_samples": w.n_samples, "p": p,
+                   "grid": w.grid, "precision": precision, "n_pit": w.n_pit,
+                   "pairs_per_step": pairs_per_step},
+        "s_per_grad_eval": grad_ms / 1e3,
+        "kernels": {
+            "repulsion": {"ms_per_step": rep["ms"] / args.steps, "launches_per_step":
+                          rep["launches"] / args.steps, "avg_launch_ms": rep_avg_ms,
+                          "pairs_per_s": rep["pairs"] / (rep["ms"] * 1e-3), "tflops": achieved},
+            "attraction": {"ms_per_step": att["ms"] / args.steps, "launches_per_step":
+                           att["launches"] / args.steps,
+                           "pairs_per_s": att["pairs"] / (att["ms"] * 1e-3) if att["ms"] else None,
+                           "tflops": att_tflops},
+            "projection_ms_per_step": kern["projection"]["ms"] / args.steps,
+            "other_ms_per_step": kern["other"]["ms"] / args.steps,
+        },
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK_TFLOPS,
+                     "traffic": None},
+        "last_step": {k: (v.tolist() if isinstance(v, np.ndarray) else v)
+                      for k, v in infos[-1].items()},
+    }
+
+    if args.fp64_fraction > 0 and precision != "plain_fp64":
+        result["fp64_plain"] = fp64_comparison(spk, torch, w, prm, K, rho, args.fp64_fraction, dev)
+
+    if args.cpu_seconds > 0:
+        result["cpu_baseline"] = cpu_baseline(w, K, rho, args.cpu_seconds)
+
+    print(json.dumps(result), flush=True)
+
+
+def fp64_comparison(spk, torch, w, prm, K, rho, fraction, dev):
+    """Plain-FP64 gradient on a leading block of targets, against every source.
+
+    Times the FP64 form on the same stored inputs (widened exactly) and reports
+    its rate, the full-gradient time that rate implies, and the relative L2
+    difference of the FP32-compensated rows from the FP64 rows.
+    """
+    p = prm.p
+    nt = max(1024, int(p * fraction))
+    nt = min(nt, p)
+    prm64 = spk.Params(prm.n_shots, prm.n_samples, prm.grid, precision="plain_fp64",
+                       half_width=prm.half_width)
+    K64 = K.double()
+    rho64 = rho.double()
+    spk.workspace(prm64, dev)
+    log(f"fp64 comparison on {nt} targets")
+    spk.timing_reset()
+    spk.timing_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g64 = spk.grad(K64, rho64, prm64, tgt=(0, nt))
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    spk.timing_enable(False)
+    rep_ms, _, rep_pairs = spk.timing_query(spk.KIND_REPULSION)
+    g32 = spk.grad(K, rho, prm, tgt=(0, nt))
+    torch.cuda.synchronize()
+    d = (g32.double() - g64).norm().item() / g64.norm().item()
+    pairs = float(nt) * (p + w.n_voxels)
+    del K64, rho64
+    return {"targets": nt, "sample": f"targets [0, {nt}) against all {p} samples and "
+            f"{w.n_voxels} cells", "s": dt, "pairs_per_s": pairs / dt,
+            "s_per_grad_eval_implied": dt * p / nt,
+            "repulsion_pairs_per_s": rep_pairs / (rep_ms * 1e-3),
+            "fp32_comp_rel_l2_vs_fp64": d}
+
+
+def cpu_baseline(w, K, rho, seconds):
+    """The FP64 oracle on a bounded sample of targets (all sources each)."""
+    import oracle
+    from paper_2108_02991_amd import inputs
+
+    Kh = K.detach().cpu().double().numpy()
+    rh = rho.detach().cpu().double().numpy()
+    p = Kh.shape[1]
+    per_target = p + w.n_voxels
+    probe = inputs.sample_targets(p, 8, seed=99)
+    t0 = time.perf_counter()
+    oracle.grad(Kh, rh, w.grid, w.half_width, 0.0, probe)
+    rate = probe.size * per_target / (time.perf_counter() - t0)
+    n = int(max(16, min(4096, seconds * rate / per_target)))
+    targets = inputs.sample_targets(p, n, seed=100)
+    log(f"cpu baseline: oracle on {targets.size} targets ({oracle.num_threads()} threads)")
+    t0 = time.perf_counter()
+    oracle.grad(Kh, rh, w.grid, w.half_width, 0.0, targets)
+    dt = time.perf_counter() - t0
+    pairs = float(targets.size) * per_target
+    return {"value": pairs / dt, "unit": "pair-interactions/s", "cores": oracle.num_threads(),
+            "kind": "oracle", "sample": f"{targets.size} random targets of {w.name}, each against "
+            f"all {p} samples and {w.n_voxels} cells (FP64, compensated sums), {dt:.1f} s",
+            "s_per_grad_eval_extrapolated": float(p) * per_target / (pairs / dt)}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,221 @@
+/*
+ * sparkling.h -- C ABI of libsparkling.so, the MI355X (gfx950) hot path of
+ * full-3D SPARKLING trajectory optimisation (arXiv 2108.02991).
+ *
+ * The library evaluates the objective of the paper's "3D SPARKLING
+ * formulation" section,
+ *
+ *     F(K) = F^a(K) - F^r(K),
+ *     F^a  = (1/p)     sum_i sum_v rho_v H(K[i] - x_v)     (attraction),
+ *     F^r  = 1/(2p^2)  sum_i sum_j H(K[i] - K[j])          (repulsion),
+ *
+ * with H(d) = |d|_2 (or the regularised sqrt(|d|^2 + eps^2) of Sec. "Choice
+ * of step size"), its gradient (Secs. "Evaluating F^a and its gradient" and
+ * "Evaluating F^r and its gradient"),
+ *
+ *     dF/dK[i] = (1/p) sum_v rho_v grad H(K[i] - x_v) - (1/p^2) sum_j grad H(K[i] - K[j]),
+ *
+ * the per-shot projection onto the hardware constraint set Q of Sec. "3D
+ * K-space sampling" (supplement, "Multi-shot projection step"), and one
+ * projected gradient step of the projected-gradient-descent equation with the
+ * step-size policy of Sec. "Choice of step size".
+ *
+ * Conventions shared by every entry point
+ *  - p = n_shots * n_samples samples in shot-lexicographic order: sample n of
+ *    shot c is index i = c * n_samples + n.
+ *  - K is passed as three device arrays kx, ky, kz of p elements each
+ *    (structure of arrays).  Element type: double for SPK_PLAIN_FP64, float
+ *    for every other precision.  rho and gradients use the same type.
+ *  - rho holds G^3 weights of a cell-centred grid over [-L, L]^3, x fastest:
+ *    weight v = ix + G*(iy + G*iz) sits at x_v = -L + (i + 1/2) * 2L/G per
+ *    axis.  The library uses the weights as given (callers normalise them to
+ *    sum 1, as the paper's density does).
+ *  - grad H(0) = 0: coincident samples (every shot passes the k-space centre
+ *    at the echo time) exert no force on each other.
+ *  - All device pointers must be on the current HIP device, 4-byte aligned
+ *    (8 for double), and must not alias each other except where an argument
+ *    is documented as in/out.  The caller owns every buffer, including the
+ *    workspace sized by spk_workspace_size(); the library allocates no device
+ *    memory.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Calls enqueue
+ *    their kernels on it and return without waiting, except that any call
+ *    writing a host output (a double* documented as "host") synchronises the
+ *    stream before returning.
+ *  - Arguments are validated before anything is enqueued: SPK_EINVAL and
+ *    SPK_EWORKSPACE mean nothing was launched and no output was written.
+ *    SPK_EDEVICE means a HIP call failed; outputs are then undefined.
+ *    spk_last_error() returns a text describing the last failure on the
+ *    calling thread.
+ *  - Results are deterministic: the same inputs give bit-identical outputs
+ *    on every run, for every target chunking of sparkling_grad.
+ */
+#ifndef SPARKLING_H
+#define SPARKLING_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SPK_OK = 0,
+    SPK_EINVAL = -1,        /* bad argument; nothing launched                     */
+    SPK_EWORKSPACE = -2,    /* workspace NULL or smaller than spk_workspace_size  */
+    SPK_EDEVICE = -3,       /* a HIP runtime call or launch failed                */
+    SPK_EUNSUPPORTED = -4,  /* valid but outside what this build implements       */
+    SPK_ENONFINITE = -5     /* the energy of a step was NaN or infinite           */
+} spk_status;
+
+typedef enum {
+    SPK_PLAIN_FP64 = 0,     /* double coordinates, pair math and accumulation           */
+    SPK_FP32_COMP = 1,      /* float pair math, per-tile float sums folded by two-sum   */
+    SPK_FP32_NAIVE = 2,     /* float pair math and one float running sum (diagnostic)   */
+    SPK_FP32_ACC64 = 3      /* float pair math, double accumulation per pair (diagn.)   */
+} spk_precision;
+
+enum {
+    SPK_FLAG_DISCREPANCY = 1   /* sparkling_energy also returns D = F - E_rho          */
+};
+
+typedef struct {
+    int64_t n_shots;      /* N_c >= 1                                                   */
+    int64_t n_samples;    /* N_s >= 1 (>= 2 for projection and step)                    */
+    int64_t grid;         /* G in [1, 1024]: rho is G^3 cells                           */
+    int32_t precision;    /* spk_precision                                              */
+    int32_t te_index;     /* sample pinned to the origin in every shot; -1 = none       */
+    double  half_width;   /* L > 0: sampling box [-L, L]^3 (the paper uses L = 1)       */
+    double  eps;          /* >= 0: H(d) = sqrt(|d|^2 + eps^2); 0 gives H = |d|          */
+    double  a_max;        /* per-raster-step speed bound (spk_alpha_beta), > 0          */
+    double  b_max;        /* per-raster-step slew bound (spk_alpha_beta), > 0           */
+    int32_t n_pit;        /* projection iterations, >= 0                                */
+    int32_t flags;        /* SPK_FLAG_*                                                 */
+} spk_params;
+
+/* Text of a status code (static storage). */
+const char *spk_status_string(int status);
+
+/* Detail of the last failure on the calling thread ("" if none). */
+const char *spk_last_error(void);
+
+/*
+ * Normalised speed and slew bounds (Sec. "3D K-space sampling"):
+ *   alpha = min(gamma_bar * gmax, 1 / (fov * dwell_dt)) / kmax,
+ *   beta  = gamma_bar * smax / kmax,
+ * scaled to one raster step of a trajectory in [-L, L]^3:
+ *   *a_max = alpha * raster_dt * L,  *b_max = beta * raster_dt^2 * L.
+ * gamma_bar is the gyromagnetic ratio over 2 pi (42.576e6 Hz/T for 1H);
+ * gmax in T/m, smax in T/m/s, times in s, fov in m, kmax in 1/m.
+ * Host only.  SPK_EINVAL if any input is not strictly positive.
+ */
+int spk_alpha_beta(double gmax, double smax, double raster_dt, double dwell_dt, double fov,
+                   double kmax, double gamma_bar, double half_width,
+                   double *a_max, double *b_max);
+
+/*
+ * Bytes of device workspace that every entry point below needs for these
+ * parameters (one size serves all of them).  Host only.
+ */
+int spk_workspace_size(const spk_params *prm, size_t *bytes);
+
+/*
+ * Energies of the objective ("3D SPARKLING formulation"): writes the host
+ * array out[4] = {F, F^a, F^r, D}, where D = F - E_rho and
+ * E_rho = 1/2 sum_{u,v} rho_u rho_v H(x_u - x_v) is the density's
+ * self-energy (D >= 0).  D costs a G^6 pair sweep and is NaN unless
+ * prm->flags has SPK_FLAG_DISCREPANCY.  Synchronises `stream`.
+ */
+int sparkling_energy(const spk_params *prm, const void *kx, const void *ky, const void *kz,
+                     const void *rho, double out[4], void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Gradient of F (Secs. "Evaluating F^a and its gradient", "Evaluating F^r
+ * and its gradient") for the targets i in [tgt_begin, tgt_end), 0 <= tgt_begin
+ * <= tgt_end <= p, against all p samples and all G^3 cells.
+ *   gx, gy, gz : device, element t - tgt_begin receives dF/dK[t] (K's type).
+ *   pot_a, pot_r : device doubles or NULL; element t - tgt_begin receives
+ *                  sum_v rho_v H(K[t] - x_v) and sum_j H(K[t] - K[j]).
+ *   energy : host double[3] or NULL; receives {F, F^a, F^r} and requires the
+ *            full range [0, p).  Synchronises `stream` when non-NULL.
+ * An empty range is valid, launches nothing and accepts NULL outputs.  Every
+ * chunking of [0, p) gives bit-identical rows.
+ */
+int sparkling_grad(const spk_params *prm, const void *kx, const void *ky, const void *kz,
+                   const void *rho, void *gx, void *gy, void *gz,
+                   int64_t tgt_begin, int64_t tgt_end, double *pot_a, double *pot_r,
+                   double *energy, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Per-shot projection onto Q (supplement, "Multi-shot projection step"), in
+ * place on kx, ky, kz: each shot s becomes an approximation of
+ * argmin_{s in Q} |s - k|^2 / 2 with Q = {|s|_inf <= L, s[te] = 0,
+ * |s[n+1] - s[n]| <= a_max, |s[n+2] - 2 s[n+1] + s[n]| <= b_max}, computed
+ * by prm->n_pit iterations of accelerated proximal gradient on the dual
+ * (step 1/20, cold start), all in double precision.  The box and the
+ * echo-time point hold exactly; a shot already strictly inside Q is
+ * returned unchanged.  viol: host double[4] or NULL, receives the
+ * constraint check of the result (see sparkling_constraint_check) and then
+ * synchronises `stream`.  n_samples must be in [2, 4096].
+ */
+int sparkling_project(const spk_params *prm, void *kx, void *ky, void *kz, double *viol,
+                      void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Normalised constraint violations of K (Sec. "3D K-space sampling"),
+ * host double[4]: {max |s[n+1]-s[n]| / a_max, max |s[n+2]-2s[n+1]+s[n]| / b_max,
+ * max |s|_inf / L, max_shots |s[te]|}; values <= 1 (resp. 0) are feasible.
+ * Computed in double from the stored values; NaN propagates.  Synchronises.
+ */
+int sparkling_constraint_check(const spk_params *prm, const void *kx, const void *ky,
+                               const void *kz, double viol[4], void *ws, size_t ws_bytes,
+                               void *stream);
+
+typedef struct {
+    int64_t iter;         /* in: iteration index t (0-based)                              */
+    double  eta_fixed;    /* in: fixed step size, used while t < 20 and as BB fallback    */
+    double  eta;          /* out: step size used                                          */
+    double  F, Fa, Fr;    /* out: energies at the input K                                 */
+    double  viol[4];      /* out: constraint check of the new K                           */
+    int32_t bb_used;      /* out: 1 if the Barzilai-Borwein step was taken                */
+    int32_t reserved;
+} spk_step_info;
+
+/*
+ * One projected gradient step (projected-gradient-descent equation,
+ * step-size policy of Sec. "Choice of step size"):
+ *   g = dF/dK at K;  eta = eta_fixed if iter < 20, else
+ *   eta = (s.s)/(s.y), s = K - k_prev, y = g - g_prev (all 3p coordinates,
+ *   double sums), clamped to [0.1, 10] * eta_fixed, or eta_fixed if s.y <= 0;
+ *   k_prev = K; g_prev = g; K = Pi_Q(K - eta g).
+ * kx, ky, kz: in/out.  k_prev, g_prev: device, 3p elements of K's type laid
+ * out [3][p], caller-owned state carried between calls (contents ignored
+ * while iter < 20).  info: host, in/out.  Synchronises `stream`.
+ * Returns SPK_ENONFINITE (after completing the step) if F is not finite.
+ */
+int sparkling_step(const spk_params *prm, void *kx, void *ky, void *kz, const void *rho,
+                   void *k_prev, void *g_prev, spk_step_info *info,
+                   void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Kernel timing.  While enabled, every kernel launch of the kinds below is
+ * bracketed by HIP events on the stream it runs on; spk_timing_query()
+ * waits for those events and returns, for one kind, the summed duration in
+ * ms, the launch count and the pair interactions processed.  Timing state is
+ * process-global and guarded by a mutex.
+ */
+enum {
+    SPK_KIND_REPULSION = 0,   /* all-pairs sample sweep                   */
+    SPK_KIND_ATTRACTION = 1,  /* sample x density-cell sweep              */
+    SPK_KIND_PROJECTION = 2,  /* per-shot projection                      */
+    SPK_KIND_OTHER = 3        /* reductions, combine, step, check         */
+};
+int spk_timing_enable(int on);
+int spk_timing_query(int kind, double *total_ms, int64_t *launches, double *pairs);
+int spk_timing_reset(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPARKLING_H */

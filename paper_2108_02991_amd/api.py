@@ -1,0 +1,314 @@
+"""Python binding of libsparkling.so: argument marshalling over ctypes only.
+
+Every computation runs in the library's HIP kernels; torch supplies device
+memory (the trajectory K as a (3, p) tensor, rho, outputs, the workspace) and
+the current stream.  The binding raises if the library was not built: there
+is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass, field
+from pathlib import Path
+
+import numpy as np
+import torch
+
+_PKG = Path(__file__).resolve().parent
+LIB_PATH = _PKG / "libsparkling.so"
+
+PRECISIONS = {"plain_fp64": 0, "fp32_comp": 1, "fp32_naive": 2, "fp32_acc64": 3}
+FLAG_DISCREPANCY = 1
+KIND_REPULSION, KIND_ATTRACTION, KIND_PROJECTION, KIND_OTHER = 0, 1, 2, 3
+
+_i32, _i64, _dbl, _vp, _sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p, ctypes.c_size_t
+
+
+class SpkParams(ctypes.Structure):
+    _fields_ = [("n_shots", _i64), ("n_samples", _i64), ("grid", _i64), ("precision", _i32),
+                ("te_index", _i32), ("half_width", _dbl), ("eps", _dbl), ("a_max", _dbl),
+                ("b_max", _dbl), ("n_pit", _i32), ("flags", _i32)]
+
+
+class SpkStepInfo(ctypes.Structure):
+    _fields_ = [("iter", _i64), ("eta_fixed", _dbl), ("eta", _dbl), ("F", _dbl), ("Fa", _dbl),
+                ("Fr", _dbl), ("viol", _dbl * 4), ("bb_used", _i32), ("reserved", _i32)]
+
+
+class SparklingError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str):
+        super().__init__(f"{where}: status {status} ({detail})")
+        self.status = status
+
+
+_lib = None
+
+
+def load_library(path: Path | str | None = None):
+    """Load libsparkling.so (once).  Raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    p = Path(path) if path else LIB_PATH
+    if not p.exists():
+        raise RuntimeError(f"{p} is missing: build it with `python -m paper_2108_02991_amd.build`")
+    lib = ctypes.CDLL(str(p))
+    sig = {
+        "spk_status_string": ([ctypes.c_int], ctypes.c_char_p),
+        "spk_last_error": ([], ctypes.c_char_p),
+        "spk_alpha_beta": ([_dbl] * 8 + [_vp, _vp], ctypes.c_int),
+        "spk_workspace_size": ([_vp, _vp], ctypes.c_int),
+        "sparkling_energy": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp], ctypes.c_int),
+        "sparkling_grad": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _i64, _vp, _vp, _vp,
+                            _vp, _sz, _vp], ctypes.c_int),
+        "sparkling_project": ([_vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp], ctypes.c_int),
+        "sparkling_constraint_check": ([_vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp], ctypes.c_int),
+        "sparkling_step": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp], ctypes.c_int),
+        "spk_timing_enable": ([ctypes.c_int], ctypes.c_int),
+        "spk_timing_query": ([ctypes.c_int, _vp, _vp, _vp], ctypes.c_int),
+        "spk_timing_reset": ([], ctypes.c_int),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = lib
+    return lib
+
+
+def _check(rc: int, where: str):
+    if rc != 0:
+        lib = load_library()
+        raise SparklingError(rc, where, f"{lib.spk_status_string(rc).decode()}: "
+                                        f"{lib.spk_last_error().decode()}")
+
+
+@dataclass
+class Params:
+    """Problem description (mirrors spk_params of sparkling.h)."""
+    n_shots: int
+    n_samples: int
+    grid: int
+    precision: str = "fp32_comp"
+    half_width: float = 0.5
+    eps: float = 0.0
+    a_max: float = 1.0
+    b_max: float = 1.0
+    te_index: int = 0
+    n_pit: int = 200
+    discrepancy: bool = False
+    _c: SpkParams = field(default=None, repr=False, compare=False)
+
+    @property
+    def p(self) -> int:
+        return self.n_shots * self.n_samples
+
+    @property
+    def dtype(self) -> torch.dtype:
+        return torch.float64 if self.precision == "plain_fp64" else torch.float32
+
+    def c(self) -> SpkParams:
+        return SpkParams(self.n_shots, self.n_samples, self.grid, PRECISIONS[self.precision],
+                         self.te_index, self.half_width, self.eps, self.a_max, self.b_max,
+                         self.n_pit, FLAG_DISCREPANCY if self.discrepancy else 0)
+
+
+def alpha_beta(gmax, smax, raster_dt, dwell_dt, fov, kmax, gamma_bar, half_width):
+    a, b = _dbl(), _dbl()
+    _check(load_library().spk_alpha_beta(gmax, smax, raster_dt, dwell_dt, fov, kmax, gamma_bar,
+                                         half_width, ctypes.byref(a), ctypes.byref(b)),
+           "spk_alpha_beta")
+    return a.value, b.value
+
+
+def workspace_size(prm: Params) -> int:
+    n = _sz()
+    c = prm.c()
+    _check(load_library().spk_workspace_size(ctypes.byref(c), ctypes.byref(n)), "spk_workspace_size")
+    return n.value
+
+
+_ws_cache: dict = {}
+
+
+def workspace(prm: Params, device) -> torch.Tensor:
+    """A cached device workspace large enough for prm (one per device and stream)."""
+    n = workspace_size(prm)
+    stream = torch.cuda.current_stream(device).cuda_stream
+    key = (torch.device(device).index, stream)
+    ws = _ws_cache.get(key)
+    if ws is None or ws.numel() < n:
+        _ws_cache.pop(key, None)
+        ws = torch.empty(n, dtype=torch.uint8, device=device)
+        _ws_cache[key] = ws
+    return ws
+
+
+def _stream(t: torch.Tensor):
+    return _vp(torch.cuda.current_stream(t.device).cuda_stream)
+
+
+def _check_k(K: torch.Tensor, prm: Params, name="K"):
+    if not K.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if K.dtype != prm.dtype:
+        raise ValueError(f"{name} must be {prm.dtype} for precision {prm.precision}")
+    if K.dim() != 2 or K.shape[0] != 3 or K.shape[1] != prm.p or not K.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous (3, {prm.p}) tensor")
+
+
+def _check_rho(rho: torch.Tensor, prm: Params):
+    if not rho.is_cuda or rho.dtype != prm.dtype or rho.numel() != prm.grid ** 3 or not rho.is_contiguous():
+        raise ValueError(f"rho must be a contiguous {prm.dtype} device tensor of {prm.grid ** 3} weights")
+
+
+def _rows(K: torch.Tensor):
+    return [_vp(K[c].data_ptr()) for c in range(3)]
+
+
+def energy(K: torch.Tensor, rho: torch.Tensor, prm: Params):
+    """(F, Fa, Fr, D) as Python floats; D is NaN unless prm.discrepancy."""
+    _check_k(K, prm)
+    _check_rho(rho, prm)
+    ws = workspace(prm, K.device)
+    out = (_dbl * 4)()
+    c = prm.c()
+    _check(load_library().sparkling_energy(ctypes.byref(c), *_rows(K), _vp(rho.data_ptr()), out,
+                                           _vp(ws.data_ptr()), ws.numel(), _stream(K)),
+           "sparkling_energy")
+    return tuple(out)
+
+
+def grad(K: torch.Tensor, rho: torch.Tensor, prm: Params, tgt=None, out: torch.Tensor | None = None,
+         potentials: bool = False, with_energy: bool = False):
+    """Gradient rows [b, e) (default all) as a (3, e-b) tensor of K's dtype.
+
+    With potentials=True also returns (pot_a, pot_r) float64 tensors of the
+    unscaled per-target sums of H; with_energy=True also returns (F, Fa, Fr).
+    """
+    _check_k(K, prm)
+    _check_rho(rho, prm)
+    b, e = (0, prm.p) if tgt is None else (int(tgt[0]), int(tgt[1]))
+    nt = e - b
+    if out is None:
+        out = torch.empty((3, nt), dtype=K.dtype, device=K.device)
+    elif out.shape != (3, nt) or out.dtype != K.dtype or not out.is_contiguous():
+        raise ValueError("out must be a contiguous (3, e-b) tensor of K's dtype")
+    pa = pr = None
+    if potentials:
+        pa = torch.empty(nt, dtype=torch.float64, device=K.device)
+        pr = torch.empty(nt, dtype=torch.float64, device=K.device)
+    en = (_dbl * 3)() if with_energy else None
+    ws = workspace(prm, K.device)
+    c = prm.c()
+    _check(load_library().sparkling_grad(
+        ctypes.byref(c), *_rows(K), _vp(rho.data_ptr()), *_rows(out), b, e,
+        _vp(pa.data_ptr()) if pa is not None else None,
+        _vp(pr.data_ptr()) if pr is not None else None,
+        en, _vp(ws.data_ptr()), ws.numel(), _stream(K)), "sparkling_grad")
+    res = [out]
+    if potentials:
+        res.append((pa, pr))
+    if with_energy:
+        res.append(tuple(en))
+    return res[0] if len(res) == 1 else tuple(res)
+
+
+def project_(K: torch.Tensor, prm: Params, check: bool = True):
+    """Project every shot of K in place; returns the constraint check (numpy, 4)."""
+    _check_k(K, prm)
+    ws = workspace(prm, K.device)
+    viol = (_dbl * 4)() if check else None
+    c = prm.c()
+    _check(load_library().sparkling_project(ctypes.byref(c), *_rows(K), viol, _vp(ws.data_ptr()),
+                                            ws.numel(), _stream(K)), "sparkling_project")
+    return np.array(viol[:]) if check else None
+
+
+def constraint_check(K: torch.Tensor, prm: Params):
+    _check_k(K, prm)
+    ws = workspace(prm, K.device)
+    viol = (_dbl * 4)()
+    c = prm.c()
+    _check(load_library().sparkling_constraint_check(ctypes.byref(c), *_rows(K), viol,
+                                                     _vp(ws.data_ptr()), ws.numel(), _stream(K)),
+           "sparkling_constraint_check")
+    return np.array(viol[:])
+
+
+class StepState:
+    """Caller-owned state of the step-size policy: previous K and gradient, (3, p) each."""
+
+    def __init__(self, prm: Params, device):
+        self.k_prev = torch.zeros((3, prm.p), dtype=prm.dtype, device=device)
+        self.g_prev = torch.zeros((3, prm.p), dtype=prm.dtype, device=device)
+
+
+def step_(K: torch.Tensor, rho: torch.Tensor, prm: Params, state: StepState, it: int,
+          eta_fixed: float):
+    """One projected gradient step in place on K; returns the step info as a dict."""
+    _check_k(K, prm)
+    _check_rho(rho, prm)
+    _check_k(state.k_prev, prm, "k_prev")
+    _check_k(state.g_prev, prm, "g_prev")
+    ws = workspace(prm, K.device)
+    info = SpkStepInfo()
+    info.iter = it
+    info.eta_fixed = eta_fixed
+    c = prm.c()
+    rc = load_library().sparkling_step(ctypes.byref(c), *_rows(K), _vp(rho.data_ptr()),
+                                       _vp(state.k_prev.data_ptr()), _vp(state.g_prev.data_ptr()),
+                                       ctypes.byref(info), _vp(ws.data_ptr()), ws.numel(), _stream(K))
+    _check(rc, "sparkling_step")
+    return {"eta": info.eta, "F": info.F, "Fa": info.Fa, "Fr": info.Fr,
+            "viol": np.array(info.viol[:]), "bb_used": bool(info.bb_used)}
+
+
+def timing_enable(on: bool = True):
+    _check(load_library().spk_timing_enable(1 if on else 0), "spk_timing_enable")
+
+
+def timing_reset():
+    _check(load_library().spk_timing_reset(), "spk_timing_reset")
+
+
+def timing_query(kind: int):
+    """(total ms, launches, pair interactions) of one kernel kind since the last reset."""
+    ms, n, pairs = _dbl(), _i64(), _dbl()
+    _check(load_library().spk_timing_query(kind, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(pairs)),
+           "spk_timing_query")
+    return ms.value, n.value, pairs.value
+
+
+class SparklingEnergy(torch.autograd.Function):
+    """F(K) as a differentiable function of K.
+
+    forward runs the energy sweep; backward is the gradient kernel itself,
+    recomputed chunk by chunk over the targets (no pair terms are stored), then
+    scaled by the incoming gradient.  Differentiable in K only.
+    """
+
+    @staticmethod
+    def forward(ctx, K, rho, prm: Params, chunk: int = 8192):
+        F, _, _, _ = energy(K, rho, prm)
+        ctx.save_for_backward(K, rho)
+        ctx.prm = prm
+        ctx.chunk = chunk
+        return torch.tensor(F, dtype=torch.float64, device=K.device)
+
+    @staticmethod
+    def backward(ctx, g_out):
+        K, rho = ctx.saved_tensors
+        prm = ctx.prm
+        if torch.is_grad_enabled():
+            raise RuntimeError("SparklingEnergy does not support double backward")
+        g = torch.empty_like(K)
+        for b in range(0, prm.p, ctx.chunk):
+            e = min(b + ctx.chunk, prm.p)
+            part = grad(K, rho, prm, tgt=(b, e))
+            g[:, b:e].copy_(part)
+        return g * g_out.to(g.dtype), None, None, None
+
+
+def sparkling_energy(K, rho, prm: Params, chunk: int = 8192):
+    return SparklingEnergy.apply(K, rho, prm, chunk)

@@ -1,0 +1,694 @@
+// Host side of libsparkling.so: argument validation, sweep planning,
+// workspace layout, launch sequencing, kernel timing and the C entry points
+// declared in sparkling.h.
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "spk_internal.h"
+
+namespace {
+
+using namespace spk;
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int device_fail(hipError_t e, const char *where)
+{
+    return fail(SPK_EDEVICE, "%s: %s", where, hipGetErrorString(e));
+}
+
+#define SPK_HIP(expr, where)                     \
+    do {                                         \
+        hipError_t e_ = (expr);                  \
+        if (e_ != hipSuccess)                    \
+            return device_fail(e_, where);       \
+    } while (0)
+
+// ------------------------------------------------------------------------
+// Kernel timing (process-global, mutex-guarded).
+// ------------------------------------------------------------------------
+struct TimedLaunch {
+    hipEvent_t a, b;
+    int kind;
+    double pairs;
+};
+
+std::mutex g_tmu;
+bool g_timing = false;
+std::vector<TimedLaunch> g_pending;
+double g_ms[4] = {0, 0, 0, 0};
+int64_t g_launches[4] = {0, 0, 0, 0};
+double g_pairs[4] = {0, 0, 0, 0};
+
+// Brackets one launch with events when timing is on.
+class Timed {
+  public:
+    Timed(int kind, double pairs, hipStream_t s) : kind_(kind), pairs_(pairs), s_(s)
+    {
+        std::lock_guard<std::mutex> lk(g_tmu);
+        if (!g_timing)
+            return;
+        if (hipEventCreate(&a_) != hipSuccess || hipEventCreate(&b_) != hipSuccess)
+            return;
+        on_ = hipEventRecord(a_, s_) == hipSuccess;
+    }
+    ~Timed()
+    {
+        if (!on_)
+            return;
+        std::lock_guard<std::mutex> lk(g_tmu);
+        if (hipEventRecord(b_, s_) == hipSuccess)
+            g_pending.push_back({a_, b_, kind_, pairs_});
+    }
+
+  private:
+    int kind_;
+    double pairs_;
+    hipStream_t s_;
+    hipEvent_t a_{}, b_{};
+    bool on_ = false;
+};
+
+// ------------------------------------------------------------------------
+// Parameters and planning.
+// ------------------------------------------------------------------------
+size_t elt_size(int precision) { return precision == SPK_PLAIN_FP64 ? 8 : 4; }
+
+int check_params(const spk_params *prm, bool need_projection)
+{
+    if (!prm)
+        return fail(SPK_EINVAL, "params is NULL");
+    if (prm->n_shots < 1)
+        return fail(SPK_EINVAL, "n_shots must be >= 1 (got %lld)", (long long)prm->n_shots);
+    if (prm->n_samples < 1)
+        return fail(SPK_EINVAL, "n_samples must be >= 1 (got %lld)", (long long)prm->n_samples);
+    if (prm->n_shots > (int64_t(1) << 31) / prm->n_samples)
+        return fail(SPK_EINVAL, "p = n_shots * n_samples must stay below 2^31");
+    if (prm->grid < 1 || prm->grid > kMaxGrid)
+        return fail(SPK_EINVAL, "grid must be in [1, %lld] (got %lld)", (long long)kMaxGrid,
+                    (long long)prm->grid);
+    if (prm->precision < SPK_PLAIN_FP64 || prm->precision > SPK_FP32_ACC64)
+        return fail(SPK_EINVAL, "unknown precision %d", prm->precision);
+    if (!(prm->half_width > 0.0) || !std::isfinite(prm->half_width))
+        return fail(SPK_EINVAL, "half_width must be finite and > 0");
+    if (!(prm->eps >= 0.0) || !std::isfinite(prm->eps))
+        return fail(SPK_EINVAL, "eps must be finite and >= 0");
+    if (prm->te_index < -1 || prm->te_index >= prm->n_samples)
+        return fail(SPK_EINVAL, "te_index must be -1 or in [0, n_samples)");
+    if (prm->flags & ~SPK_FLAG_DISCREPANCY)
+        return fail(SPK_EINVAL, "unknown flags 0x%x", prm->flags);
+    if (need_projection) {
+        if (prm->n_samples < 2)
+            return fail(SPK_EINVAL, "projection needs n_samples >= 2");
+        if (prm->n_samples > kMaxProjectSamples)
+            return fail(SPK_EUNSUPPORTED, "projection supports n_samples <= %lld",
+                        (long long)kMaxProjectSamples);
+        if (!(prm->a_max > 0.0) || !(prm->b_max > 0.0) || !std::isfinite(prm->a_max) ||
+            !std::isfinite(prm->b_max))
+            return fail(SPK_EINVAL, "a_max and b_max must be finite and > 0");
+        if (prm->n_pit < 0)
+            return fail(SPK_EINVAL, "n_pit must be >= 0");
+    }
+    return SPK_OK;
+}
+
+int check_ptr(const void *ptr, const char *name, size_t align)
+{
+    if (!ptr)
+        return fail(SPK_EINVAL, "%s is NULL", name);
+    if (reinterpret_cast<uintptr_t>(ptr) % align)
+        return fail(SPK_EINVAL, "%s is not %zu-byte aligned", name, align);
+    return SPK_OK;
+}
+
+// Slab decomposition of one sweep.  Depends only on the total target count
+// p_total, the source count and the precision, never on the target range of a
+// call, which is what makes every chunking produce bit-identical rows.
+struct Plan {
+    int64_t slab = 1;        // sources (samples or cell rows) per slab
+    int64_t nslab = 1;
+    int64_t per_launch = 1;  // slabs per launch
+    int64_t unit = 1;        // pair interactions per source and target
+};
+
+// Pair interactions one launch may carry at most (~0.3-0.6 s at full rate).
+constexpr double kMaxPairsPerLaunch = 1099511627776.0;   // 2^40
+// Blocks a launch should have to fill 256 CUs several times over.
+constexpr int64_t kWantBlocks = 2048;
+
+Plan make_plan(int precision, bool cells, int64_t p_total, int64_t n_src, int64_t G)
+{
+    Plan pl;
+    pl.unit = cells ? G : 1;
+    const int64_t tpb = sweep_targets_per_block(precision);
+    const int64_t tb = (p_total + tpb - 1) / tpb;
+    const int64_t gran = cells ? std::max<int64_t>(1, (precision == SPK_PLAIN_FP64 ? kCellTileF64
+                                                                                  : kCellTileF32) / G)
+                               : kSampleTile;
+    const double max_pairs = precision == SPK_PLAIN_FP64 ? kMaxPairsPerLaunch / 2 : kMaxPairsPerLaunch;
+    const int64_t nslab_par = std::max<int64_t>(1, (kWantBlocks + tb - 1) / tb);
+    int64_t slab = (n_src + nslab_par - 1) / nslab_par;
+    const double per_src = (double)p_total * (double)pl.unit;
+    const int64_t slab_time = std::max<int64_t>(1, (int64_t)(max_pairs / per_src));
+    slab = std::min(slab, slab_time);
+    slab = (slab + gran - 1) / gran * gran;
+    slab = std::max<int64_t>(slab, gran);
+    pl.slab = slab;
+    pl.nslab = (n_src + slab - 1) / slab;
+    const int64_t fit = (int64_t)(max_pairs / (per_src * (double)slab));
+    pl.per_launch = std::max<int64_t>(1, std::min<int64_t>(pl.nslab, fit));
+    return pl;
+}
+
+// Workspace layout (offsets from a 256-byte aligned base).
+struct Layout {
+    size_t acc_a = 0, acc_r = 0, part = 0, red = 0, scal = 0, grad = 0, viol = 0, cells = 0;
+    size_t total = 0;
+    int64_t ld = 0;
+};
+
+size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+Layout make_layout(const spk_params *prm)
+{
+    Layout L;
+    const int64_t p = prm->n_shots * prm->n_samples;
+    const int64_t G = prm->grid, M = G * G * G;
+    const bool disc = prm->flags & SPK_FLAG_DISCREPANCY;
+    const int64_t nt = disc ? std::max(p, M) : p;
+    const Plan pr = make_plan(prm->precision, false, p, p, G);
+    const Plan pa = make_plan(prm->precision, true, p, G * G, G);
+    int64_t pl = std::max(pr.per_launch, pa.per_launch);
+    if (disc)
+        pl = std::max(pl, make_plan(prm->precision, true, M, G * G, G).per_launch);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = align256(off + bytes);
+        return o;
+    };
+    L.ld = nt;
+    L.acc_a = take(sizeof(double) * 4 * nt);
+    L.acc_r = take(sizeof(double) * 4 * nt);
+    L.part = take(sizeof(double) * 4 * nt * pl);
+    L.red = take(sizeof(double) * reduce_partials_size(std::max(nt, 3 * p)));
+    L.scal = take(sizeof(double) * 16);
+    L.grad = take(elt_size(prm->precision) * 3 * p);
+    L.viol = take(sizeof(double) * 4 * prm->n_shots);
+    L.cells = disc ? take(elt_size(prm->precision) * 3 * M) : off;
+    L.total = off + 256;   // slack for aligning the caller's base pointer
+    return L;
+}
+
+struct Ws {
+    char *base;
+    Layout L;
+    double *acc_a() const { return reinterpret_cast<double *>(base + L.acc_a); }
+    double *acc_r() const { return reinterpret_cast<double *>(base + L.acc_r); }
+    double *part() const { return reinterpret_cast<double *>(base + L.part); }
+    double *red() const { return reinterpret_cast<double *>(base + L.red); }
+    double *scal() const { return reinterpret_cast<double *>(base + L.scal); }
+    void *grad() const { return base + L.grad; }
+    double *viol() const { return reinterpret_cast<double *>(base + L.viol); }
+    void *cells() const { return base + L.cells; }
+};
+
+int bind_ws(const spk_params *prm, void *ws, size_t ws_bytes, Ws *out)
+{
+    out->L = make_layout(prm);
+    if (!ws || ws_bytes < out->L.total)
+        return fail(SPK_EWORKSPACE, "workspace needs %zu bytes (got %zu%s)", out->L.total,
+                    ws_bytes, ws ? "" : ", NULL");
+    uintptr_t b = reinterpret_cast<uintptr_t>(ws);
+    out->base = reinterpret_cast<char *>((b + 255) / 256 * 256);
+    return SPK_OK;
+}
+
+// Sweeps every target in [t0, t0 + nt) against one source set, accumulating
+// the four sums into acc (rows of length ld).  p_total fixes the plan.
+int run_sweep(const spk_params *prm, bool cells, const void *tx, const void *ty, const void *tz,
+              int64_t t0, int64_t nt, int64_t p_total, const void *sx, const void *sy,
+              const void *sz, const void *rho, bool energy, const Ws &w, double *acc,
+              hipStream_t s)
+{
+    const int64_t G = prm->grid;
+    const int64_t n_src = cells ? G * G : prm->n_shots * prm->n_samples;
+    const Plan pl = make_plan(prm->precision, cells, p_total, n_src, G);
+    SweepLaunch l;
+    l.precision = prm->precision;
+    l.energy = energy;
+    l.tx = tx;
+    l.ty = ty;
+    l.tz = tz;
+    l.t0 = t0;
+    l.nt = nt;
+    l.sx = sx;
+    l.sy = sy;
+    l.sz = sz;
+    l.rho = rho;
+    l.grid = G;
+    l.half_width = prm->half_width;
+    l.eps = prm->eps;
+    l.slab = pl.slab;
+    l.src_end = n_src;
+    l.part = w.part();
+    l.ld = w.L.ld;
+    const int kind = cells ? SPK_KIND_ATTRACTION : SPK_KIND_REPULSION;
+    bool first = true;
+    for (int64_t s0 = 0; s0 < pl.nslab; s0 += pl.per_launch) {
+        l.src_begin = s0 * pl.slab;
+        l.nslabs = (int)std::min<int64_t>(pl.per_launch, pl.nslab - s0);
+        const int64_t src_hi = std::min<int64_t>(n_src, (s0 + l.nslabs) * pl.slab);
+        const double pairs = (double)nt * (double)(src_hi - l.src_begin) * (double)pl.unit;
+        {
+            Timed tm(kind, pairs, s);
+            hipError_t e = cells ? launch_sweep_cells(l, s) : launch_sweep_samples(l, s);
+            if (e != hipSuccess)
+                return device_fail(e, cells ? "cell sweep launch" : "sample sweep launch");
+        }
+        {
+            Timed tm(SPK_KIND_OTHER, 0.0, s);
+            SPK_HIP(launch_combine(acc, w.part(), l.nslabs, w.L.ld, nt, first, s), "combine");
+        }
+        first = false;
+    }
+    return SPK_OK;
+}
+
+// Both sweeps for targets [t0, t0+nt) of K; results in w.acc_a() / w.acc_r().
+int run_gradient_sums(const spk_params *prm, const void *kx, const void *ky, const void *kz,
+                      const void *rho, int64_t t0, int64_t nt, bool energy, const Ws &w,
+                      hipStream_t s)
+{
+    const int64_t p = prm->n_shots * prm->n_samples;
+    int rc = run_sweep(prm, false, kx, ky, kz, t0, nt, p, kx, ky, kz, nullptr, energy, w,
+                       w.acc_r(), s);
+    if (rc)
+        return rc;
+    return run_sweep(prm, true, kx, ky, kz, t0, nt, p, nullptr, nullptr, nullptr, rho, energy, w,
+                     w.acc_a(), s);
+}
+
+// Energy sums of the potentials in acc rows 3 into scal[0] (attraction) and scal[1].
+int reduce_energy(const Ws &w, int64_t nt, hipStream_t s)
+{
+    Timed tm(SPK_KIND_OTHER, 0.0, s);
+    SPK_HIP(launch_sum2(w.acc_a() + 3 * w.L.ld, w.acc_r() + 3 * w.L.ld, nt, w.red(), w.scal(), s),
+            "energy reduction");
+    return SPK_OK;
+}
+
+void energies_from_sums(int64_t p, const double sums[2], double out[3])
+{
+    const double fa = sums[0] / (double)p;
+    const double fr = sums[1] / (2.0 * (double)p * (double)p);
+    out[0] = fa - fr;
+    out[1] = fa;
+    out[2] = fr;
+}
+
+int check_k(const spk_params *prm, const void *kx, const void *ky, const void *kz)
+{
+    const size_t al = elt_size(prm->precision);
+    int rc;
+    if ((rc = check_ptr(kx, "kx", al)) || (rc = check_ptr(ky, "ky", al)) ||
+        (rc = check_ptr(kz, "kz", al)))
+        return rc;
+    return SPK_OK;
+}
+
+int constraint_check_into(const spk_params *prm, const void *kx, const void *ky, const void *kz,
+                          const Ws &w, double *dev_out, hipStream_t s)
+{
+    Timed tm(SPK_KIND_OTHER, 0.0, s);
+    SPK_HIP(launch_constraint_check(prm->precision, kx, ky, kz, prm->n_shots, prm->n_samples,
+                                    prm->half_width, prm->a_max, prm->b_max, prm->te_index,
+                                    w.viol(), dev_out, s),
+            "constraint check");
+    return SPK_OK;
+}
+
+int project_in_place(const spk_params *prm, void *kx, void *ky, void *kz, hipStream_t s)
+{
+    Timed tm(SPK_KIND_PROJECTION, 0.0, s);
+    SPK_HIP(launch_project(prm->precision, kx, ky, kz, prm->n_shots, prm->n_samples,
+                           prm->half_width, prm->a_max, prm->b_max, prm->te_index, prm->n_pit, s),
+            "projection");
+    return SPK_OK;
+}
+
+int copy_to_host(double *dst, const double *src, size_t n, hipStream_t s)
+{
+    SPK_HIP(hipMemcpyAsync(dst, src, sizeof(double) * n, hipMemcpyDeviceToHost, s), "copy to host");
+    SPK_HIP(hipStreamSynchronize(s), "stream synchronize");
+    return SPK_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *spk_status_string(int status)
+{
+    switch (status) {
+    case SPK_OK: return "ok";
+    case SPK_EINVAL: return "invalid argument";
+    case SPK_EWORKSPACE: return "workspace too small";
+    case SPK_EDEVICE: return "HIP device error";
+    case SPK_EUNSUPPORTED: return "unsupported parameters";
+    case SPK_ENONFINITE: return "non-finite energy";
+    default: return "unknown status";
+    }
+}
+
+const char *spk_last_error(void) { return g_err.c_str(); }
+
+int spk_alpha_beta(double gmax, double smax, double raster_dt, double dwell_dt, double fov,
+                   double kmax, double gamma_bar, double half_width, double *a_max, double *b_max)
+{
+    g_err.clear();
+    const double in[] = {gmax, smax, raster_dt, dwell_dt, fov, kmax, gamma_bar, half_width};
+    for (double v : in)
+        if (!(v > 0.0) || !std::isfinite(v))
+            return fail(SPK_EINVAL, "spk_alpha_beta: every input must be finite and > 0");
+    if (!a_max || !b_max)
+        return fail(SPK_EINVAL, "spk_alpha_beta: NULL output");
+    const double amplitude_rate = gamma_bar * gmax;       // 1/(m s) reachable by the gradient
+    const double nyquist_rate = 1.0 / (fov * dwell_dt);   // 1/(m s) allowed by the ADC
+    const double speed = std::min(amplitude_rate, nyquist_rate) / kmax;
+    const double slew = gamma_bar * smax / kmax;
+    *a_max = speed * raster_dt * half_width;
+    *b_max = slew * raster_dt * raster_dt * half_width;
+    return SPK_OK;
+}
+
+int spk_workspace_size(const spk_params *prm, size_t *bytes)
+{
+    g_err.clear();
+    int rc = check_params(prm, false);
+    if (rc)
+        return rc;
+    if (!bytes)
+        return fail(SPK_EINVAL, "bytes is NULL");
+    *bytes = make_layout(prm).total;
+    return SPK_OK;
+}
+
+int sparkling_grad(const spk_params *prm, const void *kx, const void *ky, const void *kz,
+                   const void *rho, void *gx, void *gy, void *gz, int64_t tgt_begin,
+                   int64_t tgt_end, double *pot_a, double *pot_r, double *energy, void *ws,
+                   size_t ws_bytes, void *stream)
+{
+    g_err.clear();
+    int rc = check_params(prm, false);
+    if (rc)
+        return rc;
+    const int64_t p = prm->n_shots * prm->n_samples;
+    const size_t al = elt_size(prm->precision);
+    if (tgt_begin < 0 || tgt_end < tgt_begin || tgt_end > p)
+        return fail(SPK_EINVAL, "target range [%lld, %lld) outside [0, %lld)",
+                    (long long)tgt_begin, (long long)tgt_end, (long long)p);
+    if ((rc = check_k(prm, kx, ky, kz)) || (rc = check_ptr(rho, "rho", al)))
+        return rc;
+    // outputs of an empty range are never touched and may be NULL
+    if (tgt_end > tgt_begin &&
+        ((rc = check_ptr(gx, "gx", al)) || (rc = check_ptr(gy, "gy", al)) ||
+         (rc = check_ptr(gz, "gz", al))))
+        return rc;
+    if ((pot_a && (rc = check_ptr(pot_a, "pot_a", 8))) || (pot_r && (rc = check_ptr(pot_r, "pot_r", 8))))
+        return rc;
+    if (energy && (tgt_begin != 0 || tgt_end != p))
+        return fail(SPK_EINVAL, "energy needs the full target range [0, p)");
+    Ws w;
+    if ((rc = bind_ws(prm, ws, ws_bytes, &w)))
+        return rc;
+    const int64_t nt = tgt_end - tgt_begin;
+    if (nt == 0)
+        return SPK_OK;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const bool want_pot = energy || pot_a || pot_r;
+    if ((rc = run_gradient_sums(prm, kx, ky, kz, rho, tgt_begin, nt, want_pot, w, s)))
+        return rc;
+    {
+        Timed tm(SPK_KIND_OTHER, 0.0, s);
+        const double inv_p = 1.0 / (double)p, inv_p2 = 1.0 / ((double)p * (double)p);
+        SPK_HIP(launch_finalize_grad(prm->precision, w.acc_a(), w.acc_r(), w.L.ld, nt, inv_p,
+                                     inv_p2, gx, gy, gz, pot_a, pot_r, s),
+                "finalize gradient");
+    }
+    if (energy) {
+        if ((rc = reduce_energy(w, nt, s)))
+            return rc;
+        double sums[2];
+        if ((rc = copy_to_host(sums, w.scal(), 2, s)))
+            return rc;
+        energies_from_sums(p, sums, energy);
+    }
+    return SPK_OK;
+}
+
+int sparkling_energy(const spk_params *prm, const void *kx, const void *ky, const void *kz,
+                     const void *rho, double out[4], void *ws, size_t ws_bytes, void *stream)
+{
+    g_err.clear();
+    int rc = check_params(prm, false);
+    if (rc)
+        return rc;
+    const size_t al = elt_size(prm->precision);
+    if ((rc = check_k(prm, kx, ky, kz)) || (rc = check_ptr(rho, "rho", al)))
+        return rc;
+    if (!out)
+        return fail(SPK_EINVAL, "out is NULL");
+    Ws w;
+    if ((rc = bind_ws(prm, ws, ws_bytes, &w)))
+        return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int64_t p = prm->n_shots * prm->n_samples;
+    if ((rc = run_gradient_sums(prm, kx, ky, kz, rho, 0, p, true, w, s)))
+        return rc;
+    if ((rc = reduce_energy(w, p, s)))
+        return rc;
+    const bool disc = prm->flags & SPK_FLAG_DISCREPANCY;
+    if (disc) {
+        // E_rho = 1/2 sum_v rho_v sum_u rho_u H(x_v - x_u): a cell sweep whose
+        // targets are the cell centres themselves.
+        const int64_t G = prm->grid, M = G * G * G;
+        char *cells = static_cast<char *>(w.cells());
+        void *cx = cells, *cy = cells + al * M, *cz = cells + 2 * al * M;
+        {
+            Timed tm(SPK_KIND_OTHER, 0.0, s);
+            SPK_HIP(launch_cell_centres(prm->precision, G, prm->half_width, cx, cy, cz, s),
+                    "cell centres");
+        }
+        if ((rc = run_sweep(prm, true, cx, cy, cz, 0, M, M, nullptr, nullptr, nullptr, rho, true,
+                            w, w.acc_a(), s)))
+            return rc;
+        Timed tm(SPK_KIND_OTHER, 0.0, s);
+        SPK_HIP(launch_wsum(rho, prm->precision, w.acc_a() + 3 * w.L.ld, M, w.red(),
+                            w.scal() + 2, s),
+                "self-energy reduction");
+    }
+    double sums[4];
+    if ((rc = copy_to_host(sums, w.scal(), disc ? 3 : 2, s)))
+        return rc;
+    double e3[3];
+    energies_from_sums(p, sums, e3);
+    out[0] = e3[0];
+    out[1] = e3[1];
+    out[2] = e3[2];
+    out[3] = disc ? e3[0] - 0.5 * sums[2] : NAN;
+    return SPK_OK;
+}
+
+int sparkling_constraint_check(const spk_params *prm, const void *kx, const void *ky,
+                               const void *kz, double viol[4], void *ws, size_t ws_bytes,
+                               void *stream)
+{
+    g_err.clear();
+    int rc = check_params(prm, true);
+    if (rc)
+        return rc;
+    if ((rc = check_k(prm, kx, ky, kz)))
+        return rc;
+    if (!viol)
+        return fail(SPK_EINVAL, "viol is NULL");
+    Ws w;
+    if ((rc = bind_ws(prm, ws, ws_bytes, &w)))
+        return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if ((rc = constraint_check_into(prm, kx, ky, kz, w, w.scal() + 8, s)))
+        return rc;
+    return copy_to_host(viol, w.scal() + 8, 4, s);
+}
+
+int sparkling_project(const spk_params *prm, void *kx, void *ky, void *kz, double *viol, void *ws,
+                      size_t ws_bytes, void *stream)
+{
+    g_err.clear();
+    int rc = check_params(prm, true);
+    if (rc)
+        return rc;
+    if ((rc = check_k(prm, kx, ky, kz)))
+        return rc;
+    Ws w;
+    if ((rc = bind_ws(prm, ws, ws_bytes, &w)))
+        return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if ((rc = project_in_place(prm, kx, ky, kz, s)))
+        return rc;
+    if (!viol)
+        return SPK_OK;
+    if ((rc = constraint_check_into(prm, kx, ky, kz, w, w.scal() + 8, s)))
+        return rc;
+    return copy_to_host(viol, w.scal() + 8, 4, s);
+}
+
+int sparkling_step(const spk_params *prm, void *kx, void *ky, void *kz, const void *rho,
+                   void *k_prev, void *g_prev, spk_step_info *info, void *ws, size_t ws_bytes,
+                   void *stream)
+{
+    g_err.clear();
+    int rc = check_params(prm, true);
+    if (rc)
+        return rc;
+    const size_t al = elt_size(prm->precision);
+    if ((rc = check_k(prm, kx, ky, kz)) || (rc = check_ptr(rho, "rho", al)) ||
+        (rc = check_ptr(k_prev, "k_prev", al)) || (rc = check_ptr(g_prev, "g_prev", al)))
+        return rc;
+    if (!info)
+        return fail(SPK_EINVAL, "info is NULL");
+    if (info->iter < 0 || !(info->eta_fixed > 0.0) || !std::isfinite(info->eta_fixed))
+        return fail(SPK_EINVAL, "info: iter must be >= 0 and eta_fixed finite and > 0");
+    Ws w;
+    if ((rc = bind_ws(prm, ws, ws_bytes, &w)))
+        return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int64_t p = prm->n_shots * prm->n_samples;
+    char *g = static_cast<char *>(w.grad());
+
+    if ((rc = run_gradient_sums(prm, kx, ky, kz, rho, 0, p, true, w, s)))
+        return rc;
+    {
+        Timed tm(SPK_KIND_OTHER, 0.0, s);
+        const double inv_p = 1.0 / (double)p, inv_p2 = 1.0 / ((double)p * (double)p);
+        SPK_HIP(launch_finalize_grad(prm->precision, w.acc_a(), w.acc_r(), w.L.ld, p, inv_p,
+                                     inv_p2, g, g + al * p, g + 2 * al * p, nullptr, nullptr, s),
+                "finalize gradient");
+    }
+    if ((rc = reduce_energy(w, p, s)))
+        return rc;
+    const bool bb = info->iter >= 20;
+    if (bb) {
+        Timed tm(SPK_KIND_OTHER, 0.0, s);
+        SPK_HIP(launch_bb_dots(prm->precision, kx, ky, kz, k_prev, g, g_prev, p, w.red(),
+                               w.scal() + 2, s),
+                "step dots");
+    }
+    double sc[4];
+    if ((rc = copy_to_host(sc, w.scal(), bb ? 4 : 2, s)))
+        return rc;
+    double e3[3];
+    energies_from_sums(p, sc, e3);
+    double eta = info->eta_fixed;
+    int used = 0;
+    if (bb) {
+        const double ss = sc[2], sy = sc[3];
+        if (sy > 0.0 && std::isfinite(ss / sy)) {
+            eta = ss / sy;
+            eta = std::min(std::max(eta, 0.1 * info->eta_fixed), 10.0 * info->eta_fixed);
+            used = 1;
+        }
+    }
+    {
+        Timed tm(SPK_KIND_OTHER, 0.0, s);
+        SPK_HIP(launch_axpy_save(prm->precision, kx, ky, kz, k_prev, g, g_prev, p, eta, s),
+                "step update");
+    }
+    if ((rc = project_in_place(prm, kx, ky, kz, s)))
+        return rc;
+    if ((rc = constraint_check_into(prm, kx, ky, kz, w, w.scal() + 8, s)))
+        return rc;
+    double v[4];
+    if ((rc = copy_to_host(v, w.scal() + 8, 4, s)))
+        return rc;
+    info->eta = eta;
+    info->F = e3[0];
+    info->Fa = e3[1];
+    info->Fr = e3[2];
+    for (int c = 0; c < 4; ++c)
+        info->viol[c] = v[c];
+    info->bb_used = used;
+    if (!std::isfinite(e3[0]))
+        return fail(SPK_ENONFINITE, "energy is not finite (F = %g)", e3[0]);
+    return SPK_OK;
+}
+
+int spk_timing_enable(int on)
+{
+    std::lock_guard<std::mutex> lk(g_tmu);
+    g_timing = on != 0;
+    return SPK_OK;
+}
+
+int spk_timing_query(int kind, double *total_ms, int64_t *launches, double *pairs)
+{
+    if (kind < 0 || kind > 3)
+        return fail(SPK_EINVAL, "unknown timing kind %d", kind);
+    std::lock_guard<std::mutex> lk(g_tmu);
+    for (const TimedLaunch &t : g_pending) {
+        float ms = 0.f;
+        if (hipEventSynchronize(t.b) != hipSuccess || hipEventElapsedTime(&ms, t.a, t.b) != hipSuccess)
+            return fail(SPK_EDEVICE, "timing event query failed");
+        g_ms[t.kind] += ms;
+        g_launches[t.kind] += 1;
+        g_pairs[t.kind] += t.pairs;
+        hipEventDestroy(t.a);
+        hipEventDestroy(t.b);
+    }
+    g_pending.clear();
+    if (total_ms)
+        *total_ms = g_ms[kind];
+    if (launches)
+        *launches = g_launches[kind];
+    if (pairs)
+        *pairs = g_pairs[kind];
+    return SPK_OK;
+}
+
+int spk_timing_reset(void)
+{
+    std::lock_guard<std::mutex> lk(g_tmu);
+    for (const TimedLaunch &t : g_pending) {
+        hipEventSynchronize(t.b);
+        hipEventDestroy(t.a);
+        hipEventDestroy(t.b);
+    }
+    g_pending.clear();
+    for (int k = 0; k < 4; ++k) {
+        g_ms[k] = 0;
+        g_launches[k] = 0;
+        g_pairs[k] = 0;
+    }
+    return SPK_OK;
+}
+
+}  // extern "C"

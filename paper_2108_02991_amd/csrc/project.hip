@@ -1,0 +1,307 @@
+// Per-shot projection onto the hardware constraint set and the constraint
+// check (Sec. "3D K-space sampling"; supplement, "Multi-shot projection step").
+//
+// One workgroup per shot; shots are independent, as the paper notes.  Thread j
+// owns NPT consecutive samples m = j*NPT .. j*NPT+NPT-1 and keeps the dual
+// variables q (speed, one per forward difference) and r (slew, one per second
+// difference) and their extrapolations in registers, all in double; its input
+// samples k are re-read from memory when needed.
+// Stencils reach at most two samples across a thread boundary, so each
+// iteration exchanges two values per thread through LDS: the last two dual
+// entries to the right neighbour before the primal update, the first two
+// primal entries to the left neighbour before the dual update.
+//
+// The iteration (accelerated proximal gradient on the dual of
+// min_{s in Q} |s - k|^2 / 2, step tau = 1/20 since |D1|^2 + |D2|^2 <= 20):
+//   s  = P0(k - D1^T qh - D2^T rh)       P0: clamp to [-L, L], then s[te] = 0
+//   q+ = shrink(qh + tau D1 s, tau a),  r+ = shrink(rh + tau D2 s, tau b)
+//   t+ = (1 + sqrt(1 + 4 t^2)) / 2,     qh = q+ + ((t - 1)/t+)(q+ - q), same for r
+// and the output is P0(k - D1^T q - D2^T r) of the last dual iterate.  With
+// (D1 s)[n] = s[n+1] - s[n], (D2 s)[n] = s[n+2] - 2 s[n+1] + s[n] and
+// shrink(z, th) = z * max(0, 1 - th/|z|) per sample.  Floating-point
+// contraction is off and every expression keeps one fixed evaluation order.
+
+#include "spk_internal.h"
+
+namespace spk {
+namespace {
+
+__device__ inline double clamp_box(double z, double L)
+{
+    return z < -L ? -L : (z > L ? L : z);   // NaN stays NaN
+}
+
+__device__ inline double shrink_factor(double z0, double z1, double z2, double thr)
+{
+#pragma clang fp contract(off)
+    const double nrm = sqrt((z0 * z0 + z1 * z1) + z2 * z2);
+    return (nrm > thr) ? (1.0 - thr / nrm) : 0.0;
+}
+
+template <typename T, int NPT>
+__global__ __launch_bounds__(512) void project_kernel(T *kx, T *ky, T *kz, int64_t Ns, double L,
+                                                     double a, double b, int64_t te, int n_pit)
+{
+#pragma clang fp contract(off)
+    static_assert(NPT >= 2, "two-sample halo needs NPT >= 2");
+    extern __shared__ double xch[];
+    const int nth = blockDim.x;
+    const int j = threadIdx.x;
+    double *q_tail = xch;                 // [3][nth]  q[last]
+    double *r_tail0 = q_tail + 3 * nth;   // [3][nth]  r[last-1]
+    double *r_tail1 = r_tail0 + 3 * nth;  // [3][nth]  r[last]
+    double *s_head0 = r_tail1 + 3 * nth;  // [3][nth]  s[first]
+    double *s_head1 = s_head0 + 3 * nth;  // [3][nth]  s[first+1]
+
+    const int64_t m0 = (int64_t)j * NPT;
+    T *K[3] = {kx + (int64_t)blockIdx.x * Ns, ky + (int64_t)blockIdx.x * Ns,
+               kz + (int64_t)blockIdx.x * Ns};
+
+    // k is re-read from memory when needed (exact widening, same value every
+    // time); only the dual state lives in registers.
+    double q[3][NPT], qh[3][NPT], r[3][NPT], rh[3][NPT];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int i = 0; i < NPT; ++i)
+            q[c][i] = qh[c][i] = r[c][i] = rh[c][i] = 0.0;
+    auto kval = [&](int c, int i) -> double {
+        const int64_t m = m0 + i;
+        return m < Ns ? (double)K[c][m] : 0.0;
+    };
+
+    // s[m] for the thread's samples from duals (dq, dr), halo values from the left.
+    auto primal = [&](double (&s)[3][NPT + 2], const double (&dq)[3][NPT],
+                      const double (&dr)[3][NPT]) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const double q_left = j > 0 ? q_tail[c * nth + j - 1] : 0.0;    // q[m0-1]
+            const double r_left0 = j > 0 ? r_tail0[c * nth + j - 1] : 0.0;  // r[m0-2]
+            const double r_left1 = j > 0 ? r_tail1[c * nth + j - 1] : 0.0;  // r[m0-1]
+#pragma unroll
+            for (int i = 0; i < NPT; ++i) {
+                const int64_t m = m0 + i;
+                const double qm1 = i >= 1 ? dq[c][i - 1] : q_left;
+                const double rm1 = i >= 1 ? dr[c][i - 1] : r_left1;
+                const double rm2 = i >= 2 ? dr[c][i - 2] : (i == 1 ? r_left1 : r_left0);
+                const double qa = (m >= 1) ? qm1 : 0.0;
+                const double qb = (m <= Ns - 2) ? dq[c][i] : 0.0;
+                const double ra = (m >= 2) ? rm2 : 0.0;
+                const double rb = (m >= 1 && m - 1 <= Ns - 3) ? rm1 : 0.0;
+                const double rc = (m <= Ns - 3) ? dr[c][i] : 0.0;
+                const double d1t = qa - qb;
+                const double d2t = (ra - 2.0 * rb) + rc;
+                double v = clamp_box((kval(c, i) - d1t) - d2t, L);
+                if (m == te)
+                    v = 0.0;
+                s[c][i] = v;
+            }
+        }
+    };
+    auto publish_tails = [&](const double (&dq)[3][NPT], const double (&dr)[3][NPT]) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            q_tail[c * nth + j] = dq[c][NPT - 1];
+            r_tail0[c * nth + j] = dr[c][NPT - 2];
+            r_tail1[c * nth + j] = dr[c][NPT - 1];
+        }
+    };
+
+    publish_tails(qh, rh);
+    __syncthreads();
+
+    const double tau = 1.0 / 20.0;
+    const double thr_a = tau * a, thr_b = tau * b;
+    double t = 1.0;
+    for (int it = 0; it < n_pit; ++it) {
+        double s[3][NPT + 2];
+        primal(s, qh, rh);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            s_head0[c * nth + j] = s[c][0];
+            s_head1[c * nth + j] = s[c][1];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            s[c][NPT] = j + 1 < nth ? s_head0[c * nth + j + 1] : 0.0;
+            s[c][NPT + 1] = j + 1 < nth ? s_head1[c * nth + j + 1] : 0.0;
+        }
+        const double tn = (1.0 + sqrt(1.0 + 4.0 * t * t)) / 2.0;
+        const double mom = (t - 1.0) / tn;
+#pragma unroll
+        for (int i = 0; i < NPT; ++i) {
+            const int64_t n = m0 + i;
+            double zq[3], zr[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                zq[c] = qh[c][i] + tau * (s[c][i + 1] - s[c][i]);
+                zr[c] = rh[c][i] + tau * ((s[c][i + 2] - 2.0 * s[c][i + 1]) + s[c][i]);
+            }
+            const double fq = shrink_factor(zq[0], zq[1], zq[2], thr_a);
+            const double fr = shrink_factor(zr[0], zr[1], zr[2], thr_b);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const double qn = (n <= Ns - 2) ? zq[c] * fq : 0.0;
+                const double rn = (n <= Ns - 3) ? zr[c] * fr : 0.0;
+                qh[c][i] = qn + mom * (qn - q[c][i]);
+                q[c][i] = qn;
+                rh[c][i] = rn + mom * (rn - r[c][i]);
+                r[c][i] = rn;
+            }
+        }
+        t = tn;
+        publish_tails(qh, rh);
+        __syncthreads();
+    }
+
+    publish_tails(q, r);
+    __syncthreads();
+    double s[3][NPT + 2];
+    primal(s, q, r);
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int i = 0; i < NPT; ++i) {
+            const int64_t m = m0 + i;
+            if (m < Ns)
+                K[c][m] = (T)s[c][i];
+        }
+}
+
+// NaN-propagating maximum (order-independent: NaN is sticky, otherwise exact max).
+__device__ inline double vmax(double m, double x)
+{
+    if (m != m)
+        return m;
+    return (x != x || x > m) ? x : m;
+}
+
+constexpr int CB = 256;
+
+template <typename T>
+__global__ __launch_bounds__(CB) void check_kernel(const T *kx, const T *ky, const T *kz,
+                                                   int64_t Ns, double L, double a, double b,
+                                                   int64_t te, double *per_shot)
+{
+#pragma clang fp contract(off)
+    __shared__ double red[4][CB];
+    const int64_t off = (int64_t)blockIdx.x * Ns;
+    const T *x = kx + off, *y = ky + off, *z = kz + off;
+    double m[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t n = threadIdx.x; n < Ns; n += CB) {
+        const double x0 = x[n], y0 = y[n], z0 = z[n];
+        if (n + 1 < Ns) {
+            const double dx = (double)x[n + 1] - x0, dy = (double)y[n + 1] - y0,
+                         dz = (double)z[n + 1] - z0;
+            m[0] = vmax(m[0], sqrt((dx * dx + dy * dy) + dz * dz) / a);
+        }
+        if (n + 2 < Ns) {
+            const double dx = ((double)x[n + 2] - 2.0 * (double)x[n + 1]) + x0;
+            const double dy = ((double)y[n + 2] - 2.0 * (double)y[n + 1]) + y0;
+            const double dz = ((double)z[n + 2] - 2.0 * (double)z[n + 1]) + z0;
+            m[1] = vmax(m[1], sqrt((dx * dx + dy * dy) + dz * dz) / b);
+        }
+        m[2] = vmax(m[2], fabs(x0) / L);
+        m[2] = vmax(m[2], fabs(y0) / L);
+        m[2] = vmax(m[2], fabs(z0) / L);
+        if (n == te)
+            m[3] = vmax(m[3], sqrt((x0 * x0 + y0 * y0) + z0 * z0));
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+        red[c][threadIdx.x] = m[c];
+    __syncthreads();
+    for (int w = CB / 2; w >= 1; w >>= 1) {
+        if ((int)threadIdx.x < w)
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+                red[c][threadIdx.x] = vmax(red[c][threadIdx.x], red[c][threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x < 4)
+        per_shot[(int64_t)blockIdx.x * 4 + threadIdx.x] = red[threadIdx.x][0];
+}
+
+__global__ __launch_bounds__(CB) void check_final_kernel(const double *per_shot, int64_t n_shots,
+                                                         double *out)
+{
+    __shared__ double red[4][CB];
+    double m[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t s = threadIdx.x; s < n_shots; s += CB)
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+            m[c] = vmax(m[c], per_shot[s * 4 + c]);
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+        red[c][threadIdx.x] = m[c];
+    __syncthreads();
+    for (int w = CB / 2; w >= 1; w >>= 1) {
+        if ((int)threadIdx.x < w)
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+                red[c][threadIdx.x] = vmax(red[c][threadIdx.x], red[c][threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x < 4)
+        out[threadIdx.x] = red[threadIdx.x][0];
+}
+
+template <typename T, int NPT>
+hipError_t launch_project_npt(T *kx, T *ky, T *kz, int64_t n_shots, int64_t Ns, double L,
+                              double a, double b, int64_t te, int n_pit, hipStream_t s)
+{
+    int64_t nth = (Ns + NPT - 1) / NPT;
+    nth = (nth + 63) / 64 * 64;
+    const size_t lds = sizeof(double) * 15 * (size_t)nth;
+    hipLaunchKernelGGL((project_kernel<T, NPT>), dim3((unsigned)n_shots), dim3((unsigned)nth), lds,
+                       s, kx, ky, kz, Ns, L, a, b, te, n_pit);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_project_t(T *kx, T *ky, T *kz, int64_t n_shots, int64_t Ns, double L, double a,
+                            double b, int64_t te, int n_pit, hipStream_t s)
+{
+    // at most 512 threads per shot: the halo buffers (15 doubles per thread)
+    // stay under 64 KB of LDS
+    if (Ns <= 2 * 512)
+        return launch_project_npt<T, 2>(kx, ky, kz, n_shots, Ns, L, a, b, te, n_pit, s);
+    if (Ns <= 4 * 512)
+        return launch_project_npt<T, 4>(kx, ky, kz, n_shots, Ns, L, a, b, te, n_pit, s);
+    return launch_project_npt<T, 8>(kx, ky, kz, n_shots, Ns, L, a, b, te, n_pit, s);
+}
+
+}  // namespace
+
+hipError_t launch_project(int precision, void *kx, void *ky, void *kz, int64_t n_shots,
+                          int64_t n_samples, double L, double a, double b, int64_t te, int n_pit,
+                          hipStream_t s)
+{
+    if (n_samples > kMaxProjectSamples)
+        return hipErrorInvalidValue;
+    if (precision == SPK_PLAIN_FP64)
+        return launch_project_t((double *)kx, (double *)ky, (double *)kz, n_shots, n_samples, L,
+                                a, b, te, n_pit, s);
+    return launch_project_t((float *)kx, (float *)ky, (float *)kz, n_shots, n_samples, L, a, b,
+                            te, n_pit, s);
+}
+
+hipError_t launch_constraint_check(int precision, const void *kx, const void *ky, const void *kz,
+                                   int64_t n_shots, int64_t n_samples, double L, double a,
+                                   double b, int64_t te, double *per_shot, double *out,
+                                   hipStream_t s)
+{
+    if (precision == SPK_PLAIN_FP64)
+        hipLaunchKernelGGL(check_kernel<double>, dim3((unsigned)n_shots), dim3(CB), 0, s,
+                           (const double *)kx, (const double *)ky, (const double *)kz, n_samples,
+                           L, a, b, te, per_shot);
+    else
+        hipLaunchKernelGGL(check_kernel<float>, dim3((unsigned)n_shots), dim3(CB), 0, s,
+                           (const float *)kx, (const float *)ky, (const float *)kz, n_samples, L,
+                           a, b, te, per_shot);
+    hipLaunchKernelGGL(check_final_kernel, dim3(1), dim3(CB), 0, s, per_shot, n_shots, out);
+    return hipGetLastError();
+}
+
+}  // namespace spk

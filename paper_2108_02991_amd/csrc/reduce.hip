@@ -1,0 +1,289 @@
+// Combines, finalisation, deterministic reductions and the step's vector
+// updates.  All HBM-bound; every sum runs in a fixed order that depends only
+// on the element count, so results are bit-reproducible.
+
+#include "spk_internal.h"
+
+namespace spk {
+namespace {
+
+constexpr int RB = 256;        // threads per reduction block
+constexpr int PER = 16;        // elements per thread per reduction block
+constexpr int EW = 256;        // threads per elementwise block
+
+inline unsigned ew_blocks(int64_t n) { return (unsigned)((n + EW - 1) / EW); }
+
+__global__ __launch_bounds__(EW) void combine_kernel(double *acc, const double *part, int nslabs,
+                                                     int64_t ld, int64_t nt, int init)
+{
+    const int64_t e = (int64_t)blockIdx.x * EW + threadIdx.x;
+    if (e >= 4 * nt)
+        return;
+    const int64_t c = e / nt, t = e - c * nt;
+    const int64_t o = c * ld + t;
+    double v = init ? 0.0 : acc[o];
+    for (int y = 0; y < nslabs; ++y)
+        v += part[((int64_t)y * 4 + c) * ld + t];
+    acc[o] = v;
+}
+
+template <typename T>
+__global__ __launch_bounds__(EW) void finalize_kernel(const double *acc_a, const double *acc_r,
+                                                      int64_t ld, int64_t nt, double inv_p,
+                                                      double inv_p2, T *gx, T *gy, T *gz,
+                                                      double *pot_a, double *pot_r)
+{
+    const int64_t t = (int64_t)blockIdx.x * EW + threadIdx.x;
+    if (t >= nt)
+        return;
+    T *g[3] = {gx, gy, gz};
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const double fa = acc_a[c * ld + t] * inv_p;
+        const double fr = acc_r[c * ld + t] * inv_p2;
+        g[c][t] = (T)(fa - fr);
+    }
+    if (pot_a)
+        pot_a[t] = acc_a[3 * ld + t];
+    if (pot_r)
+        pot_r[t] = acc_r[3 * ld + t];
+}
+
+// Sum over the 64 lanes of a wave; every lane ends with the same value.
+__device__ inline double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1)
+        v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Block sum in a fixed tree; the result is valid in thread 0.
+__device__ inline double block_sum(double v, double *lds)
+{
+    v = wave_sum(v);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0)
+        lds[w] = v;
+    __syncthreads();
+    double tot = 0.0;
+    if (threadIdx.x == 0)
+        for (int k = 0; k < RB / 64; ++k)
+            tot += lds[k];
+    __syncthreads();
+    return tot;
+}
+
+// Stage 1 of a two-series sum: partial b covers elements [b*RB*PER, (b+1)*RB*PER).
+// Series values come from a functor f(e, &v0, &v1).
+template <class F>
+__global__ __launch_bounds__(RB) void sum_stage1(F f, int64_t n, double *partials)
+{
+    __shared__ double lds[RB / 64];
+    const int64_t base = (int64_t)blockIdx.x * RB * PER + threadIdx.x;
+    double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int64_t e = base + (int64_t)k * RB;
+        if (e < n) {
+            double v0, v1;
+            f(e, v0, v1);
+            a0 += v0;
+            a1 += v1;
+        }
+    }
+    a0 = block_sum(a0, lds);
+    a1 = block_sum(a1, lds);
+    if (threadIdx.x == 0) {
+        partials[2 * blockIdx.x] = a0;
+        partials[2 * blockIdx.x + 1] = a1;
+    }
+}
+
+__global__ __launch_bounds__(RB) void sum_stage2(const double *partials, int64_t nb, double *out)
+{
+    __shared__ double lds[RB / 64];
+    double a0 = 0.0, a1 = 0.0;
+    for (int64_t b = threadIdx.x; b < nb; b += RB) {
+        a0 += partials[2 * b];
+        a1 += partials[2 * b + 1];
+    }
+    a0 = block_sum(a0, lds);
+    a1 = block_sum(a1, lds);
+    if (threadIdx.x == 0) {
+        out[0] = a0;
+        out[1] = a1;
+    }
+}
+
+struct Pair2 {
+    const double *x0, *x1;
+    __device__ void operator()(int64_t e, double &v0, double &v1) const
+    {
+        v0 = x0[e];
+        v1 = x1 ? x1[e] : 0.0;
+    }
+};
+
+template <typename T> struct WeightedF {
+    const T *w;
+    const double *x;
+    __device__ void operator()(int64_t e, double &v0, double &v1) const
+    {
+        v0 = (double)w[e] * x[e];
+        v1 = 0.0;
+    }
+};
+
+template <typename T> struct DotsF {
+    const T *kx, *ky, *kz, *kp, *g, *gp;
+    int64_t p;
+    __device__ void operator()(int64_t e, double &ss, double &sy) const
+    {
+        const int64_t c = e / p, i = e - c * p;
+        const T *k = c == 0 ? kx : (c == 1 ? ky : kz);
+        const double s = (double)k[i] - (double)kp[e];
+        const double y = (double)g[e] - (double)gp[e];
+        ss = s * s;
+        sy = s * y;
+    }
+};
+
+template <class F>
+hipError_t run_sum(F f, int64_t n, double *partials, double *out, hipStream_t s)
+{
+    const int64_t nb = n > 0 ? (n + RB * PER - 1) / (RB * PER) : 1;
+    if (n > 0)
+        hipLaunchKernelGGL(sum_stage1<F>, dim3((unsigned)nb), dim3(RB), 0, s, f, n, partials);
+    else
+        hipLaunchKernelGGL(sum_stage1<F>, dim3(1), dim3(RB), 0, s, f, (int64_t)0, partials);
+    hipLaunchKernelGGL(sum_stage2, dim3(1), dim3(RB), 0, s, partials, nb, out);
+    return hipGetLastError();
+}
+
+__device__ inline double cell_centre(int64_t i, int64_t G, double L)
+{
+#pragma clang fp contract(off)
+    return -L + ((double)i + 0.5) * (2.0 * L / (double)G);
+}
+
+template <typename T>
+__global__ __launch_bounds__(EW) void cell_centres_kernel(int64_t G, double L, T *cx, T *cy, T *cz)
+{
+    const int64_t v = (int64_t)blockIdx.x * EW + threadIdx.x;
+    if (v >= G * G * G)
+        return;
+    cx[v] = (T)cell_centre(v % G, G, L);
+    cy[v] = (T)cell_centre((v / G) % G, G, L);
+    cz[v] = (T)cell_centre(v / (G * G), G, L);
+}
+
+template <typename T>
+__global__ __launch_bounds__(EW) void axpy_save_kernel(T *kx, T *ky, T *kz, T *kp, const T *g,
+                                                       T *gp, int64_t p, double eta)
+{
+    const int64_t e = (int64_t)blockIdx.x * EW + threadIdx.x;
+    if (e >= 3 * p)
+        return;
+    const int64_t c = e / p, i = e - c * p;
+    T *k = c == 0 ? kx : (c == 1 ? ky : kz);
+    const T kv = k[i], gv = g[e];
+    kp[e] = kv;
+    gp[e] = gv;
+    k[i] = (T)((double)kv - eta * (double)gv);
+}
+
+}  // namespace
+
+hipError_t launch_combine(double *acc, const double *part, int nslabs, int64_t ld, int64_t nt,
+                          bool init, hipStream_t s)
+{
+    if (nt <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(combine_kernel, dim3(ew_blocks(4 * nt)), dim3(EW), 0, s, acc, part, nslabs,
+                       ld, nt, init ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize_grad(int precision, const double *acc_a, const double *acc_r,
+                                int64_t ld, int64_t nt, double inv_p, double inv_p2, void *gx,
+                                void *gy, void *gz, double *pot_a, double *pot_r, hipStream_t s)
+{
+    if (nt <= 0)
+        return hipSuccess;
+    if (precision == SPK_PLAIN_FP64)
+        hipLaunchKernelGGL(finalize_kernel<double>, dim3(ew_blocks(nt)), dim3(EW), 0, s, acc_a,
+                           acc_r, ld, nt, inv_p, inv_p2, (double *)gx, (double *)gy, (double *)gz,
+                           pot_a, pot_r);
+    else
+        hipLaunchKernelGGL(finalize_kernel<float>, dim3(ew_blocks(nt)), dim3(EW), 0, s, acc_a,
+                           acc_r, ld, nt, inv_p, inv_p2, (float *)gx, (float *)gy, (float *)gz,
+                           pot_a, pot_r);
+    return hipGetLastError();
+}
+
+int64_t reduce_partials_size(int64_t n)
+{
+    const int64_t nb = n > 0 ? (n + RB * PER - 1) / (RB * PER) : 1;
+    return 2 * nb;
+}
+
+hipError_t launch_sum2(const double *x0, const double *x1, int64_t n, double *partials,
+                       double *out, hipStream_t s)
+{
+    return run_sum(Pair2{x0, x1}, n, partials, out, s);
+}
+
+hipError_t launch_wsum(const void *w, int precision, const double *x, int64_t n,
+                       double *partials, double *out, hipStream_t s)
+{
+    if (precision == SPK_PLAIN_FP64)
+        return run_sum(WeightedF<double>{(const double *)w, x}, n, partials, out, s);
+    return run_sum(WeightedF<float>{(const float *)w, x}, n, partials, out, s);
+}
+
+hipError_t launch_cell_centres(int precision, int64_t G, double L, void *cx, void *cy, void *cz,
+                               hipStream_t s)
+{
+    const int64_t M = G * G * G;
+    if (precision == SPK_PLAIN_FP64)
+        hipLaunchKernelGGL(cell_centres_kernel<double>, dim3(ew_blocks(M)), dim3(EW), 0, s, G, L,
+                           (double *)cx, (double *)cy, (double *)cz);
+    else
+        hipLaunchKernelGGL(cell_centres_kernel<float>, dim3(ew_blocks(M)), dim3(EW), 0, s, G, L,
+                           (float *)cx, (float *)cy, (float *)cz);
+    return hipGetLastError();
+}
+
+hipError_t launch_bb_dots(int precision, const void *kx, const void *ky, const void *kz,
+                          const void *k_prev, const void *g, const void *g_prev, int64_t p,
+                          double *partials, double *out, hipStream_t s)
+{
+    if (precision == SPK_PLAIN_FP64) {
+        using T = double;
+        return run_sum(DotsF<T>{(const T *)kx, (const T *)ky, (const T *)kz, (const T *)k_prev,
+                                (const T *)g, (const T *)g_prev, p},
+                       3 * p, partials, out, s);
+    }
+    using T = float;
+    return run_sum(DotsF<T>{(const T *)kx, (const T *)ky, (const T *)kz, (const T *)k_prev,
+                            (const T *)g, (const T *)g_prev, p},
+                   3 * p, partials, out, s);
+}
+
+hipError_t launch_axpy_save(int precision, void *kx, void *ky, void *kz, void *k_prev,
+                            const void *g, void *g_prev, int64_t p, double eta, hipStream_t s)
+{
+    if (precision == SPK_PLAIN_FP64) {
+        using T = double;
+        hipLaunchKernelGGL(axpy_save_kernel<T>, dim3(ew_blocks(3 * p)), dim3(EW), 0, s, (T *)kx,
+                           (T *)ky, (T *)kz, (T *)k_prev, (const T *)g, (T *)g_prev, p, eta);
+    } else {
+        using T = float;
+        hipLaunchKernelGGL(axpy_save_kernel<T>, dim3(ew_blocks(3 * p)), dim3(EW), 0, s, (T *)kx,
+                           (T *)ky, (T *)kz, (T *)k_prev, (const T *)g, (T *)g_prev, p, eta);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace spk

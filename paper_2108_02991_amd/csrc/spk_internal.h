@@ -1,0 +1,95 @@
+// Internal interfaces between the translation units of libsparkling.so.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "sparkling.h"
+
+namespace spk {
+
+// Threads per block of the pair sweeps.
+constexpr int kSweepBlock = 256;
+// Sources staged in LDS per tile by the sample sweep.
+constexpr int kSampleTile = 512;
+// Density cells staged in LDS per tile by the cell sweep (rows of G cells).
+constexpr int kCellTileF32 = 2048;
+constexpr int kCellTileF64 = 1024;
+// Largest grid side supported (one row must fit a tile).
+constexpr int64_t kMaxGrid = 1024;
+// Largest shot length the projection kernel supports.
+constexpr int64_t kMaxProjectSamples = 4096;
+
+// Targets handled by one block of a sweep (blockDim * targets per lane).
+int sweep_targets_per_block(int precision);
+
+// One launch of a pair sweep: a target range against `nslabs` consecutive
+// source slabs.  Slab y covers sources [src_begin + y*slab, min(+slab, src_end))
+// where a source is a sample (sample sweep) or a row of G cells (cell sweep).
+// Block (x, y) writes its four sums (gx, gy, gz, potential) for target t into
+// part[(y*4 + c)*ld + (t - t0)] as doubles.
+struct SweepLaunch {
+    int precision = 0;
+    bool energy = false;
+    const void *tx = nullptr, *ty = nullptr, *tz = nullptr;
+    int64_t t0 = 0, nt = 0;
+    const void *sx = nullptr, *sy = nullptr, *sz = nullptr;  // sample sweep sources
+    const void *rho = nullptr;                                 // cell sweep weights
+    int64_t grid = 1;
+    double half_width = 0.5;
+    double eps = 0.0;
+    int64_t src_begin = 0, slab = 0, src_end = 0;
+    int nslabs = 1;
+    double *part = nullptr;
+    int64_t ld = 0;
+};
+
+hipError_t launch_sweep_samples(const SweepLaunch &l, hipStream_t s);
+hipError_t launch_sweep_cells(const SweepLaunch &l, hipStream_t s);
+
+// acc[c*ld + t] = (init ? 0 : acc[c*ld + t]) + part[0][c][t] + ... + part[n-1][c][t]
+hipError_t launch_combine(double *acc, const double *part, int nslabs, int64_t ld, int64_t nt,
+                          bool init, hipStream_t s);
+
+// g[c][t] = acc_a[c][t] * inv_p - acc_r[c][t] * inv_p2 (cast to the precision's type);
+// pot_a/pot_r (nullable) receive row 3 of acc_a/acc_r.
+hipError_t launch_finalize_grad(int precision, const double *acc_a, const double *acc_r,
+                                int64_t ld, int64_t nt, double inv_p, double inv_p2,
+                                void *gx, void *gy, void *gz, double *pot_a, double *pot_r,
+                                hipStream_t s);
+
+// Deterministic double sums of n values at x (stride 1), two series at once:
+// out[0] = sum x0, out[1] = sum x1.  Uses `partials` (reduce_partials_size(n) doubles).
+int64_t reduce_partials_size(int64_t n);
+hipError_t launch_sum2(const double *x0, const double *x1, int64_t n, double *partials,
+                       double *out, hipStream_t s);
+// out[0] = sum_u w[u]*x[u]
+hipError_t launch_wsum(const void *w, int precision, const double *x, int64_t n,
+                       double *partials, double *out, hipStream_t s);
+
+// Voxel-centre coordinates of the G^3 grid (x fastest) into cx, cy, cz (precision type).
+hipError_t launch_cell_centres(int precision, int64_t G, double L, void *cx, void *cy, void *cz,
+                               hipStream_t s);
+
+// Step helpers.  K = {kx, ky, kz} (p each), k_prev/g_prev/g laid out [3][p].
+// out[0] = sum (K - k_prev)^2, out[1] = sum (K - k_prev) (g - g_prev).
+hipError_t launch_bb_dots(int precision, const void *kx, const void *ky, const void *kz,
+                          const void *k_prev, const void *g, const void *g_prev, int64_t p,
+                          double *partials, double *out, hipStream_t s);
+// k_prev = K; g_prev = g; K = K - eta * g (computed in double).
+hipError_t launch_axpy_save(int precision, void *kx, void *ky, void *kz, void *k_prev,
+                            const void *g, void *g_prev, int64_t p, double eta, hipStream_t s);
+
+// Projection and constraint check (one block per shot).
+hipError_t launch_project(int precision, void *kx, void *ky, void *kz, int64_t n_shots,
+                          int64_t n_samples, double L, double a, double b, int64_t te,
+                          int n_pit, hipStream_t s);
+// per_shot: n_shots*4 doubles; out: 4 doubles.
+hipError_t launch_constraint_check(int precision, const void *kx, const void *ky, const void *kz,
+                                   int64_t n_shots, int64_t n_samples, double L, double a,
+                                   double b, int64_t te, double *per_shot, double *out,
+                                   hipStream_t s);
+
+}  // namespace spk

@@ -1,0 +1,364 @@
+// Pair sweeps of the SPARKLING gradient (gfx950).
+//
+// Repulsion (Sec. "Evaluating F^r and its gradient"): for target i and every
+// sample j, d = K[i] - K[j], w = 1/sqrt(|d|^2 + g) with a guard g (eps^2, or
+// the smallest normal when eps = 0, so d = 0 contributes w*0 = 0),
+//   g_r[i] += w d,   u_r[i] += w |d|^2 (= H(d)).
+// Attraction (Sec. "Evaluating F^a and its gradient", discretised density):
+// the same with every grid cell v as a source weighted by rho_v,
+//   g_a[i] += rho_v w d,   u_a[i] += rho_v w |d|^2.
+//
+// Layout and schedule.  Each lane owns R targets (register blocking), a block
+// of 256 lanes owns 256*R consecutive targets (coalesced SoA loads), and the
+// block's sources are staged tile by tile in LDS; every lane of a wave then
+// reads the same LDS address (a broadcast) and runs R pairs per read.  There
+// is no MFMA: the pair map is not a contraction, so the sweep is bound by the
+// VALU issue rate (subtract, FMA, and one reciprocal square root per pair).
+// The cell sweep walks the grid row by row: inside an x-row the y and z
+// offsets are constant, so a pair costs one subtract, one FMA for |d|^2, the
+// rsqrt, one multiply by rho_v, one add for the row weight and one FMA for
+// the x force; the y and z forces are row weight times offset, once per row.
+//
+// Precision forms (template MODE):
+//   kPlain64 : double coordinates, double math, double running sums;
+//   kComp    : float pair math, float per-tile sums folded into a float
+//              (sum, compensation) pair by an error-free two-sum;
+//   kNaive   : float pair math, one float running sum per slab (diagnostic);
+//   kAcc64   : float pair math, every pair term added into a double (diagnostic).
+// Every form writes its slab sums as doubles; slabs are combined in a fixed
+// order elsewhere, so results do not depend on the target chunking.
+
+#include <cfloat>
+
+#include "spk_internal.h"
+
+namespace spk {
+namespace {
+
+enum : int { kPlain64 = SPK_PLAIN_FP64, kComp = SPK_FP32_COMP, kNaive = SPK_FP32_NAIVE,
+             kAcc64 = SPK_FP32_ACC64 };
+
+constexpr int BLK = kSweepBlock;
+
+template <int MODE> struct ModeT {
+    using T = float;       // coordinate / pair-math type
+    using A = float;       // accumulator type inside a tile
+};
+template <> struct ModeT<kPlain64> { using T = double; using A = double; };
+template <> struct ModeT<kAcc64> { using T = float; using A = double; };
+
+template <int MODE> constexpr int lanes_targets() { return MODE == kPlain64 ? 2 : 4; }
+
+template <typename T> struct alignas(4 * sizeof(T)) P4 { T x, y, z, w; };
+template <typename T> struct alignas(2 * sizeof(T)) P2 { T x, y; };
+
+__device__ inline float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ inline double rsq(double x) { return rsqrt(x); }
+
+__device__ inline float fmaT(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ inline double fmaT(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// Cell centre -L + (i + 1/2) * (2L / G), evaluated exactly in this order in double.
+__device__ inline double cell_centre(int64_t i, int64_t G, double L)
+{
+#pragma clang fp contract(off)
+    return -L + ((double)i + 0.5) * (2.0 * L / (double)G);
+}
+
+template <typename T> __device__ inline T guard_value(double eps);
+template <> __device__ inline float guard_value<float>(double eps)
+{
+    float e2 = (float)(eps * eps);
+    return e2 > FLT_MIN ? e2 : FLT_MIN;
+}
+template <> __device__ inline double guard_value<double>(double eps)
+{
+    double e2 = eps * eps;
+    return e2 > DBL_MIN ? e2 : DBL_MIN;
+}
+
+// Running sums of one target component across tiles.
+template <int MODE> struct Acc {
+    typename ModeT<MODE>::A t = 0;    // inside the current tile (or whole slab)
+    float s = 0.f, c = 0.f;           // kComp: compensated total
+    __device__ inline void end_tile()
+    {
+        if constexpr (MODE == kComp) {
+            float x = t;
+            float sum = s + x;
+            float bp = sum - s;
+            float err = (s - (sum - bp)) + (x - bp);
+            s = sum;
+            c += err;
+            t = 0.f;
+        }
+    }
+    __device__ inline double total() const
+    {
+        if constexpr (MODE == kComp)
+            return (double)s + (double)c;
+        else
+            return (double)t;
+    }
+};
+
+// gx += w * d for the accumulator of this mode.
+template <int MODE, typename T>
+__device__ inline void acc_fma(Acc<MODE> &a, T w, T d)
+{
+    if constexpr (MODE == kAcc64)
+        a.t += (double)(w * d);
+    else
+        a.t = fmaT(w, d, a.t);
+}
+
+template <int MODE, int R, bool ENERGY>
+__global__ __launch_bounds__(BLK) void sweep_samples_kernel(SweepLaunch l)
+{
+    using T = typename ModeT<MODE>::T;
+    __shared__ P4<T> tile[kSampleTile];
+
+    const T *tx = static_cast<const T *>(l.tx), *ty = static_cast<const T *>(l.ty),
+            *tz = static_cast<const T *>(l.tz);
+    const T *sx = static_cast<const T *>(l.sx), *sy = static_cast<const T *>(l.sy),
+            *sz = static_cast<const T *>(l.sz);
+
+    const int64_t tlast = l.t0 + l.nt - 1;
+    const int64_t tbase = l.t0 + (int64_t)blockIdx.x * (BLK * R) + threadIdx.x;
+    T xi[R], yi[R], zi[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        int64_t t = tbase + r * BLK;
+        t = t < tlast ? t : tlast;
+        xi[r] = tx[t];
+        yi[r] = ty[t];
+        zi[r] = tz[t];
+    }
+    Acc<MODE> gx[R], gy[R], gz[R], ee[R];
+    const T guard = guard_value<T>(l.eps);
+
+    const int64_t lo = l.src_begin + (int64_t)blockIdx.y * l.slab;
+    int64_t hi = lo + l.slab;
+    hi = hi < l.src_end ? hi : l.src_end;
+
+    for (int64_t base = lo; base < hi; base += kSampleTile) {
+        const int n = (int)((hi - base) < kSampleTile ? (hi - base) : kSampleTile);
+        for (int j = threadIdx.x; j < n; j += BLK)
+            tile[j] = P4<T>{sx[base + j], sy[base + j], sz[base + j], T(0)};
+        __syncthreads();
+
+        auto pair = [&](const P4<T> s) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                T dx = xi[r] - s.x, dy = yi[r] - s.y, dz = zi[r] - s.z;
+                T r2 = fmaT(dz, dz, fmaT(dy, dy, fmaT(dx, dx, guard)));
+                T w = rsq(r2);
+                acc_fma(gx[r], w, dx);
+                acc_fma(gy[r], w, dy);
+                acc_fma(gz[r], w, dz);
+                if constexpr (ENERGY)
+                    acc_fma(ee[r], w, r2);
+            }
+        };
+        if (n == kSampleTile) {
+#pragma unroll 4
+            for (int j = 0; j < kSampleTile; ++j)
+                pair(tile[j]);
+        } else {
+            for (int j = 0; j < n; ++j)
+                pair(tile[j]);
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            gx[r].end_tile();
+            gy[r].end_tile();
+            gz[r].end_tile();
+            if constexpr (ENERGY)
+                ee[r].end_tile();
+        }
+        __syncthreads();
+    }
+
+    double *out = l.part + (int64_t)blockIdx.y * 4 * l.ld;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t t = tbase + r * BLK;
+        if (t <= tlast) {
+            const int64_t o = t - l.t0;
+            out[o] = gx[r].total();
+            out[l.ld + o] = gy[r].total();
+            out[2 * l.ld + o] = gz[r].total();
+            out[3 * l.ld + o] = ENERGY ? ee[r].total() : 0.0;
+        }
+    }
+}
+
+template <int MODE, int R, bool ENERGY>
+__global__ __launch_bounds__(BLK) void sweep_cells_kernel(SweepLaunch l)
+{
+    using T = typename ModeT<MODE>::T;
+    constexpr int TILE = MODE == kPlain64 ? kCellTileF64 : kCellTileF32;
+    __shared__ P2<T> cell[TILE];     // (x_v, rho_v) of the tile's cells, row after row
+    __shared__ P2<T> rowyz[TILE];    // (y, z) of each row of the tile
+
+    const T *tx = static_cast<const T *>(l.tx), *ty = static_cast<const T *>(l.ty),
+            *tz = static_cast<const T *>(l.tz);
+    const T *rho = static_cast<const T *>(l.rho);
+    const int64_t G = l.grid;
+    const int g = (int)G;
+    const double L = l.half_width;
+
+    const int64_t tlast = l.t0 + l.nt - 1;
+    const int64_t tbase = l.t0 + (int64_t)blockIdx.x * (BLK * R) + threadIdx.x;
+    T xi[R], yi[R], zi[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        int64_t t = tbase + r * BLK;
+        t = t < tlast ? t : tlast;
+        xi[r] = tx[t];
+        yi[r] = ty[t];
+        zi[r] = tz[t];
+    }
+    Acc<MODE> gx[R], gy[R], gz[R], ee[R];
+    const T guard = guard_value<T>(l.eps);
+
+    const int rows_per_tile = TILE / g;
+    const int64_t lo = l.src_begin + (int64_t)blockIdx.y * l.slab;
+    int64_t hi = lo + l.slab;
+    hi = hi < l.src_end ? hi : l.src_end;
+
+    for (int64_t base = lo; base < hi; base += rows_per_tile) {
+        const int nr = (int)((hi - base) < rows_per_tile ? (hi - base) : rows_per_tile);
+        const int nv = nr * g;
+        for (int j = threadIdx.x; j < nv; j += BLK) {
+            const int ix = j % g;
+            cell[j] = P2<T>{(T)cell_centre(ix, G, L), rho[base * G + j]};
+        }
+        for (int j = threadIdx.x; j < nr; j += BLK) {
+            const int64_t row = base + j;
+            rowyz[j] = P2<T>{(T)cell_centre(row % G, G, L), (T)cell_centre(row / G, G, L)};
+        }
+        __syncthreads();
+
+        for (int rr = 0; rr < nr; ++rr) {
+            const P2<T> yz = rowyz[rr];
+            T dy[R], dz[R], c[R];
+            typename ModeT<MODE>::A wrow[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                dy[r] = yi[r] - yz.x;
+                dz[r] = zi[r] - yz.y;
+                c[r] = fmaT(dz[r], dz[r], fmaT(dy[r], dy[r], guard));
+                wrow[r] = 0;
+            }
+            const P2<T> *rowp = cell + rr * g;
+            auto pair = [&](const P2<T> v) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    T dx = xi[r] - v.x;
+                    T r2 = fmaT(dx, dx, c[r]);
+                    T w = v.y * rsq(r2);
+                    wrow[r] += w;
+                    acc_fma(gx[r], w, dx);
+                    if constexpr (ENERGY)
+                        acc_fma(ee[r], w, r2);
+                }
+            };
+            int ix = 0;
+#pragma unroll 4
+            for (; ix + 4 <= g; ix += 4) {
+                pair(rowp[ix]);
+                pair(rowp[ix + 1]);
+                pair(rowp[ix + 2]);
+                pair(rowp[ix + 3]);
+            }
+            for (; ix < g; ++ix)
+                pair(rowp[ix]);
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                if constexpr (MODE == kAcc64) {
+                    gy[r].t += wrow[r] * (double)dy[r];
+                    gz[r].t += wrow[r] * (double)dz[r];
+                } else {
+                    gy[r].t = fmaT(wrow[r], dy[r], gy[r].t);
+                    gz[r].t = fmaT(wrow[r], dz[r], gz[r].t);
+                }
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            gx[r].end_tile();
+            gy[r].end_tile();
+            gz[r].end_tile();
+            if constexpr (ENERGY)
+                ee[r].end_tile();
+        }
+        __syncthreads();
+    }
+
+    double *out = l.part + (int64_t)blockIdx.y * 4 * l.ld;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t t = tbase + r * BLK;
+        if (t <= tlast) {
+            const int64_t o = t - l.t0;
+            out[o] = gx[r].total();
+            out[l.ld + o] = gy[r].total();
+            out[2 * l.ld + o] = gz[r].total();
+            out[3 * l.ld + o] = ENERGY ? ee[r].total() : 0.0;
+        }
+    }
+}
+
+template <int MODE, bool ENERGY>
+hipError_t launch_samples_mode(const SweepLaunch &l, hipStream_t s)
+{
+    constexpr int R = lanes_targets<MODE>();
+    dim3 grid((unsigned)((l.nt + BLK * R - 1) / (BLK * R)), (unsigned)l.nslabs);
+    hipLaunchKernelGGL((sweep_samples_kernel<MODE, R, ENERGY>), grid, dim3(BLK), 0, s, l);
+    return hipGetLastError();
+}
+
+template <int MODE, bool ENERGY>
+hipError_t launch_cells_mode(const SweepLaunch &l, hipStream_t s)
+{
+    constexpr int R = lanes_targets<MODE>();
+    dim3 grid((unsigned)((l.nt + BLK * R - 1) / (BLK * R)), (unsigned)l.nslabs);
+    hipLaunchKernelGGL((sweep_cells_kernel<MODE, R, ENERGY>), grid, dim3(BLK), 0, s, l);
+    return hipGetLastError();
+}
+
+template <bool CELLS, bool ENERGY>
+hipError_t launch_any(const SweepLaunch &l, hipStream_t s)
+{
+    switch (l.precision) {
+    case kPlain64: return CELLS ? launch_cells_mode<kPlain64, ENERGY>(l, s) : launch_samples_mode<kPlain64, ENERGY>(l, s);
+    case kComp: return CELLS ? launch_cells_mode<kComp, ENERGY>(l, s) : launch_samples_mode<kComp, ENERGY>(l, s);
+    case kNaive: return CELLS ? launch_cells_mode<kNaive, ENERGY>(l, s) : launch_samples_mode<kNaive, ENERGY>(l, s);
+    case kAcc64: return CELLS ? launch_cells_mode<kAcc64, ENERGY>(l, s) : launch_samples_mode<kAcc64, ENERGY>(l, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+int sweep_targets_per_block(int precision)
+{
+    return BLK * (precision == kPlain64 ? lanes_targets<kPlain64>() : lanes_targets<kComp>());
+}
+
+hipError_t launch_sweep_samples(const SweepLaunch &l, hipStream_t s)
+{
+    if (l.nt <= 0 || l.nslabs <= 0)
+        return hipSuccess;
+    return l.energy ? launch_any<false, true>(l, s) : launch_any<false, false>(l, s);
+}
+
+hipError_t launch_sweep_cells(const SweepLaunch &l, hipStream_t s)
+{
+    if (l.nt <= 0 || l.nslabs <= 0)
+        return hipSuccess;
+    return l.energy ? launch_any<true, true>(l, s) : launch_any<true, false>(l, s);
+}
+
+}  // namespace spk

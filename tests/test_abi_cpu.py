@@ -1,0 +1,193 @@
+"""The C ABI without a GPU: exported symbols, host helpers and argument validation.
+
+Validation runs before any HIP call, so every rejected call below returns its
+status without touching a device.  No compute entry point is run here.
+"""
+import ctypes
+import json
+import os
+import re
+
+import pytest
+
+import oracle
+import paper_2108_02991_amd as spk
+from paper_2108_02991_amd import api, configs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sparkling.h")
+EINVAL, EWORKSPACE, EUNSUPPORTED = -1, -2, -4
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not api.LIB_PATH.exists():
+        from paper_2108_02991_amd import build
+        build.build()
+    return spk.load_library()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(\w+)\s*\(", text, flags=re.M)))
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_functions()
+    assert {"sparkling_energy", "sparkling_grad", "sparkling_project", "sparkling_step",
+            "spk_workspace_size", "spk_alpha_beta"} <= set(names)
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_status_strings(lib):
+    for code in (0, -1, -2, -3, -4, -5):
+        assert lib.spk_status_string(code)
+    assert lib.spk_status_string(99) == b"unknown status"
+
+
+def test_alpha_beta_matches_oracle_and_golden(lib):
+    with open(os.path.join(ROOT, "tests", "golden", "alpha_beta.json")) as f:
+        gold = json.load(f)
+    for case in gold["cases"]:
+        a, b = spk.alpha_beta(*case["args"])
+        oa, ob = oracle.alpha_beta(*case["args"])
+        assert a == pytest.approx(case["a"], rel=1e-5) and b == pytest.approx(case["b"], rel=1e-5)
+        assert a == pytest.approx(oa, rel=1e-15) and b == pytest.approx(ob, rel=1e-15)
+    with pytest.raises(spk.SparklingError):
+        spk.alpha_beta(0.04, 180, 1e-5, 2e-6, 0.0, 66.0, 42.576e6, 0.5)
+
+
+def good_params(**kw):
+    base = dict(n_shots=4, n_samples=16, grid=8, precision="fp32_comp", a_max=0.1, b_max=0.01)
+    base.update(kw)
+    return spk.Params(**base)
+
+
+def test_workspace_size_monotone(lib):
+    small = spk.workspace_size(good_params())
+    big = spk.workspace_size(good_params(n_shots=64))
+    disc = spk.workspace_size(good_params(discrepancy=True, grid=32))
+    assert 0 < small < big and disc > small
+    assert spk.workspace_size(spk.Params(4096, 2048, 192)) < 2 * 2 ** 30
+
+
+@pytest.mark.parametrize("bad", [
+    dict(n_shots=0), dict(n_samples=0), dict(grid=0), dict(grid=2000), dict(te_index=16),
+    dict(te_index=-2), dict(half_width=0.0), dict(half_width=float("nan")), dict(eps=-1.0),
+    dict(n_shots=2 ** 20, n_samples=2 ** 12),
+])
+def test_bad_params_rejected(lib, bad):
+    prm = good_params(**bad)
+    n = ctypes.c_size_t()
+    c = prm.c()
+    assert lib.spk_workspace_size(ctypes.byref(c), ctypes.byref(n)) == EINVAL
+    assert lib.spk_last_error()
+
+
+def test_unknown_precision_and_flags(lib):
+    c = good_params().c()
+    c.precision = 7
+    n = ctypes.c_size_t()
+    assert lib.spk_workspace_size(ctypes.byref(c), ctypes.byref(n)) == EINVAL
+    c = good_params().c()
+    c.flags = 4
+    assert lib.spk_workspace_size(ctypes.byref(c), ctypes.byref(n)) == EINVAL
+    assert lib.spk_workspace_size(None, ctypes.byref(n)) == EINVAL
+
+
+FAKE = 0x10000   # an aligned, never dereferenced address
+
+
+def grad_call(lib, prm, ptrs=None, b=0, e=None, ws=FAKE, ws_bytes=None, energy=None):
+    c = prm.c()
+    ptrs = ptrs or [FAKE] * 7
+    e = prm.p if e is None else e
+    ws_bytes = spk.workspace_size(prm) if ws_bytes is None else ws_bytes
+    return lib.sparkling_grad(ctypes.byref(c), *[ctypes.c_void_p(x) for x in ptrs[:4]],
+                              *[ctypes.c_void_p(x) for x in ptrs[4:7]], b, e, None, None, energy,
+                              ctypes.c_void_p(ws), ws_bytes, None)
+
+
+def test_grad_validation(lib):
+    prm = good_params()
+    ptrs = [FAKE] * 7
+    for k in range(7):
+        bad = list(ptrs)
+        bad[k] = 0
+        assert grad_call(lib, prm, bad) == EINVAL
+    bad = list(ptrs)
+    bad[2] = FAKE + 2        # misaligned float array
+    assert grad_call(lib, prm, bad) == EINVAL
+    assert grad_call(lib, prm, b=-1) == EINVAL
+    assert grad_call(lib, prm, b=10, e=5) == EINVAL
+    assert grad_call(lib, prm, e=prm.p + 1) == EINVAL
+    assert grad_call(lib, prm, b=3, e=9, energy=(ctypes.c_double * 3)()) == EINVAL
+    assert grad_call(lib, prm, ws_bytes=16) == EWORKSPACE
+    assert grad_call(lib, prm, ws=0) == EWORKSPACE
+    # an empty target range is valid, launches nothing and takes NULL outputs
+    assert grad_call(lib, prm, b=5, e=5) == 0
+    assert grad_call(lib, prm, [FAKE] * 4 + [0, 0, 0], b=5, e=5) == 0
+
+
+def test_plain_fp64_needs_8_byte_alignment(lib):
+    prm = good_params(precision="plain_fp64")
+    bad = [FAKE] * 7
+    bad[0] = FAKE + 4
+    assert grad_call(lib, prm, bad) == EINVAL
+
+
+def test_energy_project_step_validation(lib):
+    prm = good_params()
+    c = prm.c()
+    out = (ctypes.c_double * 4)()
+    n = spk.workspace_size(prm)
+    v = ctypes.c_void_p
+    assert lib.sparkling_energy(ctypes.byref(c), v(FAKE), v(FAKE), v(FAKE), v(FAKE), None,
+                                v(FAKE), n, None) == EINVAL
+    assert lib.sparkling_energy(ctypes.byref(c), v(FAKE), v(0), v(FAKE), v(FAKE), out,
+                                v(FAKE), n, None) == EINVAL
+    assert lib.sparkling_energy(ctypes.byref(c), v(FAKE), v(FAKE), v(FAKE), v(FAKE), out,
+                                v(FAKE), 8, None) == EWORKSPACE
+    # projection needs positive bounds, 2 <= Ns <= 4096
+    for kw, want in [(dict(a_max=0.0), EINVAL), (dict(b_max=-1.0), EINVAL),
+                     (dict(n_samples=1, te_index=0), EINVAL), (dict(n_pit=-1), EINVAL),
+                     (dict(n_shots=1, n_samples=5000), EUNSUPPORTED)]:
+        cp = good_params(**kw).c()
+        assert lib.sparkling_project(ctypes.byref(cp), v(FAKE), v(FAKE), v(FAKE), None, v(FAKE),
+                                     1 << 40, None) == want, kw
+        assert lib.sparkling_constraint_check(ctypes.byref(cp), v(FAKE), v(FAKE), v(FAKE), out,
+                                              v(FAKE), 1 << 40, None) == want, kw
+    info = api.SpkStepInfo()
+    info.iter = 0
+    info.eta_fixed = 0.0
+    assert lib.sparkling_step(ctypes.byref(c), v(FAKE), v(FAKE), v(FAKE), v(FAKE), v(FAKE),
+                              v(FAKE), ctypes.byref(info), v(FAKE), n, None) == EINVAL
+    info.eta_fixed = 1.0
+    info.iter = -3
+    assert lib.sparkling_step(ctypes.byref(c), v(FAKE), v(FAKE), v(FAKE), v(FAKE), v(FAKE),
+                              v(FAKE), ctypes.byref(info), v(FAKE), n, None) == EINVAL
+    assert lib.sparkling_step(ctypes.byref(c), v(FAKE), v(FAKE), v(FAKE), v(FAKE), v(0),
+                              v(FAKE), ctypes.byref(info), v(FAKE), n, None) == EINVAL
+
+
+def test_timing_query_rejects_unknown_kind(lib):
+    assert lib.spk_timing_query(9, None, None, None) == EINVAL
+
+
+def test_python_binding_checks_shapes():
+    import torch
+    prm = good_params()
+    with pytest.raises(ValueError):
+        spk.grad(torch.zeros(3, prm.p), torch.zeros(prm.grid ** 3), prm)
+
+
+def test_workloads_have_consistent_bounds(lib):
+    for w in configs.WORKLOADS.values():
+        a, b = spk.alpha_beta(configs.GMAX, configs.SMAX, configs.RASTER_DT, configs.DWELL_DT,
+                              w.fov, w.kmax, configs.GAMMA_BAR, w.half_width)
+        # gradient-amplitude bound binds at a 2 us dwell for every workload
+        assert a == pytest.approx(configs.GAMMA_BAR * configs.GMAX * configs.RASTER_DT
+                                  * w.half_width / w.kmax, rel=1e-14)
+        assert a / b == pytest.approx(configs.GMAX / configs.SMAX / configs.RASTER_DT, rel=1e-12)

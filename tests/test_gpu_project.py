@@ -1,0 +1,118 @@
+"""GPU projection and constraint check against the FP64 oracle, through the C ABI.
+
+Both sides run the same dual iteration in the same operation order with no
+floating-point contraction, so the FP64 results are compared bit for bit.
+"""
+import numpy as np
+import pytest
+import torch
+
+from gpu_util import bounds, configs, device_problem, host64, inputs, oracle, params_for, say, spk
+
+pytestmark = pytest.mark.gpu
+
+
+def project_both(dev, K, Nc, Ns, a, b, te, n_pit, precision="plain_fp64", L=0.5):
+    prm = spk.Params(Nc, Ns, 1, precision=precision, half_width=L, a_max=a, b_max=b,
+                     te_index=te, n_pit=n_pit)
+    Kd, _ = device_problem(K, [1.0], precision, dev)
+    K_in = host64(Kd)
+    say(f"  project {precision} Nc={Nc} Ns={Ns} te={te} n_pit={n_pit}")
+    viol = spk.project_(Kd, prm)
+    ref = oracle.project(K_in, Nc, Ns, L, a, b, te, n_pit)
+    return prm, Kd, host64(Kd), ref, viol
+
+
+@pytest.mark.parametrize("Ns", [2, 3, 5, 64, 1000, 1024, 1025, 2048, 4096])
+def test_projection_bitwise_fp64(gpu, Ns):
+    Nc = 6
+    K = inputs.radial_spokes(Nc, Ns, 0.5, seed=Ns, jitter=0.05)
+    a, b = bounds(configs.C5)
+    prm, Kd, got, ref, viol = project_both(gpu, K, Nc, Ns, a, b, 0, 200)
+    assert np.array_equal(got, ref), np.abs(got - ref).max()
+    assert np.array_equal(viol, oracle.constraint_check(got, Nc, Ns, 0.5, a, b, 0))
+
+
+@pytest.mark.parametrize("te", [-1, 0, 7])
+def test_projection_te_and_box_exact(gpu, te):
+    Nc, Ns = 5, 40
+    rng = np.random.default_rng(3)
+    K = rng.uniform(-0.9, 0.9, (3, Nc * Ns))
+    prm, Kd, got, ref, viol = project_both(gpu, K, Nc, Ns, 0.05, 0.01, te, 100)
+    assert np.array_equal(got, ref)
+    assert np.abs(got).max() <= 0.5
+    if te >= 0:
+        assert np.all(got[:, te::Ns] == 0.0) and viol[3] == 0.0
+
+
+def test_projection_fp32_storage(gpu):
+    """FP32 trajectories: FP64 iteration on the widened values, one rounding on output."""
+    Nc, Ns = 8, 300
+    K = inputs.radial_spokes(Nc, Ns, 0.5, seed=4, jitter=0.05)
+    a, b = bounds(configs.C5)
+    prm, Kd, got, ref, viol = project_both(gpu, K, Nc, Ns, a, b, 0, 200, "fp32_comp")
+    assert np.array_equal(got, ref.astype(np.float32).astype(np.float64))
+    assert np.array_equal(viol, oracle.constraint_check(got, Nc, Ns, 0.5, a, b, 0))
+
+
+def test_feasible_input_is_unchanged_bitwise(gpu):
+    rng = np.random.default_rng(9)
+    Nc, Ns, a, b = 4, 128, 0.05, 0.004
+    shots = []
+    for _ in range(Nc):
+        acc = rng.normal(size=(3, Ns))
+        acc *= 0.4 * b / np.linalg.norm(acc, axis=0).max()
+        vel = np.cumsum(acc, axis=1)
+        vel *= min(1.0, 0.4 * a / np.linalg.norm(vel, axis=0).max())
+        s = np.concatenate([np.zeros((3, 1)), np.cumsum(vel, axis=1)[:, :-1]], axis=1)
+        s *= min(1.0, 0.4 / np.abs(s).max())      # shrinking keeps speed and slew feasible
+        shots.append(s)
+    K = np.concatenate(shots, axis=1)
+    assert oracle.constraint_check(K, Nc, Ns, 0.5, a, b, 0).max() < 1
+    prm, Kd, got, ref, viol = project_both(gpu, K, Nc, Ns, a, b, 0, 200)
+    assert np.array_equal(got, K) and np.array_equal(ref, K)
+    assert viol[0] < 1 and viol[1] < 1 and viol[2] < 1
+
+
+def test_projection_rerun_bitwise_and_violation(gpu):
+    w = configs.C5
+    K = inputs.radial_spokes(64, w.n_samples, 0.5, seed=12, jitter=w.jitter)
+    a, b = bounds(w)
+    outs = []
+    for _ in range(2):
+        prm, Kd, got, ref, viol = project_both(gpu, K, 64, w.n_samples, a, b, 0, w.n_pit,
+                                               "fp32_comp")
+        outs.append((got, viol))
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+    viol = outs[0][1]
+    say(f"  violations after {w.n_pit} iterations: {viol}")
+    assert viol[2] <= 1.0 and viol[3] == 0.0
+    assert viol[0] < 1.5 and viol[1] < 2.0
+
+
+def test_c5_full_size_projection(gpu):
+    """2048 shots x 1024 samples, 200 iterations: every shot matches the oracle."""
+    w = configs.C5
+    K = w.trajectory()
+    a, b = bounds(w)
+    prm, Kd, got, ref, viol = project_both(gpu, K, w.n_shots, w.n_samples, a, b, 0, w.n_pit,
+                                           "fp32_comp")
+    assert np.array_equal(got, ref.astype(np.float32).astype(np.float64))
+    want = oracle.constraint_check(got, w.n_shots, w.n_samples, 0.5, a, b, 0)
+    assert np.array_equal(viol, want)
+
+
+def test_constraint_check_bitwise(gpu):
+    rng = np.random.default_rng(2)
+    Nc, Ns = 33, 257
+    K = rng.uniform(-0.6, 0.6, (3, Nc * Ns))
+    for precision in ("plain_fp64", "fp32_comp"):
+        prm = spk.Params(Nc, Ns, 1, precision=precision, a_max=0.07, b_max=0.011, te_index=5)
+        Kd, _ = device_problem(K, [1.0], precision, gpu)
+        got = spk.constraint_check(Kd, prm)
+        want = oracle.constraint_check(host64(Kd), Nc, Ns, 0.5, 0.07, 0.011, 5)
+        assert np.array_equal(got, want)
+    K[1, 100] = np.nan
+    Kd, _ = device_problem(K, [1.0], "plain_fp64", gpu)
+    prm = spk.Params(Nc, Ns, 1, precision="plain_fp64", a_max=0.07, b_max=0.011)
+    assert np.isnan(spk.constraint_check(Kd, prm)[:3]).all()

@@ -1,0 +1,87 @@
+"""Projected gradient steps on the GPU against the oracle's steps."""
+import numpy as np
+import pytest
+import torch
+
+from gpu_util import bounds, configs, device_problem, host64, inputs, oracle, params_for, say, spk
+
+pytestmark = pytest.mark.gpu
+
+
+def test_c1_five_iterations_plain_fp64(gpu):
+    w = configs.C1
+    K, rho = w.trajectory(), w.density()
+    a, b = bounds(w)
+    prm = params_for(w, "plain_fp64")
+    Kd, rd = device_problem(K, rho, "plain_fp64", gpu)
+    state = spk.StepState(prm, gpu)
+    Ko, kp, gp = K.copy(), np.zeros_like(K), np.zeros_like(K)
+    for it in range(w.n_iters):
+        say(f"  c1 step {it}")
+        info = spk.step_(Kd, rd, prm, state, it, w.eta_fixed)
+        Ko, kp, gp, oinfo = oracle.step(Ko, rho, w.n_shots, w.n_samples, w.grid, 0.5, a, b, 0,
+                                        w.n_pit, kp, gp, it, w.eta_fixed)
+        assert info["eta"] == oinfo["eta"]
+        assert info["F"] == pytest.approx(oinfo["F"], rel=1e-12)
+        assert np.abs(host64(Kd) - Ko).max() <= 1e-10
+        assert np.abs(host64(state.g_prev) - gp).max() <= 1e-12 * np.abs(gp).max()
+        np.testing.assert_allclose(info["viol"], oinfo["viol"], rtol=1e-8)
+    # the energy decreased over the run
+    assert oinfo["F"] < oracle.energy(K, rho, w.grid, 0.5)[0]
+
+
+def test_barzilai_borwein_iterations(gpu):
+    """Iterations 20.. use the BB step: compare eta with the oracle's."""
+    w = configs.C1
+    K = inputs.radial_spokes(16, 64, 0.5, seed=7, jitter=0.01)
+    rho = w.density()
+    a, b = bounds(w)
+    prm = spk.Params(16, 64, w.grid, precision="plain_fp64", a_max=a, b_max=b, n_pit=200)
+    Kd, rd = device_problem(K, rho, "plain_fp64", gpu)
+    state = spk.StepState(prm, gpu)
+    Ko, kp, gp = K.copy(), np.zeros_like(K), np.zeros_like(K)
+    used = 0
+    for it in range(18, 24):
+        info = spk.step_(Kd, rd, prm, state, it, 16.0)
+        Ko, kp, gp, oinfo = oracle.step(Ko, rho, 16, 64, w.grid, 0.5, a, b, 0, 200, kp, gp, it,
+                                        16.0)
+        assert info["bb_used"] == oinfo["bb_used"]
+        assert info["eta"] == pytest.approx(oinfo["eta"], rel=1e-9)
+        assert np.abs(host64(Kd) - Ko).max() <= 1e-9
+        used += info["bb_used"]
+    assert used >= 2
+
+
+def test_fp32_step_and_resume_bitwise(gpu):
+    """Saving the caller-owned state and resuming continues bit-identically."""
+    w = configs.C4
+    K, rho = w.trajectory(), w.density()
+    prm = params_for(w, "fp32_comp")
+    Kd, rd = device_problem(K, rho, "fp32_comp", gpu)
+    spk.project_(Kd, prm)
+    state = spk.StepState(prm, gpu)
+    for it in range(3):
+        spk.step_(Kd, rd, prm, state, it, w.eta_fixed)
+    saved = [Kd.clone(), state.k_prev.clone(), state.g_prev.clone()]
+    ref = [spk.step_(Kd, rd, prm, state, it, w.eta_fixed) for it in (3, 4)]
+    K2 = saved[0].clone()
+    st2 = spk.StepState(prm, gpu)
+    st2.k_prev.copy_(saved[1])
+    st2.g_prev.copy_(saved[2])
+    again = [spk.step_(K2, rd, prm, st2, it, w.eta_fixed) for it in (3, 4)]
+    assert torch.equal(K2, Kd)
+    for x, y in zip(ref, again):
+        assert x["F"] == y["F"] and x["eta"] == y["eta"]
+        assert np.array_equal(x["viol"], y["viol"])
+
+
+def test_nonfinite_energy_reported(gpu):
+    w = configs.C1
+    prm = spk.Params(4, 16, 4, precision="fp32_comp", a_max=0.1, b_max=0.01)
+    K = inputs.radial_spokes(4, 16, 0.5, seed=1)
+    K[0, 5] = np.nan
+    Kd, rd = device_problem(K, inputs.radial_density(4, 0.5, 0.05, 2.0), "fp32_comp", gpu)
+    state = spk.StepState(prm, gpu)
+    with pytest.raises(spk.SparklingError) as e:
+        spk.step_(Kd, rd, prm, state, 0, 1.0)
+    assert e.value.status == -5
