@@ -28,8 +28,8 @@ FLAGS = [
 ]
 
 
-def _compile(src: str, extra) -> Path:
-    obj = BUILD_DIR / (Path(src).stem + ".o")
+def _compile(src: str, extra, bdir: Path) -> Path:
+    obj = bdir / (Path(src).stem + ".o")
     cmd = [HIPCC, *FLAGS, *extra, "-c", str(CSRC / src), "-o", str(obj)]
     if src.endswith(".cpp"):
         cmd.insert(1, "-x")
@@ -40,18 +40,24 @@ def _compile(src: str, extra) -> Path:
     return obj
 
 
-def build(extra_flags=()) -> Path:
-    """Compile every source and link libsparkling.so next to this file."""
-    BUILD_DIR.mkdir(exist_ok=True)
+def build(extra_flags=(), out: Path | None = None, build_dir: Path | None = None) -> Path:
+    """Compile every source and link libsparkling.so (next to this file by default).
+
+    extra_flags may override the sweep tunables of spk_internal.h, e.g.
+    ["-DSPK_TARGETS_F32=8"]; such variants should go to another `out`.
+    """
+    out = Path(out) if out else OUT
+    bdir = Path(build_dir) if build_dir else BUILD_DIR
+    bdir.mkdir(parents=True, exist_ok=True)
     with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
-        objs = list(ex.map(lambda s: _compile(s, list(extra_flags)), SOURCES))
-    tmp = OUT.with_suffix(".so.tmp%d" % os.getpid())
+        objs = list(ex.map(lambda s: _compile(s, list(extra_flags), bdir), SOURCES))
+    tmp = out.with_suffix(".so.tmp%d" % os.getpid())
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *map(str, objs), "-o", str(tmp)]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
-    os.replace(tmp, OUT)
-    return OUT
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

@@ -10,10 +10,36 @@
 
 namespace spk {
 
+// Build-time tunables of the pair sweeps (defaults are the tuned values).
+#ifndef SPK_SWEEP_BLOCK
+#define SPK_SWEEP_BLOCK 256
+#endif
+#ifndef SPK_SAMPLE_TILE
+#define SPK_SAMPLE_TILE 512
+#endif
+#ifndef SPK_TARGETS_F32
+#define SPK_TARGETS_F32 4
+#endif
+#ifndef SPK_TARGETS_F64
+#define SPK_TARGETS_F64 2
+#endif
+#ifndef SPK_SOURCE_UNROLL
+#define SPK_SOURCE_UNROLL 4
+#endif
+// Minimum waves per SIMD the FP32-accumulating sweeps are compiled for (caps
+// VGPRs at 512/waves); 1 leaves the choice to the compiler.  Sweeps with FP64
+// accumulators are not capped.
+#ifndef SPK_SWEEP_WAVES_F32
+#define SPK_SWEEP_WAVES_F32 1
+#endif
+
 // Threads per block of the pair sweeps.
-constexpr int kSweepBlock = 256;
+constexpr int kSweepBlock = SPK_SWEEP_BLOCK;
 // Sources staged in LDS per tile by the sample sweep.
-constexpr int kSampleTile = 512;
+constexpr int kSampleTile = SPK_SAMPLE_TILE;
+// Targets per lane (register blocking) of the FP32 forms and of plain FP64.
+constexpr int kTargetsF32 = SPK_TARGETS_F32;
+constexpr int kTargetsF64 = SPK_TARGETS_F64;
 // Density cells staged in LDS per tile by the cell sweep (rows of G cells).
 constexpr int kCellTileF32 = 2048;
 constexpr int kCellTileF64 = 1024;

@@ -47,7 +47,8 @@ template <int MODE> struct ModeT {
 template <> struct ModeT<kPlain64> { using T = double; using A = double; };
 template <> struct ModeT<kAcc64> { using T = float; using A = double; };
 
-template <int MODE> constexpr int lanes_targets() { return MODE == kPlain64 ? 2 : 4; }
+template <int MODE> constexpr int lanes_targets() { return MODE == kPlain64 ? kTargetsF64 : kTargetsF32; }
+template <int MODE> constexpr int min_waves() { return MODE == kComp || MODE == kNaive ? SPK_SWEEP_WAVES_F32 : 1; }
 
 template <typename T> struct alignas(4 * sizeof(T)) P4 { T x, y, z, w; };
 template <typename T> struct alignas(2 * sizeof(T)) P2 { T x, y; };
@@ -113,7 +114,8 @@ __device__ inline void acc_fma(Acc<MODE> &a, T w, T d)
 }
 
 template <int MODE, int R, bool ENERGY>
-__global__ __launch_bounds__(BLK) void sweep_samples_kernel(SweepLaunch l)
+__global__ __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(min_waves<MODE>())))
+void sweep_samples_kernel(SweepLaunch l)
 {
     using T = typename ModeT<MODE>::T;
     __shared__ P4<T> tile[kSampleTile];
@@ -161,7 +163,7 @@ __global__ __launch_bounds__(BLK) void sweep_samples_kernel(SweepLaunch l)
             }
         };
         if (n == kSampleTile) {
-#pragma unroll 4
+#pragma unroll SPK_SOURCE_UNROLL
             for (int j = 0; j < kSampleTile; ++j)
                 pair(tile[j]);
         } else {
@@ -194,12 +196,12 @@ __global__ __launch_bounds__(BLK) void sweep_samples_kernel(SweepLaunch l)
 }
 
 template <int MODE, int R, bool ENERGY>
-__global__ __launch_bounds__(BLK) void sweep_cells_kernel(SweepLaunch l)
+__global__ __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(min_waves<MODE>())))
+void sweep_cells_kernel(SweepLaunch l)
 {
     using T = typename ModeT<MODE>::T;
     constexpr int TILE = MODE == kPlain64 ? kCellTileF64 : kCellTileF32;
     __shared__ P2<T> cell[TILE];     // (x_v, rho_v) of the tile's cells, row after row
-    __shared__ P2<T> rowyz[TILE];    // (y, z) of each row of the tile
 
     const T *tx = static_cast<const T *>(l.tx), *ty = static_cast<const T *>(l.ty),
             *tz = static_cast<const T *>(l.tz);
@@ -226,6 +228,8 @@ __global__ __launch_bounds__(BLK) void sweep_cells_kernel(SweepLaunch l)
     const int64_t lo = l.src_begin + (int64_t)blockIdx.y * l.slab;
     int64_t hi = lo + l.slab;
     hi = hi < l.src_end ? hi : l.src_end;
+    // row = iy + G*iz; the (iy, iz) counters advance with the rows (wave-uniform)
+    int64_t iy = lo % G, iz = lo / G;
 
     for (int64_t base = lo; base < hi; base += rows_per_tile) {
         const int nr = (int)((hi - base) < rows_per_tile ? (hi - base) : rows_per_tile);
@@ -234,14 +238,14 @@ __global__ __launch_bounds__(BLK) void sweep_cells_kernel(SweepLaunch l)
             const int ix = j % g;
             cell[j] = P2<T>{(T)cell_centre(ix, G, L), rho[base * G + j]};
         }
-        for (int j = threadIdx.x; j < nr; j += BLK) {
-            const int64_t row = base + j;
-            rowyz[j] = P2<T>{(T)cell_centre(row % G, G, L), (T)cell_centre(row / G, G, L)};
-        }
         __syncthreads();
 
         for (int rr = 0; rr < nr; ++rr) {
-            const P2<T> yz = rowyz[rr];
+            const P2<T> yz{(T)cell_centre(iy, G, L), (T)cell_centre(iz, G, L)};
+            if (++iy == G) {
+                iy = 0;
+                ++iz;
+            }
             T dy[R], dz[R], c[R];
             typename ModeT<MODE>::A wrow[R];
 #pragma unroll
