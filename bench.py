@@ -81,6 +81,9 @@ def main():
                     help="approximate CPU time budget of the oracle baseline (0 = skip)")
     ap.add_argument("--fp64-fraction", type=float, default=1.0 / 16,
                     help="fraction of targets of the plain-FP64 comparison run (0 = skip)")
+    ap.add_argument("--attraction", choices=["direct", "field"], default="direct",
+                    help="attraction by the direct sum over the density cells (default) or by "
+                         "trilinear interpolation of a precomputed node field")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed region, run a plain 1 GiB device copy three times "
                          "(reference dispatches for HBM byte counters)")
@@ -112,6 +115,14 @@ def main():
     rho = torch.tensor(rho_host, dtype=prm.dtype, device=dev)
     state = spk.StepState(prm, dev)
     spk.workspace(prm, dev)
+    field_s = None
+    if args.attraction == "field":
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        prm.attraction_field = spk.attraction_field(rho, prm)
+        torch.cuda.synchronize()
+        field_s = time.perf_counter() - t0
+        log(f"node field precomputed in {field_s:.2f} s")
 
     # code-object load and first-launch costs, on a tiny problem in another
     # precision form (not a step; keeps the timed kernels' launch counts clean)
@@ -145,11 +156,12 @@ def main():
 
     kern = {}
     for name, kind in (("repulsion", spk.KIND_REPULSION), ("attraction", spk.KIND_ATTRACTION),
-                       ("projection", spk.KIND_PROJECTION), ("other", spk.KIND_OTHER)):
+                       ("projection", spk.KIND_PROJECTION), ("other", spk.KIND_OTHER),
+                       ("interpolation", spk.KIND_INTERPOLATION)):
         ms, n, pairs = spk.timing_query(kind)
         kern[name] = {"ms": ms, "launches": n, "pairs": pairs}
 
-    pairs_per_step = float(p) * p + float(p) * M
+    pairs_per_step = float(p) * p + (float(p) * M if args.attraction == "direct" else 0.0)
     ms_per_step = 1e3 * elapsed / args.steps
     value = pairs_per_step * args.steps / elapsed
 
@@ -160,7 +172,7 @@ def main():
     att = kern["attraction"]
     att_tflops = (FLOP_PER_PAIR_ATTRACTION * att["pairs"] / (att["ms"] * 1e-3) / 1e12
                   if att["ms"] > 0 else None)
-    grad_ms = (rep["ms"] + att["ms"] + kern["other"]["ms"]) / args.steps
+    grad_ms = (rep["ms"] + att["ms"] + kern["interpolation"]["ms"] + kern["other"]["ms"]) / args.steps
 
     result = {
         "metric": "pair-interactions/s & sec per gradient eval at 8.4M samples, FP32-comp vs FP64",
@@ -177,7 +189,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "n_shots": w.n_shots, "n_samples": w.n_samples, "p": p,
                    "grid": w.grid, "precision": precision, "n_pit": w.n_pit,
-                   "pairs_per_step": pairs_per_step},
+                   "attraction": args.attraction, "pairs_per_step": pairs_per_step},
         "s_per_grad_eval": grad_ms / 1e3,
         "kernels": {
             "repulsion": {"ms_per_step": rep["ms"] / args.steps, "launches_per_step":
@@ -187,6 +199,8 @@ def main():
                            att["launches"] / args.steps,
                            "pairs_per_s": att["pairs"] / (att["ms"] * 1e-3) if att["ms"] else None,
                            "tflops": att_tflops},
+            "interpolation_ms_per_step": kern["interpolation"]["ms"] / args.steps,
+            "field_precompute_s": field_s,
             "projection_ms_per_step": kern["projection"]["ms"] / args.steps,
             "other_ms_per_step": kern["other"]["ms"] / args.steps,
         },
@@ -206,11 +220,12 @@ def main():
         result["copy_calibration_bytes"] = {"read": src.numel() * 4, "write": dst.numel() * 4}
         del src, dst
 
-    if args.fp64_fraction > 0 and precision != "plain_fp64":
+    if args.fp64_fraction > 0 and precision != "plain_fp64" and args.attraction == "direct":
         result["fp64_plain"] = fp64_comparison(spk, torch, w, prm, K, rho, args.fp64_fraction, dev)
 
     if args.cpu_seconds > 0:
-        result["cpu_baseline"] = cpu_baseline(w, K, rho, args.cpu_seconds)
+        result["cpu_baseline"] = cpu_baseline(w, K, rho, args.cpu_seconds,
+                                              field=args.attraction == "field")
 
     print(json.dumps(result), flush=True)
 
@@ -252,30 +267,38 @@ def fp64_comparison(spk, torch, w, prm, K, rho, fraction, dev):
             "fp32_comp_rel_l2_vs_fp64": d}
 
 
-def cpu_baseline(w, K, rho, seconds):
-    """The FP64 oracle on a bounded sample of targets (all sources each)."""
+def cpu_baseline(w, K, rho, seconds, field=False):
+    """The FP64 oracle on a bounded sample of targets (all sources each).
+
+    With field=True the oracle's grid attraction is timed instead (the 8
+    surrounding nodes of each target summed over all cells, then the
+    trilinear interpolant), and the rate counts the pair interactions the
+    step itself performs per target (p, the repulsion)."""
     import oracle
     from paper_2108_02991_amd import inputs
 
     Kh = K.detach().cpu().double().numpy()
     rh = rho.detach().cpu().double().numpy()
     p = Kh.shape[1]
-    per_target = p + w.n_voxels
-    probe = inputs.sample_targets(p, 8, seed=99)
+    fn = oracle.grad_field if field else oracle.grad
+    per_target = p + (8 if field else 1) * w.n_voxels
+    credited = p if field else p + w.n_voxels
+    probe = inputs.sample_targets(p, 4, seed=99)
     t0 = time.perf_counter()
-    oracle.grad(Kh, rh, w.grid, w.half_width, 0.0, probe)
+    fn(Kh, rh, w.grid, w.half_width, 0.0, probe)
     rate = probe.size * per_target / (time.perf_counter() - t0)
     n = int(max(16, min(4096, seconds * rate / per_target)))
     targets = inputs.sample_targets(p, n, seed=100)
     log(f"cpu baseline: oracle on {targets.size} targets ({oracle.num_threads()} threads)")
     t0 = time.perf_counter()
-    oracle.grad(Kh, rh, w.grid, w.half_width, 0.0, targets)
+    fn(Kh, rh, w.grid, w.half_width, 0.0, targets)
     dt = time.perf_counter() - t0
-    pairs = float(targets.size) * per_target
+    pairs = float(targets.size) * credited
+    what = ("the grid attraction of 8 nodes x all cells" if field else f"all {w.n_voxels} cells")
     return {"value": pairs / dt, "unit": "pair-interactions/s", "cores": oracle.num_threads(),
             "kind": "oracle", "sample": f"{targets.size} random targets of {w.name}, each against "
-            f"all {p} samples and {w.n_voxels} cells (FP64, compensated sums), {dt:.1f} s",
-            "s_per_grad_eval_extrapolated": float(p) * per_target / (pairs / dt)}
+            f"all {p} samples and {what} (FP64, compensated sums), {dt:.1f} s",
+            "s_per_grad_eval_extrapolated": float(p) * dt / targets.size}
 
 
 if __name__ == "__main__":

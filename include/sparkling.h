@@ -91,6 +91,9 @@ typedef struct {
     double  b_max;        /* per-raster-step slew bound (spk_alpha_beta), > 0           */
     int32_t n_pit;        /* projection iterations, >= 0                                */
     int32_t flags;        /* SPK_FLAG_*                                                 */
+    const void *attraction_field; /* NULL: attraction summed directly over the G^3
+                                     cells; else the node field of sparkling_field(),
+                                     evaluated by trilinear interpolation            */
 } spk_params;
 
 /* Text of a status code (static storage). */
@@ -128,6 +131,24 @@ int spk_workspace_size(const spk_params *prm, size_t *bytes);
  */
 int sparkling_energy(const spk_params *prm, const void *kx, const void *ky, const void *kz,
                      const void *rho, double out[4], void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Node field of the grid attraction (Sec. "Evaluating F^a and its gradient":
+ * the discrete convolution of the sampled kernel with the sampled density,
+ * computed once per density and evaluated off the grid by the trilinear
+ * interpolant).  Nodes sit at X_k = -L + (k - 1/2) * 2L/G, k = 0..G+1, per
+ * axis (the cell centres plus one node beyond each face), node
+ * n = kx + (G+2)*(ky + (G+2)*kz).  field (device, K's type, 16-byte aligned
+ * for float, 32 for double) receives 4*(G+2)^3 values laid out
+ * [n][U, dU/dx, dU/dy, dU/dz] with U(x) = sum_v rho_v H(x - x_v), summed
+ * directly over the cells in the precision form of prm.  Setting
+ * prm->attraction_field to this buffer makes energy, gradient and step use
+ * the interpolant for the attraction (valid for samples inside
+ * [-L - h/2, L + h/2]^3; outside, the nearest node layer is extrapolated
+ * linearly).  prm->attraction_field is ignored by this call.
+ */
+int sparkling_field(const spk_params *prm, const void *rho, void *field, void *ws,
+                    size_t ws_bytes, void *stream);
 
 /*
  * Gradient of F (Secs. "Evaluating F^a and its gradient", "Evaluating F^r
@@ -208,7 +229,8 @@ enum {
     SPK_KIND_REPULSION = 0,   /* all-pairs sample sweep                   */
     SPK_KIND_ATTRACTION = 1,  /* sample x density-cell sweep              */
     SPK_KIND_PROJECTION = 2,  /* per-shot projection                      */
-    SPK_KIND_OTHER = 3        /* reductions, combine, step, check         */
+    SPK_KIND_OTHER = 3,       /* reductions, combine, step, check         */
+    SPK_KIND_INTERPOLATION = 4 /* grid-attraction interpolant              */
 };
 int spk_timing_enable(int on);
 int spk_timing_query(int kind, double *total_ms, int64_t *launches, double *pairs);

@@ -57,6 +57,9 @@ def _load():
                          _p, _p, _i64, _dbl, _p],
             "orc_fd_directional": [_i64, _p, _p, _p, _i64, _dbl, _p, _dbl, _p, _dbl, _p],
             "orc_num_threads": [],
+            "orc_field": [_i64, _dbl, _p, _dbl, _p],
+            "orc_interpolate": [_i64, _dbl, _p, _i64, _p, _p, _p, _p],
+            "orc_grad_field": [_i64, _p, _p, _p, _i64, _dbl, _p, _dbl, _i64, _p, _p, _p, _p, _p, _p],
         }.items():
             f = getattr(lib, name)
             f.argtypes = args
@@ -178,3 +181,41 @@ def fd_directional(K, rho, G, L, delta, h, eps: float = 0.0) -> float:
                                     eps, _ptr(delta), h, _ptr(out))
     _check(rc, "fd_directional")
     return float(out[0])
+
+
+def field(rho, G: int, L: float, eps: float = 0.0) -> np.ndarray:
+    """Node field of the grid attraction, shape ((G+2)^3, 4): U, dU/dx, dU/dy, dU/dz."""
+    rho = _f64(rho)
+    out = np.empty(((G + 2) ** 3, 4))
+    _check(_load().orc_field(G, L, _ptr(rho), eps, _ptr(out)), "field")
+    return out
+
+
+def interpolate(node_field, G: int, L: float, P) -> np.ndarray:
+    """Trilinear interpolant of a ((G+2)^3, 4) node field at points P (3, n) -> (4, n)."""
+    f = _f64(node_field)
+    P = _f64(P)
+    n = P.shape[1]
+    out = np.empty((4, n))
+    x, y, z = (np.ascontiguousarray(P[c]) for c in range(3))
+    _check(_load().orc_interpolate(G, L, _ptr(f), n, _ptr(x), _ptr(y), _ptr(z), _ptr(out)),
+           "interpolate")
+    return out
+
+
+def grad_field(K, rho, G: int, L: float, eps: float = 0.0, targets=None):
+    """Gradient with the grid attraction (node field + trilinear interpolant) at targets."""
+    K = _f64(K)
+    rho = _f64(rho)
+    p = K.shape[1]
+    if targets is None:
+        targets = np.arange(p, dtype=np.int64)
+    targets = np.ascontiguousarray(np.asarray(targets, dtype=np.int64))
+    n_t = targets.size
+    dF, dFa, dFr = (np.empty((3, n_t)) for _ in range(3))
+    ua, ur = np.empty(n_t), np.empty(n_t)
+    x, y, z = (np.ascontiguousarray(K[c]) for c in range(3))
+    rc = _load().orc_grad_field(p, _ptr(x), _ptr(y), _ptr(z), G, L, _ptr(rho), eps, n_t,
+                                _ptr(targets), _ptr(dF), _ptr(dFa), _ptr(dFr), _ptr(ua), _ptr(ur))
+    _check(rc, "grad_field")
+    return {"dF": dF, "dFa": dFa, "dFr": dFr, "ua": ua, "ur": ur, "targets": targets}

@@ -610,6 +610,173 @@ int orc_fd_directional(int64_t p, const double *kx, const double *ky, const doub
     return 0;
 }
 
+/* ------------------------------------------------------------------ */
+/* Grid attraction (Sec. "Evaluating F^a and its gradient"): the        */
+/* potential U(x) = sum_v rho_v H(x - x_v) and the field                 */
+/* dU(x) = sum_v rho_v grad H(x - x_v) are sampled once on a node grid   */
+/* (the discrete convolution of the sampled kernel with the sampled      */
+/* density) and evaluated off the grid by the trilinear interpolant.     */
+/* The node grid extends the cell centres by one node on each side:      */
+/* X_k = -L + (k - 1/2) h, k = 0..G+1, h = 2L/G, so every point of       */
+/* [-L, L]^3 lies inside it.  Node (kx, ky, kz) has index                */
+/* kx + (G+2)(ky + (G+2) kz).                                            */
+/* ------------------------------------------------------------------ */
+static double node_coord(int64_t k, int64_t G, double L)
+{
+    return -L + ((double)k - 0.5) * (2.0 * L / (double)G);
+}
+
+/* U and dU at one point by direct summation over the G^3 cells. */
+static void attraction_at(double x, double y, double z, int64_t G, double L, const double *rho,
+                          double eps, double out[4])
+{
+    csum u = {0, 0}, d[3] = {{0, 0}, {0, 0}, {0, 0}};
+    double g[3];
+    for (int64_t iz = 0; iz < G; ++iz)
+        for (int64_t iy = 0; iy < G; ++iy)
+            for (int64_t ix = 0; ix < G; ++ix) {
+                double w = rho[ix + G * (iy + G * iz)];
+                double dx = x - cell_centre(ix, G, L), dy = y - cell_centre(iy, G, L),
+                       dz = z - cell_centre(iz, G, L);
+                cs_add(&u, w * kernel_h(dx, dy, dz, eps));
+                kernel_grad(dx, dy, dz, eps, g);
+                for (int c = 0; c < 3; ++c)
+                    cs_add(&d[c], w * g[c]);
+            }
+    out[0] = cs_get(&u);
+    for (int c = 0; c < 3; ++c)
+        out[1 + c] = cs_get(&d[c]);
+}
+
+/* Field at every node of the extended grid: out[(node)*4 + {U, Ux, Uy, Uz}]. */
+int orc_field(int64_t G, double L, const double *rho, double eps, double *out)
+{
+    if (G < 1 || !rho || !out || eps < 0.0)
+        return -1;
+    int64_t Gn = G + 2, Mn = Gn * Gn * Gn;
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t n = 0; n < Mn; ++n) {
+        int64_t kx = n % Gn, ky = (n / Gn) % Gn, kz = n / (Gn * Gn);
+        attraction_at(node_coord(kx, G, L), node_coord(ky, G, L), node_coord(kz, G, L), G, L,
+                      rho, eps, out + 4 * n);
+    }
+    return 0;
+}
+
+/* Lower node index and weight of the upper node along one axis:
+ * t = (x - X_0)/h, k0 = floor(t) clamped to [0, G], f = t - k0. */
+static void axis_weight(double x, int64_t G, double L, int64_t *k0, double *f)
+{
+    double h = 2.0 * L / (double)G;
+    double t = (x - node_coord(0, G, L)) / h;
+    double k = floor(t);
+    if (!(k >= 0.0)) k = 0.0;          /* NaN and -inf: node 0, the weight carries it */
+    if (k > (double)G) k = (double)G;
+    *k0 = (int64_t)k;
+    *f = t - k;
+}
+
+/* Trilinear interpolant of the 4 node fields at one point (x fastest). */
+static void trilinear(const double *field, int64_t G, double L, double x, double y, double z,
+                      double out[4])
+{
+    int64_t Gn = G + 2, k[3];
+    double f[3];
+    axis_weight(x, G, L, &k[0], &f[0]);
+    axis_weight(y, G, L, &k[1], &f[1]);
+    axis_weight(z, G, L, &k[2], &f[2]);
+    for (int c = 0; c < 4; ++c)
+        out[c] = 0.0;
+    for (int dz = 0; dz < 2; ++dz)
+        for (int dy = 0; dy < 2; ++dy)
+            for (int dx = 0; dx < 2; ++dx) {
+                double w = (dx ? f[0] : 1.0 - f[0]) * (dy ? f[1] : 1.0 - f[1]) *
+                           (dz ? f[2] : 1.0 - f[2]);
+                int64_t n = (k[0] + dx) + Gn * ((k[1] + dy) + Gn * (k[2] + dz));
+                for (int c = 0; c < 4; ++c)
+                    out[c] += w * field[4 * n + c];
+            }
+}
+
+/* Trilinear interpolation of a given node field at n points (out [4][n]). */
+int orc_interpolate(int64_t G, double L, const double *field, int64_t n, const double *px,
+                    const double *py, const double *pz, double *out)
+{
+    if (G < 1 || !field || n < 0 || !px || !py || !pz || !out)
+        return -1;
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        double v[4];
+        trilinear(field, G, L, px[i], py[i], pz[i], v);
+        for (int c = 0; c < 4; ++c)
+            out[c * n + i] = v[c];
+    }
+    return 0;
+}
+
+/*
+ * Gradient with the grid attraction at a list of targets: the attraction of
+ * target i is the trilinear interpolant of the node field (each of the 8
+ * surrounding nodes summed directly over the G^3 cells), the repulsion is
+ * the all-pairs sum.  Outputs as orc_grad (ua = interpolated potential).
+ */
+int orc_grad_field(int64_t p, const double *kx, const double *ky, const double *kz,
+                   int64_t G, double L, const double *rho, double eps,
+                   int64_t n_t, const int64_t *targets,
+                   double *dF, double *dFa, double *dFr, double *ua, double *ur)
+{
+    if (p < 1 || G < 1 || n_t < 0 || !kx || !ky || !kz || !rho || !targets || eps < 0.0)
+        return -1;
+    for (int64_t t = 0; t < n_t; ++t)
+        if (targets[t] < 0 || targets[t] >= p)
+            return -1;
+    double inv_p = 1.0 / (double)p;
+    double inv_p2 = inv_p * inv_p;
+    int64_t Gn = G + 2;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t t = 0; t < n_t; ++t) {
+        int64_t i = targets[t], k[3];
+        double f[3], att[4] = {0, 0, 0, 0};
+        axis_weight(kx[i], G, L, &k[0], &f[0]);
+        axis_weight(ky[i], G, L, &k[1], &f[1]);
+        axis_weight(kz[i], G, L, &k[2], &f[2]);
+        double local[8 * 4];
+        for (int dz = 0; dz < 2; ++dz)
+            for (int dy = 0; dy < 2; ++dy)
+                for (int dx = 0; dx < 2; ++dx)
+                    attraction_at(node_coord(k[0] + dx, G, L), node_coord(k[1] + dy, G, L),
+                                  node_coord(k[2] + dz, G, L), G, L, rho, eps,
+                                  local + 4 * (dx + 2 * (dy + 2 * dz)));
+        for (int dz = 0; dz < 2; ++dz)
+            for (int dy = 0; dy < 2; ++dy)
+                for (int dx = 0; dx < 2; ++dx) {
+                    double w = (dx ? f[0] : 1.0 - f[0]) * (dy ? f[1] : 1.0 - f[1]) *
+                               (dz ? f[2] : 1.0 - f[2]);
+                    for (int c = 0; c < 4; ++c)
+                        att[c] += w * local[4 * (dx + 2 * (dy + 2 * dz)) + c];
+                }
+        (void)Gn;
+        csum sr = {0, 0}, r3[3] = {{0, 0}, {0, 0}, {0, 0}};
+        double g[3];
+        for (int64_t j = 0; j < p; ++j) {
+            double dx = kx[i] - kx[j], dy = ky[i] - ky[j], dz = kz[i] - kz[j];
+            cs_add(&sr, kernel_h(dx, dy, dz, eps));
+            kernel_grad(dx, dy, dz, eps, g);
+            for (int c = 0; c < 3; ++c)
+                cs_add(&r3[c], g[c]);
+        }
+        for (int c = 0; c < 3; ++c) {
+            double fa = att[1 + c] * inv_p, fr = cs_get(&r3[c]) * inv_p2;
+            if (dFa) dFa[c * n_t + t] = fa;
+            if (dFr) dFr[c * n_t + t] = fr;
+            if (dF) dF[c * n_t + t] = fa - fr;
+        }
+        if (ua) ua[t] = att[0];
+        if (ur) ur[t] = cs_get(&sr);
+    }
+    return 0;
+}
+
 int orc_num_threads(void)
 {
 #ifdef _OPENMP

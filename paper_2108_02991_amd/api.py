@@ -19,7 +19,7 @@ LIB_PATH = _PKG / "libsparkling.so"
 
 PRECISIONS = {"plain_fp64": 0, "fp32_comp": 1, "fp32_naive": 2, "fp32_acc64": 3}
 FLAG_DISCREPANCY = 1
-KIND_REPULSION, KIND_ATTRACTION, KIND_PROJECTION, KIND_OTHER = 0, 1, 2, 3
+KIND_REPULSION, KIND_ATTRACTION, KIND_PROJECTION, KIND_OTHER, KIND_INTERPOLATION = 0, 1, 2, 3, 4
 
 _i32, _i64, _dbl, _vp, _sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p, ctypes.c_size_t
 
@@ -27,7 +27,7 @@ _i32, _i64, _dbl, _vp, _sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ct
 class SpkParams(ctypes.Structure):
     _fields_ = [("n_shots", _i64), ("n_samples", _i64), ("grid", _i64), ("precision", _i32),
                 ("te_index", _i32), ("half_width", _dbl), ("eps", _dbl), ("a_max", _dbl),
-                ("b_max", _dbl), ("n_pit", _i32), ("flags", _i32)]
+                ("b_max", _dbl), ("n_pit", _i32), ("flags", _i32), ("attraction_field", _vp)]
 
 
 class SpkStepInfo(ctypes.Structure):
@@ -59,6 +59,7 @@ def load_library(path: Path | str | None = None):
         "spk_alpha_beta": ([_dbl] * 8 + [_vp, _vp], ctypes.c_int),
         "spk_workspace_size": ([_vp, _vp], ctypes.c_int),
         "sparkling_energy": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp], ctypes.c_int),
+        "sparkling_field": ([_vp, _vp, _vp, _vp, _sz, _vp], ctypes.c_int),
         "sparkling_grad": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _i64, _vp, _vp, _vp,
                             _vp, _sz, _vp], ctypes.c_int),
         "sparkling_project": ([_vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp], ctypes.c_int),
@@ -97,6 +98,7 @@ class Params:
     te_index: int = 0
     n_pit: int = 200
     discrepancy: bool = False
+    attraction_field: "torch.Tensor | None" = None   # from attraction_field(); None = direct sum
     _c: SpkParams = field(default=None, repr=False, compare=False)
 
     @property
@@ -108,9 +110,15 @@ class Params:
         return torch.float64 if self.precision == "plain_fp64" else torch.float32
 
     def c(self) -> SpkParams:
+        f = self.attraction_field
+        if f is not None and (not f.is_cuda or f.dtype != self.dtype or not f.is_contiguous()
+                              or f.numel() != 4 * (self.grid + 2) ** 3):
+            raise ValueError("attraction_field must be a contiguous device tensor of "
+                             f"4*(G+2)^3 {self.dtype} values")
         return SpkParams(self.n_shots, self.n_samples, self.grid, PRECISIONS[self.precision],
                          self.te_index, self.half_width, self.eps, self.a_max, self.b_max,
-                         self.n_pit, FLAG_DISCREPANCY if self.discrepancy else 0)
+                         self.n_pit, FLAG_DISCREPANCY if self.discrepancy else 0,
+                         _vp(f.data_ptr()) if f is not None else None)
 
 
 def alpha_beta(gmax, smax, raster_dt, dwell_dt, fov, kmax, gamma_bar, half_width):
@@ -164,6 +172,22 @@ def _check_rho(rho: torch.Tensor, prm: Params):
 
 def _rows(K: torch.Tensor):
     return [_vp(K[c].data_ptr()) for c in range(3)]
+
+
+def attraction_field(rho: torch.Tensor, prm: Params) -> torch.Tensor:
+    """Node field of the grid attraction, a ((G+2)^3, 4) tensor of rho's dtype.
+
+    Assign it to prm.attraction_field to evaluate the attraction by trilinear
+    interpolation instead of the direct sum over the cells.
+    """
+    _check_rho(rho, prm)
+    out = torch.empty(((prm.grid + 2) ** 3, 4), dtype=prm.dtype, device=rho.device)
+    ws = workspace(prm, rho.device)
+    c = prm.c()
+    _check(load_library().sparkling_field(ctypes.byref(c), _vp(rho.data_ptr()),
+                                          _vp(out.data_ptr()), _vp(ws.data_ptr()), ws.numel(),
+                                          _stream(rho)), "sparkling_field")
+    return out
 
 
 def energy(K: torch.Tensor, rho: torch.Tensor, prm: Params):

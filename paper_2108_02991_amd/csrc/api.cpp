@@ -55,9 +55,10 @@ struct TimedLaunch {
 std::mutex g_tmu;
 bool g_timing = false;
 std::vector<TimedLaunch> g_pending;
-double g_ms[4] = {0, 0, 0, 0};
-int64_t g_launches[4] = {0, 0, 0, 0};
-double g_pairs[4] = {0, 0, 0, 0};
+constexpr int kKinds = 5;
+double g_ms[kKinds] = {};
+int64_t g_launches[kKinds] = {};
+double g_pairs[kKinds] = {};
 
 // Brackets one launch with events when timing is on.
 class Timed {
@@ -116,6 +117,10 @@ int check_params(const spk_params *prm, bool need_projection)
         return fail(SPK_EINVAL, "te_index must be -1 or in [0, n_samples)");
     if (prm->flags & ~SPK_FLAG_DISCREPANCY)
         return fail(SPK_EINVAL, "unknown flags 0x%x", prm->flags);
+    if (prm->attraction_field &&
+        reinterpret_cast<uintptr_t>(prm->attraction_field) % (4 * elt_size(prm->precision)))
+        return fail(SPK_EINVAL, "attraction_field is not %zu-byte aligned",
+                    4 * elt_size(prm->precision));
     if (need_projection) {
         if (prm->n_samples < 2)
             return fail(SPK_EINVAL, "projection needs n_samples >= 2");
@@ -188,16 +193,21 @@ struct Layout {
 
 size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
+int64_t field_nodes(int64_t G) { return (G + 2) * (G + 2) * (G + 2); }
+
 Layout make_layout(const spk_params *prm)
 {
     Layout L;
     const int64_t p = prm->n_shots * prm->n_samples;
-    const int64_t G = prm->grid, M = G * G * G;
+    const int64_t G = prm->grid, M = G * G * G, Mn = field_nodes(G);
     const bool disc = prm->flags & SPK_FLAG_DISCREPANCY;
-    const int64_t nt = disc ? std::max(p, M) : p;
+    // targets of one sweep: the samples, or the nodes of the field precompute
+    // (which also covers the cell centres of the self-energy, M < Mn)
+    const int64_t nt = std::max(p, Mn);
     const Plan pr = make_plan(prm->precision, false, p, p, G);
     const Plan pa = make_plan(prm->precision, true, p, G * G, G);
     int64_t pl = std::max(pr.per_launch, pa.per_launch);
+    pl = std::max(pl, make_plan(prm->precision, true, Mn, G * G, G).per_launch);
     if (disc)
         pl = std::max(pl, make_plan(prm->precision, true, M, G * G, G).per_launch);
     size_t off = 0;
@@ -214,7 +224,7 @@ Layout make_layout(const spk_params *prm)
     L.scal = take(sizeof(double) * 16);
     L.grad = take(elt_size(prm->precision) * 3 * p);
     L.viol = take(sizeof(double) * 4 * prm->n_shots);
-    L.cells = disc ? take(elt_size(prm->precision) * 3 * M) : off;
+    L.cells = take(elt_size(prm->precision) * 3 * Mn);
     L.total = off + 256;   // slack for aligning the caller's base pointer
     return L;
 }
@@ -304,6 +314,13 @@ int run_gradient_sums(const spk_params *prm, const void *kx, const void *ky, con
                        w.acc_r(), s);
     if (rc)
         return rc;
+    if (prm->attraction_field) {
+        Timed tm(SPK_KIND_INTERPOLATION, (double)nt, s);
+        SPK_HIP(launch_interpolate(prm->precision, kx, ky, kz, t0, nt, prm->grid, prm->half_width,
+                                   prm->attraction_field, w.acc_a(), w.L.ld, s),
+                "field interpolation");
+        return SPK_OK;
+    }
     return run_sweep(prm, true, kx, ky, kz, t0, nt, p, nullptr, nullptr, nullptr, rho, energy, w,
                      w.acc_a(), s);
 }
@@ -466,6 +483,38 @@ int sparkling_grad(const spk_params *prm, const void *kx, const void *ky, const 
     return SPK_OK;
 }
 
+int sparkling_field(const spk_params *prm, const void *rho, void *field, void *ws,
+                    size_t ws_bytes, void *stream)
+{
+    g_err.clear();
+    int rc = check_params(prm, false);
+    if (rc)
+        return rc;
+    const size_t al = elt_size(prm->precision);
+    if ((rc = check_ptr(rho, "rho", al)) || (rc = check_ptr(field, "field", 4 * al)))
+        return rc;
+    Ws w;
+    if ((rc = bind_ws(prm, ws, ws_bytes, &w)))
+        return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int64_t G = prm->grid, Mn = field_nodes(G);
+    char *pts = static_cast<char *>(w.cells());
+    void *nx = pts, *ny = pts + al * Mn, *nz = pts + 2 * al * Mn;
+    {
+        Timed tm(SPK_KIND_OTHER, 0.0, s);
+        SPK_HIP(launch_node_coords(prm->precision, G, prm->half_width, nx, ny, nz, s),
+                "node coordinates");
+    }
+    spk_params direct = *prm;
+    direct.attraction_field = nullptr;
+    if ((rc = run_sweep(&direct, true, nx, ny, nz, 0, Mn, Mn, nullptr, nullptr, nullptr, rho, true,
+                        w, w.acc_a(), s)))
+        return rc;
+    Timed tm(SPK_KIND_OTHER, 0.0, s);
+    SPK_HIP(launch_field_pack(prm->precision, w.acc_a(), w.L.ld, Mn, field, s), "field pack");
+    return SPK_OK;
+}
+
 int sparkling_energy(const spk_params *prm, const void *kx, const void *ky, const void *kz,
                      const void *rho, double out[4], void *ws, size_t ws_bytes, void *stream)
 {
@@ -499,8 +548,10 @@ int sparkling_energy(const spk_params *prm, const void *kx, const void *ky, cons
             SPK_HIP(launch_cell_centres(prm->precision, G, prm->half_width, cx, cy, cz, s),
                     "cell centres");
         }
-        if ((rc = run_sweep(prm, true, cx, cy, cz, 0, M, M, nullptr, nullptr, nullptr, rho, true,
-                            w, w.acc_a(), s)))
+        spk_params direct = *prm;
+        direct.attraction_field = nullptr;
+        if ((rc = run_sweep(&direct, true, cx, cy, cz, 0, M, M, nullptr, nullptr, nullptr, rho,
+                            true, w, w.acc_a(), s)))
             return rc;
         Timed tm(SPK_KIND_OTHER, 0.0, s);
         SPK_HIP(launch_wsum(rho, prm->precision, w.acc_a() + 3 * w.L.ld, M, w.red(),
@@ -651,7 +702,7 @@ int spk_timing_enable(int on)
 
 int spk_timing_query(int kind, double *total_ms, int64_t *launches, double *pairs)
 {
-    if (kind < 0 || kind > 3)
+    if (kind < 0 || kind >= kKinds)
         return fail(SPK_EINVAL, "unknown timing kind %d", kind);
     std::lock_guard<std::mutex> lk(g_tmu);
     for (const TimedLaunch &t : g_pending) {
@@ -683,7 +734,7 @@ int spk_timing_reset(void)
         hipEventDestroy(t.b);
     }
     g_pending.clear();
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < kKinds; ++k) {
         g_ms[k] = 0;
         g_launches[k] = 0;
         g_pairs[k] = 0;

@@ -99,6 +99,17 @@ hipError_t launch_wsum(const void *w, int precision, const double *x, int64_t n,
 hipError_t launch_cell_centres(int precision, int64_t G, double L, void *cx, void *cy, void *cz,
                                hipStream_t s);
 
+// Grid attraction: node coordinates (G+2 per axis), packing of node sums into
+// the [n][4] field, and the trilinear interpolant writing the four attraction
+// sums of targets [t0, t0+nt) into acc rows (like a cell sweep would).
+hipError_t launch_node_coords(int precision, int64_t G, double L, void *nx, void *ny, void *nz,
+                              hipStream_t s);
+hipError_t launch_field_pack(int precision, const double *acc, int64_t ld, int64_t Mn, void *field,
+                             hipStream_t s);
+hipError_t launch_interpolate(int precision, const void *kx, const void *ky, const void *kz,
+                              int64_t t0, int64_t nt, int64_t G, double L, const void *field,
+                              double *acc, int64_t ld, hipStream_t s);
+
 // Step helpers.  K = {kx, ky, kz} (p each), k_prev/g_prev/g laid out [3][p].
 // out[0] = sum (K - k_prev)^2, out[1] = sum (K - k_prev) (g - g_prev).
 hipError_t launch_bb_dots(int precision, const void *kx, const void *ky, const void *kz,

@@ -407,3 +407,67 @@ def test_step_barzilai_borwein():
         assert info["eta"] == pytest.approx(want, rel=1e-12)
     else:
         assert not info["bb_used"]
+
+
+# --------------------------------------------------------------------------
+# Grid attraction: node field and trilinear interpolant
+# --------------------------------------------------------------------------
+def test_field_nodes_are_direct_sums():
+    """Node values equal the direct attraction sums at the node positions."""
+    G, L = 5, 0.5
+    rho = inputs.radial_density(G, L, 0.1, 2.0)
+    f = oracle.field(rho, G, L)
+    h = 2 * L / G
+    kx, ky, kz = 3, 0, 6                          # includes the extended layer (k = 0, G+1)
+    node = np.array([[-L + (kx - 0.5) * h], [-L + (ky - 0.5) * h], [-L + (kz - 0.5) * h]])
+    # a one-sample problem whose single target sits on the node: its attraction
+    # part is the field value (unscaled by 1/p = 1)
+    r = oracle.grad(node, rho, G, L)
+    n = kx + (G + 2) * (ky + (G + 2) * kz)
+    assert f[n, 0] == pytest.approx(r["ua"][0], rel=1e-15)
+    np.testing.assert_allclose(f[n, 1:], r["dFa"][:, 0], rtol=1e-14, atol=1e-17)
+
+
+def test_trilinear_reproduces_nodes_and_affine_fields():
+    G, L = 4, 0.5
+    Gn = G + 2
+    h = 2 * L / G
+    ax = -L + (np.arange(Gn) - 0.5) * h
+    z, y, x = np.meshgrid(ax, ax, ax, indexing="ij")
+    coef = np.array([[0.3, 1.0, -2.0, 0.5], [1.0, 0.0, 0.0, 0.0],
+                     [-0.2, 0.0, 3.0, 0.0], [0.0, 0.7, 0.1, -1.1]])
+    f = np.stack([c[0] + c[1] * x + c[2] * y + c[3] * z for c in coef], axis=-1).reshape(-1, 4)
+    # at nodes: exact
+    P = np.stack([x.ravel(), y.ravel(), z.ravel()])
+    np.testing.assert_allclose(oracle.interpolate(f, G, L, P), f.T, atol=1e-15)
+    # affine fields are reproduced everywhere inside the grid, also at the box faces
+    Q = RNG.uniform(-L, L, (3, 500))
+    Q[:, 0] = [L, -L, L]
+    got = oracle.interpolate(f, G, L, Q)
+    want = np.stack([c[0] + c[1] * Q[0] + c[2] * Q[1] + c[3] * Q[2] for c in coef])
+    np.testing.assert_allclose(got, want, atol=1e-14)
+
+
+def test_grid_attraction_converges_to_direct_sum():
+    """Interpolation error of the grid attraction shrinks as the grid is refined."""
+    L = 0.5
+    K = RNG.uniform(-0.45, 0.45, (3, 40))
+    errs = []
+    for G in (4, 8, 16):
+        rho = inputs.radial_density(G, L, 0.1, 2.0)
+        d = oracle.grad(K, rho, G, L)
+        f = oracle.grad_field(K, rho, G, L)
+        np.testing.assert_array_equal(f["dFr"], d["dFr"])
+        errs.append(np.linalg.norm(f["dFa"] - d["dFa"]) / np.linalg.norm(d["dFa"]))
+    assert errs[2] < errs[1] < errs[0] and errs[2] < 0.05
+
+
+def test_grad_field_matches_field_plus_interpolate():
+    G, L = 4, 0.5
+    K = RNG.uniform(-L, L, (3, 25))
+    rho = inputs.radial_density(G, L, 0.1, 2.0)
+    f = oracle.field(rho, G, L)
+    att = oracle.interpolate(f, G, L, K)
+    r = oracle.grad_field(K, rho, G, L)
+    np.testing.assert_allclose(r["ua"], att[0], rtol=1e-14)
+    np.testing.assert_allclose(r["dFa"], att[1:] / K.shape[1], rtol=1e-13, atol=1e-18)
