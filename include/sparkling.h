@@ -192,6 +192,20 @@ int sparkling_constraint_check(const spk_params *prm, const void *kx, const void
                                const void *kz, double viol[4], void *ws, size_t ws_bytes,
                                void *stream);
 
+/*
+ * Warm restart of the multi-resolution strategy (Sec. "Multi-resolution
+ * strategy for faster convergence", Algorithm 1): every shot of the coarse
+ * trajectory (prm->n_shots shots of prm->n_samples samples on a raster twice
+ * as long) is up-sampled by linear interpolation to 2*n_samples samples.
+ * Fine sample m sits at coarse position m/2: even m copy coarse sample m/2,
+ * odd m average its two neighbours, and the last fine sample continues the
+ * last coarse step (1.5 k[N-1] - 0.5 k[N-2]).  kx, ky, kz: device, coarse,
+ * p elements each; fx, fy, fz: device, 2p elements each, K's type, no
+ * aliasing.  Asynchronous.
+ */
+int sparkling_upsample(const spk_params *prm, const void *kx, const void *ky, const void *kz,
+                       void *fx, void *fy, void *fz, void *stream);
+
 typedef struct {
     int64_t iter;         /* in: iteration index t (0-based)                              */
     double  eta_fixed;    /* in: fixed step size, used while t < 20 and as BB fallback    */

@@ -57,6 +57,7 @@ def _load():
                          _p, _p, _i64, _dbl, _p],
             "orc_fd_directional": [_i64, _p, _p, _p, _i64, _dbl, _p, _dbl, _p, _dbl, _p],
             "orc_num_threads": [],
+            "orc_upsample": [_i64, _i64, _p, _p],
             "orc_field": [_i64, _dbl, _p, _dbl, _p],
             "orc_interpolate": [_i64, _dbl, _p, _i64, _p, _p, _p, _p],
             "orc_grad_field": [_i64, _p, _p, _p, _i64, _dbl, _p, _dbl, _i64, _p, _p, _p, _p, _p, _p],
@@ -219,3 +220,35 @@ def grad_field(K, rho, G: int, L: float, eps: float = 0.0, targets=None):
                                 _ptr(targets), _ptr(dF), _ptr(dFa), _ptr(dFr), _ptr(ua), _ptr(ur))
     _check(rc, "grad_field")
     return {"dF": dF, "dFa": dFa, "dFr": dFr, "ua": ua, "ur": ur, "targets": targets}
+
+
+def upsample(K, n_shots: int, n_samples: int) -> np.ndarray:
+    """Dyadic linear up-sampling of every shot: (3, Nc*N) -> (3, Nc*2N)."""
+    K = _f64(K)
+    out = np.empty((3, 2 * K.shape[1]))
+    _check(_load().orc_upsample(n_shots, n_samples, _ptr(K), _ptr(out)), "upsample")
+    return out
+
+
+def multiresolution(K0, rho, n_shots, n_samples_coarse, levels, G, L, a, b, te, n_pit, n_git,
+                    eta_scale=0.25, final_level=True, eps=0.0):
+    """Algorithm 1: projected gradient iterations on decimated shots, warm restart by
+    linear up-sampling, bounds halved per level.  K0 holds the coarsest shots
+    (n_samples_coarse each); a, b are the full-resolution per-raster bounds, scaled
+    by 2^d at decimation level d.  Returns the final K and the per-level records."""
+    K = _f64(K0).copy()
+    Ns = n_samples_coarse
+    recs = []
+    for d in range(levels, -1 if final_level else 0, -1):
+        p = n_shots * Ns
+        ad, bd = a * 2.0 ** d, b * 2.0 ** d
+        eta = eta_scale * (2.0 * L) * p ** (2.0 / 3.0)
+        kp, gp = np.zeros_like(K), np.zeros_like(K)
+        for it in range(n_git):
+            K, kp, gp, info = step(K, rho, n_shots, Ns, G, L, ad, bd, te, n_pit, kp, gp, it, eta,
+                                   eps)
+            recs.append(dict(level=d, iter=it, **info))
+        if d > 0:
+            K = upsample(K, n_shots, Ns)
+            Ns *= 2
+    return K, recs

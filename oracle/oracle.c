@@ -777,6 +777,38 @@ int orc_grad_field(int64_t p, const double *kx, const double *ky, const double *
     return 0;
 }
 
+/* ------------------------------------------------------------------ */
+/* Dyadic up-sampling of shots by linear interpolation (Sec.            */
+/* "Multi-resolution strategy for faster convergence", Algorithm 1):    */
+/* a shot of N samples on a raster of 2 dt becomes 2N samples on dt.    */
+/* Fine sample m sits at coarse position m/2: even m copy k[m/2], odd   */
+/* m average k[(m-1)/2] and k[(m+1)/2]; the last fine sample, half a    */
+/* coarse step past the end, continues the last coarse step linearly:   */
+/* 1.5 k[N-1] - 0.5 k[N-2] (k[0] when N = 1).                            */
+/* coarse: [3][Nc*N], fine: [3][Nc*2N], both shot-lexicographic.        */
+/* ------------------------------------------------------------------ */
+int orc_upsample(int64_t Nc, int64_t N, const double *coarse, double *fine)
+{
+    if (Nc < 1 || N < 1 || !coarse || !fine)
+        return -1;
+    int64_t pc = Nc * N, pf = 2 * pc;
+    for (int c = 0; c < 3; ++c)
+        for (int64_t s = 0; s < Nc; ++s) {
+            const double *k = coarse + c * pc + s * N;
+            double *f = fine + c * pf + s * 2 * N;
+            for (int64_t m = 0; m < 2 * N; ++m) {
+                int64_t n = m / 2;
+                if (m % 2 == 0)
+                    f[m] = k[n];
+                else if (n + 1 < N)
+                    f[m] = (k[n] + k[n + 1]) * 0.5;
+                else
+                    f[m] = N > 1 ? 1.5 * k[n] - 0.5 * k[n - 1] : k[n];
+            }
+        }
+    return 0;
+}
+
 int orc_num_threads(void)
 {
 #ifdef _OPENMP

@@ -6,11 +6,11 @@ is its ctypes binding plus the seeded input generators and workload table.
 from .api import (FLAG_DISCREPANCY, KIND_ATTRACTION, KIND_INTERPOLATION, KIND_OTHER, KIND_PROJECTION, KIND_REPULSION,
                   PRECISIONS, Params, SparklingEnergy, SparklingError, StepState, alpha_beta,
                   attraction_field, constraint_check, energy, grad, load_library, project_, sparkling_energy, step_,
-                  timing_enable, timing_query, timing_reset, workspace, workspace_size)
+                  timing_enable, timing_query, timing_reset, upsample, workspace, workspace_size)
 
 __all__ = [
     "FLAG_DISCREPANCY", "KIND_ATTRACTION", "KIND_INTERPOLATION", "KIND_OTHER", "KIND_PROJECTION", "KIND_REPULSION",
     "PRECISIONS", "Params", "SparklingEnergy", "SparklingError", "StepState", "alpha_beta",
     "attraction_field", "constraint_check", "energy", "grad", "load_library", "project_", "sparkling_energy", "step_",
-    "timing_enable", "timing_query", "timing_reset", "workspace", "workspace_size",
+    "timing_enable", "timing_query", "timing_reset", "upsample", "workspace", "workspace_size",
 ]

@@ -65,6 +65,7 @@ def load_library(path: Path | str | None = None):
         "sparkling_project": ([_vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp], ctypes.c_int),
         "sparkling_constraint_check": ([_vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp], ctypes.c_int),
         "sparkling_step": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp], ctypes.c_int),
+        "sparkling_upsample": ([_vp] * 8, ctypes.c_int),
         "spk_timing_enable": ([ctypes.c_int], ctypes.c_int),
         "spk_timing_query": ([ctypes.c_int, _vp, _vp, _vp], ctypes.c_int),
         "spk_timing_reset": ([], ctypes.c_int),
@@ -258,6 +259,17 @@ def constraint_check(K: torch.Tensor, prm: Params):
                                                      _vp(ws.data_ptr()), ws.numel(), _stream(K)),
            "sparkling_constraint_check")
     return np.array(viol[:])
+
+
+def upsample(K: torch.Tensor, prm: Params) -> torch.Tensor:
+    """Dyadic linear up-sampling of every shot of K (prm describes the coarse
+    trajectory); returns a (3, 2p) tensor."""
+    _check_k(K, prm)
+    out = torch.empty((3, 2 * prm.p), dtype=K.dtype, device=K.device)
+    c = prm.c()
+    _check(load_library().sparkling_upsample(ctypes.byref(c), *_rows(K), *_rows(out), _stream(K)),
+           "sparkling_upsample")
+    return out
 
 
 class StepState:

@@ -693,6 +693,27 @@ int sparkling_step(const spk_params *prm, void *kx, void *ky, void *kz, const vo
     return SPK_OK;
 }
 
+int sparkling_upsample(const spk_params *prm, const void *kx, const void *ky, const void *kz,
+                       void *fx, void *fy, void *fz, void *stream)
+{
+    g_err.clear();
+    int rc = check_params(prm, false);
+    if (rc)
+        return rc;
+    const int64_t p = prm->n_shots * prm->n_samples;
+    if (p > (int64_t(1) << 30))
+        return fail(SPK_EINVAL, "the up-sampled trajectory must stay below 2^31 samples");
+    const size_t al = elt_size(prm->precision);
+    if ((rc = check_k(prm, kx, ky, kz)) || (rc = check_ptr(fx, "fx", al)) ||
+        (rc = check_ptr(fy, "fy", al)) || (rc = check_ptr(fz, "fz", al)))
+        return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Timed tm(SPK_KIND_OTHER, 0.0, s);
+    SPK_HIP(launch_upsample(prm->precision, kx, ky, kz, fx, fy, fz, prm->n_shots, prm->n_samples, s),
+            "up-sampling");
+    return SPK_OK;
+}
+
 int spk_timing_enable(int on)
 {
     std::lock_guard<std::mutex> lk(g_tmu);

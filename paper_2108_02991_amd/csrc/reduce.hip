@@ -193,7 +193,48 @@ __global__ __launch_bounds__(EW) void axpy_save_kernel(T *kx, T *ky, T *kz, T *k
     k[i] = (T)((double)kv - eta * (double)gv);
 }
 
+// Dyadic linear up-sampling of shots (fine sample m at coarse position m/2;
+// the last one continues the last coarse step), in double, contraction off.
+template <typename T>
+__global__ __launch_bounds__(EW) void upsample_kernel(const T *kx, const T *ky, const T *kz, T *fx,
+                                                      T *fy, T *fz, int64_t Nc, int64_t N)
+{
+#pragma clang fp contract(off)
+    const int64_t pf = 2 * Nc * N;
+    const int64_t e = (int64_t)blockIdx.x * EW + threadIdx.x;
+    if (e >= 3 * pf)
+        return;
+    const int64_t c = e / pf, i = e - c * pf;
+    const int64_t shot = i / (2 * N), m = i - shot * (2 * N), n = m / 2;
+    const T *k = (c == 0 ? kx : (c == 1 ? ky : kz)) + shot * N;
+    T *f = (c == 0 ? fx : (c == 1 ? fy : fz)) + shot * 2 * N;
+    double v;
+    if (m % 2 == 0)
+        v = (double)k[n];
+    else if (n + 1 < N)
+        v = ((double)k[n] + (double)k[n + 1]) * 0.5;
+    else
+        v = N > 1 ? 1.5 * (double)k[n] - 0.5 * (double)k[n - 1] : (double)k[n];
+    f[m] = (T)v;
+}
+
 }  // namespace
+
+hipError_t launch_upsample(int precision, const void *kx, const void *ky, const void *kz, void *fx,
+                           void *fy, void *fz, int64_t Nc, int64_t N, hipStream_t s)
+{
+    const int64_t n = 3 * 2 * Nc * N;
+    if (precision == SPK_PLAIN_FP64) {
+        using T = double;
+        hipLaunchKernelGGL(upsample_kernel<T>, dim3(ew_blocks(n)), dim3(EW), 0, s, (const T *)kx,
+                           (const T *)ky, (const T *)kz, (T *)fx, (T *)fy, (T *)fz, Nc, N);
+    } else {
+        using T = float;
+        hipLaunchKernelGGL(upsample_kernel<T>, dim3(ew_blocks(n)), dim3(EW), 0, s, (const T *)kx,
+                           (const T *)ky, (const T *)kz, (T *)fx, (T *)fy, (T *)fz, Nc, N);
+    }
+    return hipGetLastError();
+}
 
 hipError_t launch_combine(double *acc, const double *part, int nslabs, int64_t ld, int64_t nt,
                           bool init, hipStream_t s)

@@ -119,6 +119,10 @@ hipError_t launch_bb_dots(int precision, const void *kx, const void *ky, const v
 hipError_t launch_axpy_save(int precision, void *kx, void *ky, void *kz, void *k_prev,
                             const void *g, void *g_prev, int64_t p, double eta, hipStream_t s);
 
+// Dyadic linear up-sampling: coarse shots of N samples -> fine shots of 2N.
+hipError_t launch_upsample(int precision, const void *kx, const void *ky, const void *kz, void *fx,
+                           void *fy, void *fz, int64_t Nc, int64_t N, hipStream_t s);
+
 // Projection and constraint check (one block per shot).
 hipError_t launch_project(int precision, void *kx, void *ky, void *kz, int64_t n_shots,
                           int64_t n_samples, double L, double a, double b, int64_t te,

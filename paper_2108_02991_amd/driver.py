@@ -1,5 +1,6 @@
-"""Projected-gradient loop over `sparkling_step` (the inner loop of Algorithm 1 at
-one resolution level) with per-iteration JSON records.
+"""Drivers over the C ABI: the projected-gradient loop at one resolution level
+(`run`) and the multi-resolution strategy of Algorithm 1 (`multiresolution`),
+with per-iteration JSON records.
 
     python -m paper_2108_02991_amd.driver --workload c5_loop --precision fp32_comp \\
         --iters 100 --out run.jsonl
@@ -60,6 +61,56 @@ def run(workload: configs.Workload, precision: str, iters: int, device="cuda:0",
         out.write(json.dumps(records[-1]) + "\n")
         out.flush()
     return records, K
+
+
+def multiresolution(K0: torch.Tensor, rho: torch.Tensor, prm_full: api.Params, levels: int,
+                    n_git: int, final_level: bool = True, eta_scale: float = 0.25, out=None,
+                    log_every: int = 0):
+    """Algorithm 1 (multi-resolution SPARKLING) on the GPU.
+
+    K0 holds the coarsest shots, prm_full.n_samples >> levels samples each.  At
+    decimation level d the per-raster bounds are prm_full.a_max * 2^d and
+    prm_full.b_max * 2^d (the scaling printed with Algorithm 1), n_git
+    projected gradient steps run with a fixed step for the first 20 and
+    Barzilai-Borwein after (state reset per level, eta_fixed from the level's
+    p), and the result is up-sampled to twice the samples as the warm start of
+    the next level.  With final_level=True the full resolution (d = 0) is
+    optimised as well.  Returns the final K and the per-iteration records.
+    """
+    if prm_full.n_samples % (1 << levels):
+        raise ValueError("n_samples must be divisible by 2^levels")
+    Ns = prm_full.n_samples >> levels
+    K = K0
+    records = []
+    for d in range(levels, -1 if final_level else 0, -1):
+        prm = api.Params(prm_full.n_shots, Ns, prm_full.grid, precision=prm_full.precision,
+                         half_width=prm_full.half_width, eps=prm_full.eps,
+                         a_max=prm_full.a_max * 2.0 ** d, b_max=prm_full.b_max * 2.0 ** d,
+                         te_index=prm_full.te_index, n_pit=prm_full.n_pit,
+                         attraction_field=prm_full.attraction_field)
+        if K.shape[1] != prm.p:
+            raise ValueError(f"level {d}: K has {K.shape[1]} samples, expected {prm.p}")
+        eta = eta_scale * (2.0 * prm.half_width) * float(prm.p) ** (2.0 / 3.0)
+        state = api.StepState(prm, K.device)
+        for it in range(n_git):
+            torch.cuda.synchronize(K.device)
+            t0 = time.perf_counter()
+            info = api.step_(K, rho, prm, state, it, eta)
+            torch.cuda.synchronize(K.device)
+            rec = {"level": d, "iter": it, "n_samples": Ns, "F": info["F"], "Fa": info["Fa"],
+                   "Fr": info["Fr"], "eta": info["eta"], "bb_used": info["bb_used"],
+                   "viol": [float(v) for v in info["viol"]], "s": time.perf_counter() - t0}
+            records.append(rec)
+            if out is not None:
+                out.write(json.dumps(rec) + "\n")
+                out.flush()
+            if log_every and (it % log_every == 0 or it == n_git - 1):
+                print(f"[driver] level {d} iter {it}: F={info['F']:.12e} eta={info['eta']:.5g}",
+                      file=sys.stderr, flush=True)
+        if d > 0:
+            K = api.upsample(K, prm)
+            Ns *= 2
+    return K, records
 
 
 def main():

@@ -1,0 +1,46 @@
+"""Algorithm 1 (multi-resolution) on the GPU against the oracle's Algorithm 1."""
+import numpy as np
+import pytest
+import torch
+
+from gpu_util import configs, device_problem, host64, inputs, oracle, say, spk
+from paper_2108_02991_amd import driver
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("precision", ["plain_fp64", "fp32_comp"])
+def test_upsample_matches_oracle(gpu, precision):
+    Nc, N = 5, 37
+    K = inputs.radial_spokes(Nc, N, 0.5, seed=9, jitter=0.05)
+    prm = spk.Params(Nc, N, 1, precision=precision)
+    Kd, _ = device_problem(K, [1.0], precision, gpu)
+    got = host64(spk.upsample(Kd, prm))
+    want = oracle.upsample(host64(Kd), Nc, N)
+    if precision == "plain_fp64":
+        assert np.array_equal(got, want)
+    else:
+        assert np.array_equal(got, want.astype(np.float32).astype(np.float64))
+
+
+def test_multiresolution_plain_fp64_matches_oracle(gpu):
+    w = configs.C1
+    Nc, Ns, levels, n_git, G = 6, 64, 2, 4, 8
+    a, b = spk.alpha_beta(configs.GMAX, configs.SMAX, configs.RASTER_DT, configs.DWELL_DT, w.fov,
+                          w.kmax, configs.GAMMA_BAR, 0.5)
+    K0 = inputs.radial_spokes(Nc, Ns >> levels, 0.5, seed=3, jitter=0.02)
+    rho = inputs.radial_density(G, 0.5, 0.05, 2.0)
+    prm = spk.Params(Nc, Ns, G, precision="plain_fp64", a_max=a, b_max=b, n_pit=100)
+    Kd, rd = device_problem(K0, rho, "plain_fp64", gpu)
+    say("  multires GPU")
+    Kg, recs = driver.multiresolution(Kd, rd, prm, levels, n_git)
+    say("  multires oracle")
+    Ko, orecs = oracle.multiresolution(K0, rho, Nc, Ns >> levels, levels, G, 0.5, a, b, 0, 100,
+                                       n_git)
+    assert len(recs) == len(orecs) == (levels + 1) * n_git
+    for r, o in zip(recs, orecs):
+        assert r["level"] == o["level"] and r["iter"] == o["iter"]
+        assert r["F"] == pytest.approx(o["F"], rel=1e-11)
+        assert r["eta"] == pytest.approx(o["eta"], rel=1e-12)
+    assert Kg.shape == (3, Nc * Ns)
+    assert np.abs(host64(Kg) - Ko).max() <= 1e-9

@@ -471,3 +471,26 @@ def test_grad_field_matches_field_plus_interpolate():
     r = oracle.grad_field(K, rho, G, L)
     np.testing.assert_allclose(r["ua"], att[0], rtol=1e-14)
     np.testing.assert_allclose(r["dFa"], att[1:] / K.shape[1], rtol=1e-13, atol=1e-18)
+
+
+# --------------------------------------------------------------------------
+# Multi-resolution: dyadic linear up-sampling of shots
+# --------------------------------------------------------------------------
+def test_upsample_reproduces_uniform_motion():
+    """A shot moving at constant velocity on the coarse raster is sampled
+    exactly at half steps on the fine raster (including the last sample)."""
+    Nc, N = 3, 9
+    c0 = RNG.uniform(-0.1, 0.1, (3, Nc, 1))
+    v = RNG.uniform(-0.02, 0.02, (3, Nc, 1))
+    n = np.arange(N)[None, None, :]
+    K = (c0 + v * n).reshape(3, -1)
+    f = oracle.upsample(K, Nc, N).reshape(3, Nc, 2 * N)
+    m = np.arange(2 * N)[None, None, :]
+    np.testing.assert_allclose(f, c0 + v * m / 2, atol=1e-16)
+    assert np.array_equal(f[:, :, ::2], K.reshape(3, Nc, N))
+
+
+def test_upsample_single_sample_shots():
+    K = RNG.uniform(-0.3, 0.3, (3, 4))
+    f = oracle.upsample(K, 4, 1)
+    assert np.array_equal(f[:, 0::2], K) and np.array_equal(f[:, 1::2], K)
