@@ -18,7 +18,7 @@ namespace spk {
 #define SPK_SAMPLE_TILE 512
 #endif
 #ifndef SPK_TARGETS_F32
-#define SPK_TARGETS_F32 4
+#define SPK_TARGETS_F32 2
 #endif
 #ifndef SPK_TARGETS_F64
 #define SPK_TARGETS_F64 2

@@ -163,9 +163,27 @@ void sweep_samples_kernel(SweepLaunch l)
             }
         };
         if (n == kSampleTile) {
-#pragma unroll SPK_SOURCE_UNROLL
-            for (int j = 0; j < kSampleTile; ++j)
-                pair(tile[j]);
+            // Full tile: LDS reads run one group of U sources ahead of the
+            // pair arithmetic, so the broadcast latency hides behind the
+            // previous group's VALU work.
+            constexpr int U = SPK_SOURCE_UNROLL;
+            static_assert(kSampleTile % U == 0 && (kSampleTile & (kSampleTile - 1)) == 0, "");
+            P4<T> cur[U], nxt[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                cur[u] = tile[u];
+            for (int j = 0; j < kSampleTile; j += U) {
+                const int jn = (j + U) & (kSampleTile - 1);   // the last group re-reads group 0
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    nxt[u] = tile[jn + u];
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    pair(cur[u]);
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    cur[u] = nxt[u];
+            }
         } else {
             for (int j = 0; j < n; ++j)
                 pair(tile[j]);
