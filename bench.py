@@ -281,18 +281,18 @@ def cpu_baseline(w, K, rho, seconds, field=False):
     rh = rho.detach().cpu().double().numpy()
     p = Kh.shape[1]
     fn = oracle.grad_field if field else oracle.grad
-    per_target = p + (8 if field else 1) * w.n_voxels
     credited = p if field else p + w.n_voxels
-    probe = inputs.sample_targets(p, 4, seed=99)
-    t0 = time.perf_counter()
-    fn(Kh, rh, w.grid, w.half_width, 0.0, probe)
-    rate = probe.size * per_target / (time.perf_counter() - t0)
-    n = int(max(16, min(4096, seconds * rate / per_target)))
-    targets = inputs.sample_targets(p, n, seed=100)
-    log(f"cpu baseline: oracle on {targets.size} targets ({oracle.num_threads()} threads)")
-    t0 = time.perf_counter()
-    fn(Kh, rh, w.grid, w.half_width, 0.0, targets)
-    dt = time.perf_counter() - t0
+    # targets in batches of 64 until the time budget is spent (at least one batch)
+    pool = inputs.sample_targets(p, min(p, 65536), seed=100)
+    done, dt = 0, 0.0
+    while done < pool.size and (done == 0 or dt < seconds):
+        batch = pool[done:done + 64]
+        t0 = time.perf_counter()
+        fn(Kh, rh, w.grid, w.half_width, 0.0, batch)
+        dt += time.perf_counter() - t0
+        done += batch.size
+    targets = pool[:done]
+    log(f"cpu baseline: oracle on {done} targets ({oracle.num_threads()} threads), {dt:.1f} s")
     pairs = float(targets.size) * credited
     what = ("the grid attraction of 8 nodes x all cells" if field else f"all {w.n_voxels} cells")
     return {"value": pairs / dt, "unit": "pair-interactions/s", "cores": oracle.num_threads(),
