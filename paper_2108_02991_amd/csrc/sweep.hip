@@ -54,7 +54,18 @@ template <typename T> struct alignas(4 * sizeof(T)) P4 { T x, y, z, w; };
 template <typename T> struct alignas(2 * sizeof(T)) P2 { T x, y; };
 
 __device__ inline float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
-__device__ inline double rsq(double x) { return rsqrt(x); }
+// Double reciprocal square root for the guarded |d|^2 (finite, >= the
+// smallest normal): the hardware estimate y0 refined once with the
+// second-order term of (1 - r)^(-1/2) = 1 + r/2 + 3r^2/8 + ..., where
+// r = 1 - x*y0^2 is formed with an FMA; the estimate's relative error e
+// leaves O(e^3), far below double rounding.
+__device__ inline double rsq(double x)
+{
+    const double y0 = __builtin_amdgcn_rsq(x);
+    const double r = __builtin_fma(-x * y0, y0, 1.0);
+    const double c = __builtin_fma(r, 0.375, 0.5);
+    return __builtin_fma(y0 * r, c, y0);
+}
 
 __device__ inline float fmaT(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ inline double fmaT(double a, double b, double c) { return __builtin_fma(a, b, c); }

@@ -120,6 +120,10 @@ def main():
     ap.add_argument("--iters", type=int, default=None)
     ap.add_argument("--out", default=None)
     ap.add_argument("--log-every", type=int, default=10)
+    ap.add_argument("--levels", type=int, default=0,
+                    help="run Algorithm 1 with this many decimation levels (0 = single level)")
+    ap.add_argument("--field", action="store_true",
+                    help="evaluate the attraction by the grid interpolant")
     args = ap.parse_args()
     w = configs.WORKLOADS[args.workload]
     precision = args.precision or w.precision
@@ -127,7 +131,39 @@ def main():
     api.load_library()
     out = open(args.out, "a") if args.out else None
     try:
-        run(w, precision, iters, out=out, log_every=args.log_every)
+        if args.levels == 0 and not args.field:
+            run(w, precision, iters, out=out, log_every=args.log_every)
+        else:
+            dev = torch.device("cuda:0")
+            a, b = api.alpha_beta(configs.GMAX, configs.SMAX, configs.RASTER_DT,
+                                  configs.DWELL_DT, w.fov, w.kmax, configs.GAMMA_BAR,
+                                  w.half_width)
+            prm = api.Params(w.n_shots, w.n_samples, w.grid, precision=precision,
+                             half_width=w.half_width, a_max=a, b_max=b, te_index=0,
+                             n_pit=w.n_pit)
+            from . import inputs
+            K0 = inputs.radial_spokes(w.n_shots, w.n_samples >> args.levels, w.half_width,
+                                      w.seed, w.jitter)
+            K0 = torch.tensor(K0, dtype=prm.dtype, device=dev)
+            rho = torch.tensor(w.density(), dtype=prm.dtype, device=dev)
+            t0 = time.perf_counter()
+            if args.field:
+                prm.attraction_field = api.attraction_field(rho, prm)
+                torch.cuda.synchronize(dev)
+                print(f"[driver] node field in {time.perf_counter() - t0:.2f} s",
+                      file=sys.stderr, flush=True)
+            K, recs = multiresolution(K0, rho, prm, args.levels, iters, out=out,
+                                      log_every=args.log_every)
+            torch.cuda.synchronize(dev)
+            total = time.perf_counter() - t0
+            F, _, _, _ = api.energy(K, rho, prm)
+            summary = {"levels": args.levels, "n_git": iters, "precision": precision,
+                       "field": args.field, "total_s": total, "final_F": F,
+                       "s_per_level": {str(d): sum(r["s"] for r in recs if r["level"] == d)
+                                       for d in range(args.levels, -1, -1)}}
+            print(json.dumps(summary), flush=True)
+            if out is not None:
+                out.write(json.dumps(summary) + "\n")
     finally:
         if out is not None:
             out.close()
