@@ -186,3 +186,21 @@ def test_c3_full_size_sampled_targets(gpu):
     assert rel_l2(host64(pr)[t], ref["ur"]) <= ENERGY_TOL["fp32_comp"]
     assert rel_l2(host64(pa)[t], ref["ua"]) <= ENERGY_TOL["fp32_comp"]
     assert np.isfinite(en).all() and en[1] > en[2] > 0
+
+
+def test_c2_all_fp32_forms_sampled_targets(gpu):
+    """The three FP32 forms on the same stored inputs against one oracle pass."""
+    w = configs.C2
+    K, rho = w.trajectory(), w.density()
+    t = inputs.sample_targets(w.p, 2048, seed=23)
+    ref = None
+    for precision in ("fp32_comp", "fp32_acc64", "fp32_naive"):
+        prm = params_for(w, precision)
+        Kd, rd = device_problem(K, rho, precision, gpu)
+        g, (pa, pr) = spk.grad(Kd, rd, prm, potentials=True)
+        torch.cuda.synchronize()
+        if ref is None:
+            ref = oracle.grad(host64(Kd), host64(rd), w.grid, 0.5, 0.0, t)
+        err = rel_l2(host64(g)[:, t], ref["dF"])
+        say(f"  c2 {precision} rel L2 = {err:.3e} (potentials {rel_l2(host64(pr)[t], ref['ur']):.3e})")
+        assert err <= GRAD_TOL[precision]
