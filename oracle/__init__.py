@@ -51,10 +51,12 @@ def _load():
             "orc_energy": [_i64, _p, _p, _p, _i64, _dbl, _p, _dbl, _p],
             "orc_rho_self_energy": [_i64, _dbl, _p, _dbl, _p],
             "orc_alpha_beta": [_dbl] * 8 + [_p, _p],
-            "orc_project": [_i64, _i64, _p, _p, _p, _dbl, _dbl, _dbl, _i64, ctypes.c_int],
-            "orc_constraint_check": [_i64, _i64, _p, _p, _p, _dbl, _dbl, _dbl, _i64, _p],
+            "orc_project": [_i64, _i64, _p, _p, _p, _dbl, _dbl, _dbl, _i64, ctypes.c_int,
+                            ctypes.c_int],
+            "orc_constraint_check": [_i64, _i64, _p, _p, _p, _dbl, _dbl, _dbl, _i64, ctypes.c_int,
+                                     _p],
             "orc_step": [_i64, _i64, _p, _i64, _dbl, _p, _dbl, _dbl, _dbl, _i64, ctypes.c_int,
-                         _p, _p, _i64, _dbl, _p],
+                         ctypes.c_int, _p, _p, _i64, _dbl, _p],
             "orc_fd_directional": [_i64, _p, _p, _p, _i64, _dbl, _p, _dbl, _p, _dbl, _p],
             "orc_num_threads": [],
             "orc_upsample": [_i64, _i64, _p, _p],
@@ -135,28 +137,28 @@ def alpha_beta(gmax, smax, raster_dt, dwell_dt, fov, kmax, gamma_bar, half_width
 
 
 def project(K, n_shots: int, n_samples: int, L: float, a: float, b: float, te: int,
-            n_pit: int) -> np.ndarray:
+            n_pit: int, rotation_variant: bool = False) -> np.ndarray:
     """Per-shot projection of K (3, Nc*Ns); returns a new float64 array."""
     K = _f64(K).copy()
     rc = _load().orc_project(n_shots, n_samples, _ptr(K[0]), _ptr(K[1]), _ptr(K[2]),
-                             L, a, b, te, n_pit)
+                             L, a, b, te, n_pit, int(rotation_variant))
     _check(rc, "project")
     return K
 
 
 def constraint_check(K, n_shots: int, n_samples: int, L: float, a: float, b: float,
-                     te: int) -> np.ndarray:
+                     te: int, rotation_variant: bool = False) -> np.ndarray:
     K = _f64(K)
     out = np.empty(4)
     x, y, z = (np.ascontiguousarray(K[c]) for c in range(3))
     rc = _load().orc_constraint_check(n_shots, n_samples, _ptr(x), _ptr(y), _ptr(z),
-                                      L, a, b, te, _ptr(out))
+                                      L, a, b, te, int(rotation_variant), _ptr(out))
     _check(rc, "constraint_check")
     return out
 
 
 def step(K, rho, n_shots, n_samples, G, L, a, b, te, n_pit, k_prev, g_prev, it, eta_fixed,
-         eps: float = 0.0):
+         eps: float = 0.0, rotation_variant: bool = False):
     """One projected gradient step.  Returns (K_new, k_prev, g_prev, info dict)."""
     K = _f64(K).copy()
     k_prev = _f64(k_prev).copy()
@@ -164,7 +166,8 @@ def step(K, rho, n_shots, n_samples, G, L, a, b, te, n_pit, k_prev, g_prev, it, 
     rho = _f64(rho)
     info = np.empty(10)
     rc = _load().orc_step(n_shots, n_samples, _ptr(K), G, L, _ptr(rho), eps, a, b, te, n_pit,
-                          _ptr(k_prev), _ptr(g_prev), it, eta_fixed, _ptr(info))
+                          int(rotation_variant), _ptr(k_prev), _ptr(g_prev), it, eta_fixed,
+                          _ptr(info))
     _check(rc, "step")
     d = {"eta": info[0], "F": info[1], "Fa": info[2], "Fr": info[3],
          "viol": info[4:8].copy(), "bb_used": bool(info[8])}

@@ -322,8 +322,20 @@ static void shrink3(double z[3], double thr)
     z[2] = z[2] * f;
 }
 
+/* Rotation-variant bounds (per-axis |.| <= bound, the l_inf form noted in
+ * Sec. "3D K-space sampling"): the dual prox is soft-thresholding of each
+ * coordinate on its own, z * max(0, 1 - thr/|z|). */
+static void shrink_each(double z[3], double thr)
+{
+    for (int c = 0; c < 3; ++c) {
+        double m = fabs(z[c]);
+        double f = (m > thr) ? (1.0 - thr / m) : 0.0;
+        z[c] = z[c] * f;
+    }
+}
+
 static void project_shot(int64_t Ns, double *xyz[3], double L, double a, double b,
-                         int64_t te, int n_pit, double *buf)
+                         int64_t te, int n_pit, int rv, double *buf)
 {
     /* buf holds k[3][Ns], s[3][Ns], q,qh,qn[3][Ns], r,rh,rn[3][Ns] */
     double *k = buf, *s = k + 3 * Ns;
@@ -352,7 +364,10 @@ static void project_shot(int64_t Ns, double *xyz[3], double L, double a, double 
                 const double *sc = s + c * Ns;
                 z[c] = qh[c * Ns + n] + tau * (sc[n + 1] - sc[n]);
             }
-            shrink3(z, thr_a);
+            if (rv)
+                shrink_each(z, thr_a);
+            else
+                shrink3(z, thr_a);
             for (int c = 0; c < 3; ++c)
                 qn[c * Ns + n] = z[c];
         }
@@ -362,7 +377,10 @@ static void project_shot(int64_t Ns, double *xyz[3], double L, double a, double 
                 const double *sc = s + c * Ns;
                 z[c] = rh[c * Ns + n] + tau * ((sc[n + 2] - 2.0 * sc[n + 1]) + sc[n]);
             }
-            shrink3(z, thr_b);
+            if (rv)
+                shrink_each(z, thr_b);
+            else
+                shrink3(z, thr_b);
             for (int c = 0; c < 3; ++c)
                 rn[c * Ns + n] = z[c];
         }
@@ -390,9 +408,10 @@ static void project_shot(int64_t Ns, double *xyz[3], double L, double a, double 
             xyz[c][te] = 0.0;
 }
 
-/* Project every shot of K (3 arrays of Nc*Ns, shot-lexicographic) in place. */
+/* Project every shot of K (3 arrays of Nc*Ns, shot-lexicographic) in place.
+ * rv = 0: rotation-invariant bounds on |.|_2 per sample; rv = 1: per-axis bounds. */
 int orc_project(int64_t Nc, int64_t Ns, double *kx, double *ky, double *kz,
-                double L, double a, double b, int64_t te, int n_pit)
+                double L, double a, double b, int64_t te, int n_pit, int rv)
 {
     if (Nc < 1 || Ns < 2 || !kx || !ky || !kz || !(L > 0) || !(a > 0) || !(b > 0) ||
         te < -1 || te >= Ns || n_pit < 0)
@@ -408,7 +427,7 @@ int orc_project(int64_t Nc, int64_t Ns, double *kx, double *ky, double *kz,
 #pragma omp for schedule(dynamic, 1)
             for (int64_t c = 0; c < Nc; ++c) {
                 double *xyz[3] = {kx + c * Ns, ky + c * Ns, kz + c * Ns};
-                project_shot(Ns, xyz, L, a, b, te, n_pit, buf);
+                project_shot(Ns, xyz, L, a, b, te, n_pit, rv, buf);
             }
             free(buf);
         }
@@ -428,11 +447,20 @@ static double vmax(double m, double x)
  * Normalised constraint violations of K (Sec. "3D K-space sampling"):
  *   out[0] = max |s[n+1] - s[n]| / a          (speed; <= 1 is feasible)
  *   out[1] = max |s[n+2] - 2 s[n+1] + s[n]| / b  (slew)
+ * with |.| the Euclidean norm of the 3 coordinates (rv = 0) or their
+ * largest magnitude (rv = 1, per-axis bounds);
  *   out[2] = max |s|_inf / L                  (box)
  *   out[3] = max over shots |s[te]|           (echo-time point; 0 if te < 0)
  */
+static double norm3(double dx, double dy, double dz, int rv)
+{
+    if (rv)
+        return vmax(vmax(fabs(dx), fabs(dy)), fabs(dz));
+    return sqrt((dx * dx + dy * dy) + dz * dz);
+}
+
 int orc_constraint_check(int64_t Nc, int64_t Ns, const double *kx, const double *ky,
-                         const double *kz, double L, double a, double b, int64_t te,
+                         const double *kz, double L, double a, double b, int64_t te, int rv,
                          double out[4])
 {
     if (Nc < 1 || Ns < 2 || !kx || !ky || !kz || !(L > 0) || !(a > 0) || !(b > 0) ||
@@ -443,13 +471,13 @@ int orc_constraint_check(int64_t Nc, int64_t Ns, const double *kx, const double 
         const double *x = kx + c * Ns, *y = ky + c * Ns, *z = kz + c * Ns;
         for (int64_t n = 0; n + 1 < Ns; ++n) {
             double dx = x[n + 1] - x[n], dy = y[n + 1] - y[n], dz = z[n + 1] - z[n];
-            m0 = vmax(m0, sqrt((dx * dx + dy * dy) + dz * dz) / a);
+            m0 = vmax(m0, norm3(dx, dy, dz, rv) / a);
         }
         for (int64_t n = 0; n + 2 < Ns; ++n) {
             double dx = (x[n + 2] - 2.0 * x[n + 1]) + x[n];
             double dy = (y[n + 2] - 2.0 * y[n + 1]) + y[n];
             double dz = (z[n + 2] - 2.0 * z[n + 1]) + z[n];
-            m1 = vmax(m1, sqrt((dx * dx + dy * dy) + dz * dz) / b);
+            m1 = vmax(m1, norm3(dx, dy, dz, rv) / b);
         }
         for (int64_t n = 0; n < Ns; ++n) {
             m2 = vmax(m2, fabs(x[n]) / L);
@@ -475,7 +503,7 @@ int orc_constraint_check(int64_t Nc, int64_t Ns, const double *kx, const double 
  * info_out[0..9] = eta, F, Fa, Fr, viol[0..3], bb_used, (unused 0).
  */
 int orc_step(int64_t Nc, int64_t Ns, double *K, int64_t G, double L, const double *rho,
-             double eps, double a, double b, int64_t te, int n_pit,
+             double eps, double a, double b, int64_t te, int n_pit, int rv,
              double *k_prev, double *g_prev, int64_t iter, double eta_fixed,
              double info_out[10])
 {
@@ -527,9 +555,9 @@ int orc_step(int64_t Nc, int64_t Ns, double *K, int64_t G, double L, const doubl
         K[e] = K[e] - eta * g[e];
     }
     double viol[4];
-    rc = orc_project(Nc, Ns, K, K + p, K + 2 * p, L, a, b, te, n_pit);
+    rc = orc_project(Nc, Ns, K, K + p, K + 2 * p, L, a, b, te, n_pit, rv);
     if (!rc)
-        rc = orc_constraint_check(Nc, Ns, K, K + p, K + 2 * p, L, a, b, te, viol);
+        rc = orc_constraint_check(Nc, Ns, K, K + p, K + 2 * p, L, a, b, te, rv, viol);
     info_out[0] = eta;
     info_out[1] = fa - fr;
     info_out[2] = fa;

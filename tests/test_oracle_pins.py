@@ -355,6 +355,97 @@ def test_projection_variational_inequality():
                                         for _ in range(20))
 
 
+# Rotation-variant (per-axis) bounds: the constraint set is a product of one
+# polytope per axis, so each axis is an independent box-constrained QP.
+def test_projection_per_axis_two_samples_te0():
+    a, b, L = 0.1, 0.05, 0.5
+    for seed in range(4):
+        k = np.random.default_rng(seed).uniform(-0.3, 0.3, (3, 2))
+        s = oracle.project(k, 1, 2, L, a, b, 0, 10000, rotation_variant=True)
+        assert np.array_equal(s[:, 0], [0, 0, 0])
+        np.testing.assert_allclose(s[:, 1], np.clip(k[:, 1], -a, a), atol=1e-10)
+
+
+def test_projection_per_axis_two_samples_free_ends():
+    a, b, L = 0.1, 0.05, 0.5
+    for seed in range(4):
+        k = np.random.default_rng(seed).uniform(-0.3, 0.3, (3, 2))
+        s = oracle.project(k, 1, 2, L, a, b, -1, 10000, rotation_variant=True)
+        m, d = (k[:, 0] + k[:, 1]) / 2, np.clip(k[:, 1] - k[:, 0], -a, a)
+        np.testing.assert_allclose(s[:, 0], m - d / 2, atol=1e-10)
+        np.testing.assert_allclose(s[:, 1], m + d / 2, atol=1e-10)
+
+
+def test_projection_per_axis_three_samples_slew_only():
+    # projection onto {|<w, s>| <= b} per axis with w = (1, -2, 1), |w|^2 = 6
+    a, b, L = 10.0, 0.02, 0.5
+    w = np.array([1.0, -2.0, 1.0])
+    for seed in range(4):
+        k = np.random.default_rng(seed).uniform(-0.2, 0.2, (3, 3))
+        s = oracle.project(k, 1, 3, L, a, b, -1, 10000, rotation_variant=True)
+        wk = k @ w
+        want = k - np.outer((wk - np.clip(wk, -b, b)) / 6.0, w)
+        np.testing.assert_allclose(s, want, atol=1e-10)
+
+
+def test_projection_per_axis_matches_a_generic_qp_solver():
+    """Each axis solved by SLSQP on the explicit linear constraints."""
+    from scipy.optimize import minimize
+    rng = np.random.default_rng(12)
+    Ns, a, b, L, te = 14, 0.06, 0.01, 0.5, 3
+    k = rng.uniform(-0.45, 0.45, (3, Ns))
+    k[:, 9] = [0.7, -0.8, 0.2]                    # outside the box too
+    s = oracle.project(k, 1, Ns, L, a, b, te, 200000, rotation_variant=True)
+    D1 = np.diff(np.eye(Ns), axis=0)
+    D2 = np.diff(np.eye(Ns), n=2, axis=0)
+    A = np.vstack([D1, -D1, D2, -D2])
+    c = np.concatenate([np.full(Ns - 1, a), np.full(Ns - 1, a), np.full(Ns - 2, b),
+                        np.full(Ns - 2, b)])
+    for ax in range(3):
+        e = np.zeros(Ns)
+        e[te] = 1.0
+        res = minimize(lambda x: 0.5 * np.sum((x - k[ax]) ** 2), np.zeros(Ns),
+                       jac=lambda x: x - k[ax], method="SLSQP",
+                       bounds=[(-L, L)] * Ns,
+                       constraints=[{"type": "ineq", "fun": lambda x: c - A @ x,
+                                     "jac": lambda x: -A},
+                                    {"type": "eq", "fun": lambda x: e @ x,
+                                     "jac": lambda x: e}],
+                       options={"ftol": 1e-15, "maxiter": 2000})
+        assert res.success, res.message
+        np.testing.assert_allclose(s[ax], res.x, atol=1e-9)
+    v = oracle.constraint_check(s, 1, Ns, L, a, b, te, rotation_variant=True)
+    assert v[0] <= 1 + 1e-6 and v[1] <= 1 + 1e-6 and v[2] <= 1 and v[3] == 0
+
+
+def test_projection_per_axis_is_separable():
+    # zeroing two axes of the input leaves the third axis' result unchanged
+    rng = np.random.default_rng(13)
+    Ns, a, b = 40, 0.05, 0.004
+    k = rng.uniform(-0.3, 0.3, (3, Ns))
+    full = oracle.project(k, 1, Ns, 0.5, a, b, 0, 3000, rotation_variant=True)
+    for ax in range(3):
+        only = np.zeros_like(k)
+        only[ax] = k[ax]
+        one = oracle.project(only, 1, Ns, 0.5, a, b, 0, 3000, rotation_variant=True)
+        assert np.array_equal(one[ax], full[ax])
+        assert not np.any(np.delete(one, ax, axis=0))
+
+
+def test_constraint_check_per_axis_values():
+    K = np.zeros((3, 4))
+    K[0] = [0.0, 0.1, 0.2, 0.25]
+    K[1] = [0.0, 0.1, 0.2, 0.15]
+    v2 = oracle.constraint_check(K, 1, 4, 0.5, 0.2, 0.1, 1)
+    vi = oracle.constraint_check(K, 1, 4, 0.5, 0.2, 0.1, 1, rotation_variant=True)
+    assert v2[0] == pytest.approx(np.hypot(0.1, 0.1) / 0.2)    # steps (0.1, 0.1)
+    assert vi[0] == pytest.approx(0.1 / 0.2)
+    assert v2[1] == pytest.approx(np.hypot(0.05, 0.15) / 0.1)  # second difference (-0.05, -0.15)
+    assert vi[1] == pytest.approx(0.15 / 0.1)
+    assert vi[2] == v2[2] == pytest.approx(0.5)
+    assert vi[3] == v2[3] == pytest.approx(np.hypot(0.1, 0.1))   # the TE sample's distance to 0
+
+
 def test_constraint_check_simple_values():
     K = np.zeros((3, 4))
     K[0] = [0.0, 0.1, 0.3, 0.3]
