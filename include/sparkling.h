@@ -76,7 +76,10 @@ typedef enum {
 } spk_precision;
 
 enum {
-    SPK_FLAG_DISCREPANCY = 1   /* sparkling_energy also returns D = F - E_rho          */
+    SPK_FLAG_DISCREPANCY = 1,        /* sparkling_energy also returns D = F - E_rho    */
+    SPK_FLAG_ROTATION_VARIANT = 2    /* constraint norms |.| are per-axis maxima (the
+                                        l_inf bounds of Sec. "3D K-space sampling")
+                                        instead of Euclidean norms                     */
 };
 
 typedef struct {
@@ -173,7 +176,9 @@ int sparkling_grad(const spk_params *prm, const void *kx, const void *ky, const 
  * argmin_{s in Q} |s - k|^2 / 2 with Q = {|s|_inf <= L, s[te] = 0,
  * |s[n+1] - s[n]| <= a_max, |s[n+2] - 2 s[n+1] + s[n]| <= b_max}, computed
  * by prm->n_pit iterations of accelerated proximal gradient on the dual
- * (step 1/20, cold start), all in double precision.  The box and the
+ * (step 1/20, cold start), all in double precision.  |.| is the Euclidean
+ * norm of a sample's 3 coordinates, or their largest magnitude when
+ * prm->flags has SPK_FLAG_ROTATION_VARIANT (per-axis hardware bounds).  The box and the
  * echo-time point hold exactly; a shot already strictly inside Q is
  * returned unchanged.  viol: host double[4] or NULL, receives the
  * constraint check of the result (see sparkling_constraint_check) and then
@@ -185,7 +190,9 @@ int sparkling_project(const spk_params *prm, void *kx, void *ky, void *kz, doubl
 /*
  * Normalised constraint violations of K (Sec. "3D K-space sampling"),
  * host double[4]: {max |s[n+1]-s[n]| / a_max, max |s[n+2]-2s[n+1]+s[n]| / b_max,
- * max |s|_inf / L, max_shots |s[te]|}; values <= 1 (resp. 0) are feasible.
+ * max |s|_inf / L, max_shots |s[te]|_2}; values <= 1 (resp. 0) are feasible.
+ * The first two use the norm that sparkling_project uses (per-axis maximum
+ * with SPK_FLAG_ROTATION_VARIANT, else Euclidean).
  * Computed in double from the stored values; NaN propagates.  Synchronises.
  */
 int sparkling_constraint_check(const spk_params *prm, const void *kx, const void *ky,

@@ -19,6 +19,7 @@ LIB_PATH = _PKG / "libsparkling.so"
 
 PRECISIONS = {"plain_fp64": 0, "fp32_comp": 1, "fp32_naive": 2, "fp32_acc64": 3}
 FLAG_DISCREPANCY = 1
+FLAG_ROTATION_VARIANT = 2
 KIND_REPULSION, KIND_ATTRACTION, KIND_PROJECTION, KIND_OTHER, KIND_INTERPOLATION = 0, 1, 2, 3, 4
 
 _i32, _i64, _dbl, _vp, _sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p, ctypes.c_size_t
@@ -99,6 +100,7 @@ class Params:
     te_index: int = 0
     n_pit: int = 200
     discrepancy: bool = False
+    rotation_variant: bool = False                   # per-axis speed/slew bounds
     attraction_field: "torch.Tensor | None" = None   # from attraction_field(); None = direct sum
     _c: SpkParams = field(default=None, repr=False, compare=False)
 
@@ -118,7 +120,9 @@ class Params:
                              f"4*(G+2)^3 {self.dtype} values")
         return SpkParams(self.n_shots, self.n_samples, self.grid, PRECISIONS[self.precision],
                          self.te_index, self.half_width, self.eps, self.a_max, self.b_max,
-                         self.n_pit, FLAG_DISCREPANCY if self.discrepancy else 0,
+                         self.n_pit,
+                         (FLAG_DISCREPANCY if self.discrepancy else 0)
+                         | (FLAG_ROTATION_VARIANT if self.rotation_variant else 0),
                          _vp(f.data_ptr()) if f is not None else None)
 
 

@@ -115,7 +115,7 @@ int check_params(const spk_params *prm, bool need_projection)
         return fail(SPK_EINVAL, "eps must be finite and >= 0");
     if (prm->te_index < -1 || prm->te_index >= prm->n_samples)
         return fail(SPK_EINVAL, "te_index must be -1 or in [0, n_samples)");
-    if (prm->flags & ~SPK_FLAG_DISCREPANCY)
+    if (prm->flags & ~(SPK_FLAG_DISCREPANCY | SPK_FLAG_ROTATION_VARIANT))
         return fail(SPK_EINVAL, "unknown flags 0x%x", prm->flags);
     if (prm->attraction_field &&
         reinterpret_cast<uintptr_t>(prm->attraction_field) % (4 * elt_size(prm->precision)))
@@ -359,7 +359,8 @@ int constraint_check_into(const spk_params *prm, const void *kx, const void *ky,
     Timed tm(SPK_KIND_OTHER, 0.0, s);
     SPK_HIP(launch_constraint_check(prm->precision, kx, ky, kz, prm->n_shots, prm->n_samples,
                                     prm->half_width, prm->a_max, prm->b_max, prm->te_index,
-                                    w.viol(), dev_out, s),
+                                    (prm->flags & SPK_FLAG_ROTATION_VARIANT) != 0, w.viol(),
+                                    dev_out, s),
             "constraint check");
     return SPK_OK;
 }
@@ -368,7 +369,8 @@ int project_in_place(const spk_params *prm, void *kx, void *ky, void *kz, hipStr
 {
     Timed tm(SPK_KIND_PROJECTION, 0.0, s);
     SPK_HIP(launch_project(prm->precision, kx, ky, kz, prm->n_shots, prm->n_samples,
-                           prm->half_width, prm->a_max, prm->b_max, prm->te_index, prm->n_pit, s),
+                           prm->half_width, prm->a_max, prm->b_max, prm->te_index, prm->n_pit,
+                           (prm->flags & SPK_FLAG_ROTATION_VARIANT) != 0, s),
             "projection");
     return SPK_OK;
 }

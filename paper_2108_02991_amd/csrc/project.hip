@@ -18,8 +18,10 @@
 //   t+ = (1 + sqrt(1 + 4 t^2)) / 2,     qh = q+ + ((t - 1)/t+)(q+ - q), same for r
 // and the output is P0(k - D1^T q - D2^T r) of the last dual iterate.  With
 // (D1 s)[n] = s[n+1] - s[n], (D2 s)[n] = s[n+2] - 2 s[n+1] + s[n] and
-// shrink(z, th) = z * max(0, 1 - th/|z|) per sample.  Floating-point
-// contraction is off and every expression keeps one fixed evaluation order.
+// shrink(z, th) = z * max(0, 1 - th/|z|) per sample (group soft threshold of
+// the 3-vector), or per coordinate for per-axis bounds, where the dual prox
+// acts on each axis on its own.  Floating-point contraction is off and every
+// expression keeps one fixed evaluation order.
 
 #include "spk_internal.h"
 
@@ -38,9 +40,17 @@ __device__ inline double shrink_factor(double z0, double z1, double z2, double t
     return (nrm > thr) ? (1.0 - thr / nrm) : 0.0;
 }
 
+__device__ inline double shrink_one(double z, double thr)
+{
+#pragma clang fp contract(off)
+    const double m = fabs(z);
+    return z * ((m > thr) ? (1.0 - thr / m) : 0.0);
+}
+
 template <typename T, int NPT>
 __global__ __launch_bounds__(512) void project_kernel(T *kx, T *ky, T *kz, int64_t Ns, double L,
-                                                     double a, double b, int64_t te, int n_pit)
+                                                     double a, double b, int64_t te, int n_pit,
+                                                     int per_axis)
 {
 #pragma clang fp contract(off)
     static_assert(NPT >= 2, "two-sample halo needs NPT >= 2");
@@ -138,12 +148,25 @@ __global__ __launch_bounds__(512) void project_kernel(T *kx, T *ky, T *kz, int64
                 zq[c] = qh[c][i] + tau * (s[c][i + 1] - s[c][i]);
                 zr[c] = rh[c][i] + tau * ((s[c][i + 2] - 2.0 * s[c][i + 1]) + s[c][i]);
             }
-            const double fq = shrink_factor(zq[0], zq[1], zq[2], thr_a);
-            const double fr = shrink_factor(zr[0], zr[1], zr[2], thr_b);
+            if (per_axis) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    zq[c] = shrink_one(zq[c], thr_a);
+                    zr[c] = shrink_one(zr[c], thr_b);
+                }
+            } else {
+                const double fq = shrink_factor(zq[0], zq[1], zq[2], thr_a);
+                const double fr = shrink_factor(zr[0], zr[1], zr[2], thr_b);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    zq[c] = zq[c] * fq;
+                    zr[c] = zr[c] * fr;
+                }
+            }
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                const double qn = (n <= Ns - 2) ? zq[c] * fq : 0.0;
-                const double rn = (n <= Ns - 3) ? zr[c] * fr : 0.0;
+                const double qn = (n <= Ns - 2) ? zq[c] : 0.0;
+                const double rn = (n <= Ns - 3) ? zr[c] : 0.0;
                 qh[c][i] = qn + mom * (qn - q[c][i]);
                 q[c][i] = qn;
                 rh[c][i] = rn + mom * (rn - r[c][i]);
@@ -179,10 +202,18 @@ __device__ inline double vmax(double m, double x)
 
 constexpr int CB = 256;
 
+__device__ inline double norm3(double dx, double dy, double dz, int per_axis)
+{
+#pragma clang fp contract(off)
+    if (per_axis)
+        return vmax(vmax(fabs(dx), fabs(dy)), fabs(dz));
+    return sqrt((dx * dx + dy * dy) + dz * dz);
+}
+
 template <typename T>
 __global__ __launch_bounds__(CB) void check_kernel(const T *kx, const T *ky, const T *kz,
                                                    int64_t Ns, double L, double a, double b,
-                                                   int64_t te, double *per_shot)
+                                                   int64_t te, int per_axis, double *per_shot)
 {
 #pragma clang fp contract(off)
     __shared__ double red[4][CB];
@@ -194,13 +225,13 @@ __global__ __launch_bounds__(CB) void check_kernel(const T *kx, const T *ky, con
         if (n + 1 < Ns) {
             const double dx = (double)x[n + 1] - x0, dy = (double)y[n + 1] - y0,
                          dz = (double)z[n + 1] - z0;
-            m[0] = vmax(m[0], sqrt((dx * dx + dy * dy) + dz * dz) / a);
+            m[0] = vmax(m[0], norm3(dx, dy, dz, per_axis) / a);
         }
         if (n + 2 < Ns) {
             const double dx = ((double)x[n + 2] - 2.0 * (double)x[n + 1]) + x0;
             const double dy = ((double)y[n + 2] - 2.0 * (double)y[n + 1]) + y0;
             const double dz = ((double)z[n + 2] - 2.0 * (double)z[n + 1]) + z0;
-            m[1] = vmax(m[1], sqrt((dx * dx + dy * dy) + dz * dz) / b);
+            m[1] = vmax(m[1], norm3(dx, dy, dz, per_axis) / b);
         }
         m[2] = vmax(m[2], fabs(x0) / L);
         m[2] = vmax(m[2], fabs(y0) / L);
@@ -249,57 +280,62 @@ __global__ __launch_bounds__(CB) void check_final_kernel(const double *per_shot,
 
 template <typename T, int NPT>
 hipError_t launch_project_npt(T *kx, T *ky, T *kz, int64_t n_shots, int64_t Ns, double L,
-                              double a, double b, int64_t te, int n_pit, hipStream_t s)
+                              double a, double b, int64_t te, int n_pit, int per_axis,
+                              hipStream_t s)
 {
     int64_t nth = (Ns + NPT - 1) / NPT;
     nth = (nth + 63) / 64 * 64;
     const size_t lds = sizeof(double) * 15 * (size_t)nth;
     hipLaunchKernelGGL((project_kernel<T, NPT>), dim3((unsigned)n_shots), dim3((unsigned)nth), lds,
-                       s, kx, ky, kz, Ns, L, a, b, te, n_pit);
+                       s, kx, ky, kz, Ns, L, a, b, te, n_pit, per_axis);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_project_t(T *kx, T *ky, T *kz, int64_t n_shots, int64_t Ns, double L, double a,
-                            double b, int64_t te, int n_pit, hipStream_t s)
+                            double b, int64_t te, int n_pit, int per_axis, hipStream_t s)
 {
     // at most 512 threads per shot: the halo buffers (15 doubles per thread)
     // stay under 64 KB of LDS
     if (Ns <= 2 * 512)
-        return launch_project_npt<T, 2>(kx, ky, kz, n_shots, Ns, L, a, b, te, n_pit, s);
+        return launch_project_npt<T, 2>(kx, ky, kz, n_shots, Ns, L, a, b, te, n_pit,
+                                            per_axis, s);
     if (Ns <= 4 * 512)
-        return launch_project_npt<T, 4>(kx, ky, kz, n_shots, Ns, L, a, b, te, n_pit, s);
-    return launch_project_npt<T, 8>(kx, ky, kz, n_shots, Ns, L, a, b, te, n_pit, s);
+        return launch_project_npt<T, 4>(kx, ky, kz, n_shots, Ns, L, a, b, te, n_pit,
+                                            per_axis, s);
+    return launch_project_npt<T, 8>(kx, ky, kz, n_shots, Ns, L, a, b, te, n_pit,
+                                            per_axis, s);
 }
 
 }  // namespace
 
 hipError_t launch_project(int precision, void *kx, void *ky, void *kz, int64_t n_shots,
                           int64_t n_samples, double L, double a, double b, int64_t te, int n_pit,
-                          hipStream_t s)
+                          bool per_axis, hipStream_t s)
 {
     if (n_samples > kMaxProjectSamples)
         return hipErrorInvalidValue;
     if (precision == SPK_PLAIN_FP64)
         return launch_project_t((double *)kx, (double *)ky, (double *)kz, n_shots, n_samples, L,
-                                a, b, te, n_pit, s);
+                                a, b, te, n_pit, per_axis ? 1 : 0, s);
     return launch_project_t((float *)kx, (float *)ky, (float *)kz, n_shots, n_samples, L, a, b,
-                            te, n_pit, s);
+                            te, n_pit, per_axis ? 1 : 0, s);
 }
 
 hipError_t launch_constraint_check(int precision, const void *kx, const void *ky, const void *kz,
                                    int64_t n_shots, int64_t n_samples, double L, double a,
-                                   double b, int64_t te, double *per_shot, double *out,
-                                   hipStream_t s)
+                                   double b, int64_t te, bool per_axis, double *per_shot,
+                                   double *out, hipStream_t s)
 {
+    const int pa = per_axis ? 1 : 0;
     if (precision == SPK_PLAIN_FP64)
         hipLaunchKernelGGL(check_kernel<double>, dim3((unsigned)n_shots), dim3(CB), 0, s,
                            (const double *)kx, (const double *)ky, (const double *)kz, n_samples,
-                           L, a, b, te, per_shot);
+                           L, a, b, te, pa, per_shot);
     else
         hipLaunchKernelGGL(check_kernel<float>, dim3((unsigned)n_shots), dim3(CB), 0, s,
                            (const float *)kx, (const float *)ky, (const float *)kz, n_samples, L,
-                           a, b, te, per_shot);
+                           a, b, te, pa, per_shot);
     hipLaunchKernelGGL(check_final_kernel, dim3(1), dim3(CB), 0, s, per_shot, n_shots, out);
     return hipGetLastError();
 }

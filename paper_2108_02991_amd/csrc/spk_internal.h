@@ -123,14 +123,15 @@ hipError_t launch_axpy_save(int precision, void *kx, void *ky, void *kz, void *k
 hipError_t launch_upsample(int precision, const void *kx, const void *ky, const void *kz, void *fx,
                            void *fy, void *fz, int64_t Nc, int64_t N, hipStream_t s);
 
-// Projection and constraint check (one block per shot).
+// Projection and constraint check (one block per shot).  per_axis selects the
+// per-axis maximum instead of the Euclidean norm in the speed and slew bounds.
 hipError_t launch_project(int precision, void *kx, void *ky, void *kz, int64_t n_shots,
                           int64_t n_samples, double L, double a, double b, int64_t te,
-                          int n_pit, hipStream_t s);
+                          int n_pit, bool per_axis, hipStream_t s);
 // per_shot: n_shots*4 doubles; out: 4 doubles.
 hipError_t launch_constraint_check(int precision, const void *kx, const void *ky, const void *kz,
                                    int64_t n_shots, int64_t n_samples, double L, double a,
-                                   double b, int64_t te, double *per_shot, double *out,
-                                   hipStream_t s);
+                                   double b, int64_t te, bool per_axis, double *per_shot,
+                                   double *out, hipStream_t s);
 
 }  // namespace spk

@@ -24,14 +24,14 @@ from . import api, configs
 
 
 def run(workload: configs.Workload, precision: str, iters: int, device="cuda:0",
-        out=None, log_every: int = 1):
+        out=None, log_every: int = 1, rotation_variant: bool = False):
     """Runs `iters` projected gradient steps; returns the list of records."""
     dev = torch.device(device)
     a, b = api.alpha_beta(configs.GMAX, configs.SMAX, configs.RASTER_DT, configs.DWELL_DT,
                           workload.fov, workload.kmax, configs.GAMMA_BAR, workload.half_width)
     prm = api.Params(workload.n_shots, workload.n_samples, workload.grid, precision=precision,
                      half_width=workload.half_width, a_max=a, b_max=b, te_index=0,
-                     n_pit=workload.n_pit)
+                     n_pit=workload.n_pit, rotation_variant=rotation_variant)
     K = torch.tensor(workload.trajectory(), dtype=prm.dtype, device=dev)
     rho = torch.tensor(workload.density(), dtype=prm.dtype, device=dev)
     viol0 = api.project_(K, prm)
@@ -87,6 +87,7 @@ def multiresolution(K0: torch.Tensor, rho: torch.Tensor, prm_full: api.Params, l
                          half_width=prm_full.half_width, eps=prm_full.eps,
                          a_max=prm_full.a_max * 2.0 ** d, b_max=prm_full.b_max * 2.0 ** d,
                          te_index=prm_full.te_index, n_pit=prm_full.n_pit,
+                         rotation_variant=prm_full.rotation_variant,
                          attraction_field=prm_full.attraction_field)
         if K.shape[1] != prm.p:
             raise ValueError(f"level {d}: K has {K.shape[1]} samples, expected {prm.p}")
@@ -124,6 +125,8 @@ def main():
                     help="run Algorithm 1 with this many decimation levels (0 = single level)")
     ap.add_argument("--field", action="store_true",
                     help="evaluate the attraction by the grid interpolant")
+    ap.add_argument("--rotation-variant", action="store_true",
+                    help="per-axis gradient and slew bounds instead of Euclidean ones")
     args = ap.parse_args()
     w = configs.WORKLOADS[args.workload]
     precision = args.precision or w.precision
@@ -132,7 +135,8 @@ def main():
     out = open(args.out, "a") if args.out else None
     try:
         if args.levels == 0 and not args.field:
-            run(w, precision, iters, out=out, log_every=args.log_every)
+            run(w, precision, iters, out=out, log_every=args.log_every,
+                rotation_variant=args.rotation_variant)
         else:
             dev = torch.device("cuda:0")
             a, b = api.alpha_beta(configs.GMAX, configs.SMAX, configs.RASTER_DT,
@@ -140,7 +144,7 @@ def main():
                                   w.half_width)
             prm = api.Params(w.n_shots, w.n_samples, w.grid, precision=precision,
                              half_width=w.half_width, a_max=a, b_max=b, te_index=0,
-                             n_pit=w.n_pit)
+                             n_pit=w.n_pit, rotation_variant=args.rotation_variant)
             from . import inputs
             K0 = inputs.radial_spokes(w.n_shots, w.n_samples >> args.levels, w.half_width,
                                       w.seed, w.jitter)

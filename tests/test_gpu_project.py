@@ -116,3 +116,43 @@ def test_constraint_check_bitwise(gpu):
     Kd, _ = device_problem(K, [1.0], "plain_fp64", gpu)
     prm = spk.Params(Nc, Ns, 1, precision="plain_fp64", a_max=0.07, b_max=0.011)
     assert np.isnan(spk.constraint_check(Kd, prm)[:3]).all()
+
+
+@pytest.mark.parametrize("precision,Ns", [("plain_fp64", 3), ("plain_fp64", 1025),
+                                          ("fp32_comp", 1024)])
+def test_per_axis_projection_bitwise(gpu, precision, Ns):
+    """Rotation-variant bounds: per-coordinate dual prox, per-axis check."""
+    Nc = 6
+    K = inputs.radial_spokes(Nc, Ns, 0.5, seed=Ns + 1, jitter=0.05)
+    a, b = bounds(configs.C5)
+    prm = spk.Params(Nc, Ns, 1, precision=precision, a_max=a, b_max=b, te_index=0, n_pit=200,
+                     rotation_variant=True)
+    Kd, _ = device_problem(K, [1.0], precision, gpu)
+    K_in = host64(Kd)
+    say(f"  per-axis project {precision} Nc={Nc} Ns={Ns}")
+    viol = spk.project_(Kd, prm)
+    got = host64(Kd)
+    ref = oracle.project(K_in, Nc, Ns, 0.5, a, b, 0, 200, rotation_variant=True)
+    if precision == "fp32_comp":
+        ref = ref.astype(np.float32).astype(np.float64)
+    assert np.array_equal(got, ref), np.abs(got - ref).max()
+    want = oracle.constraint_check(got, Nc, Ns, 0.5, a, b, 0, rotation_variant=True)
+    assert np.array_equal(viol, want)
+    # the Euclidean form gives a different result on the same input
+    prm.rotation_variant = False
+    Kd2, _ = device_problem(K, [1.0], precision, gpu)
+    spk.project_(Kd2, prm)
+    assert not np.array_equal(host64(Kd2), got)
+
+
+def test_per_axis_constraint_check_bitwise(gpu):
+    rng = np.random.default_rng(21)
+    Nc, Ns = 17, 130
+    K = rng.uniform(-0.6, 0.6, (3, Nc * Ns))
+    prm = spk.Params(Nc, Ns, 1, precision="plain_fp64", a_max=0.07, b_max=0.011, te_index=3,
+                     rotation_variant=True)
+    Kd, _ = device_problem(K, [1.0], "plain_fp64", gpu)
+    got = spk.constraint_check(Kd, prm)
+    want = oracle.constraint_check(K, Nc, Ns, 0.5, 0.07, 0.011, 3, rotation_variant=True)
+    assert np.array_equal(got, want)
+    assert not np.array_equal(got, oracle.constraint_check(K, Nc, Ns, 0.5, 0.07, 0.011, 3))

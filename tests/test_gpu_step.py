@@ -85,3 +85,23 @@ def test_nonfinite_energy_reported(gpu):
     with pytest.raises(spk.SparklingError) as e:
         spk.step_(Kd, rd, prm, state, 0, 1.0)
     assert e.value.status == -5
+
+
+def test_per_axis_steps_plain_fp64(gpu):
+    """Three projected steps with rotation-variant bounds against the oracle."""
+    w = configs.C1
+    K, rho = w.trajectory(), w.density()
+    a, b = bounds(w)
+    prm = params_for(w, "plain_fp64")
+    prm.rotation_variant = True
+    Kd, rd = device_problem(K, rho, "plain_fp64", gpu)
+    state = spk.StepState(prm, gpu)
+    Ko, kp, gp = K.copy(), np.zeros_like(K), np.zeros_like(K)
+    for it in range(3):
+        say(f"  c1 per-axis step {it}")
+        info = spk.step_(Kd, rd, prm, state, it, w.eta_fixed)
+        Ko, kp, gp, oinfo = oracle.step(Ko, rho, w.n_shots, w.n_samples, w.grid, 0.5, a, b, 0,
+                                        w.n_pit, kp, gp, it, w.eta_fixed, rotation_variant=True)
+        assert info["F"] == pytest.approx(oinfo["F"], rel=1e-12)
+        assert np.abs(host64(Kd) - Ko).max() <= 1e-10
+        np.testing.assert_allclose(info["viol"], oinfo["viol"], rtol=1e-8)
