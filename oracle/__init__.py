@@ -27,6 +27,7 @@ _lib = None
 
 _i64 = ctypes.c_int64
 _dbl = ctypes.c_double
+_int = ctypes.c_int
 _p = ctypes.c_void_p
 
 
@@ -47,28 +48,36 @@ def _load():
         build()
         lib = ctypes.CDLL(str(_LIB))
         for name, args in {
-            "orc_grad": [_i64, _p, _p, _p, _i64, _dbl, _p, _dbl, _i64, _p, _p, _p, _p, _p, _p],
-            "orc_energy": [_i64, _p, _p, _p, _i64, _dbl, _p, _dbl, _p],
-            "orc_rho_self_energy": [_i64, _dbl, _p, _dbl, _p],
+            "orc_grad": [_i64, _p, _p, _p, _i64, _dbl, _p, _dbl, _int, _i64, _p, _p, _p, _p, _p, _p],
+            "orc_energy": [_i64, _p, _p, _p, _i64, _dbl, _p, _dbl, _int, _p],
+            "orc_rho_self_energy": [_i64, _dbl, _p, _dbl, _int, _p],
             "orc_alpha_beta": [_dbl] * 8 + [_p, _p],
             "orc_project": [_i64, _i64, _p, _p, _p, _dbl, _dbl, _dbl, _i64, ctypes.c_int,
                             ctypes.c_int],
             "orc_constraint_check": [_i64, _i64, _p, _p, _p, _dbl, _dbl, _dbl, _i64, ctypes.c_int,
                                      _p],
-            "orc_step": [_i64, _i64, _p, _i64, _dbl, _p, _dbl, _dbl, _dbl, _i64, ctypes.c_int,
-                         ctypes.c_int, _p, _p, _i64, _dbl, _p],
-            "orc_fd_directional": [_i64, _p, _p, _p, _i64, _dbl, _p, _dbl, _p, _dbl, _p],
+            "orc_step": [_i64, _i64, _p, _i64, _dbl, _p, _dbl, _int, _dbl, _dbl, _i64, _int, _int,
+                         _p, _p, _i64, _dbl, _p],
+            "orc_fd_directional": [_i64, _p, _p, _p, _i64, _dbl, _p, _dbl, _int, _p, _dbl, _p],
             "orc_num_threads": [],
             "orc_upsample": [_i64, _i64, _p, _p],
-            "orc_field": [_i64, _dbl, _p, _dbl, _p],
+            "orc_field": [_i64, _dbl, _p, _dbl, _int, _p],
             "orc_interpolate": [_i64, _dbl, _p, _i64, _p, _p, _p, _p],
-            "orc_grad_field": [_i64, _p, _p, _p, _i64, _dbl, _p, _dbl, _i64, _p, _p, _p, _p, _p, _p],
+            "orc_grad_field": [_i64, _p, _p, _p, _i64, _dbl, _p, _dbl, _int, _i64, _p, _p, _p, _p, _p, _p],
         }.items():
             f = getattr(lib, name)
             f.argtypes = args
             f.restype = ctypes.c_int
         _lib = lib
     return _lib
+
+
+KERNELS = {"distance": 0, "log": 1}
+
+
+def _kern(name: str) -> int:
+    """Kernel selector: "distance" H = sqrt(|d|^2 + eps^2); "log" H = log(|d|^2 + eps^2) / 2."""
+    return KERNELS[name]
 
 
 def _f64(a) -> np.ndarray:
@@ -88,7 +97,7 @@ def num_threads() -> int:
     return _load().orc_num_threads()
 
 
-def grad(K, rho, G: int, L: float, eps: float = 0.0, targets=None):
+def grad(K, rho, G: int, L: float, eps: float = 0.0, targets=None, kernel: str = "distance"):
     """Gradient of F at the listed targets (all if None).
 
     Returns dict with dF, dFa, dFr of shape (3, n_t) and the unscaled
@@ -104,27 +113,28 @@ def grad(K, rho, G: int, L: float, eps: float = 0.0, targets=None):
     dF, dFa, dFr = (np.empty((3, n_t)) for _ in range(3))
     ua, ur = np.empty(n_t), np.empty(n_t)
     x, y, z = (np.ascontiguousarray(K[c]) for c in range(3))
-    rc = _load().orc_grad(p, _ptr(x), _ptr(y), _ptr(z), G, L, _ptr(rho), eps, n_t,
-                          _ptr(targets), _ptr(dF), _ptr(dFa), _ptr(dFr), _ptr(ua), _ptr(ur))
+    rc = _load().orc_grad(p, _ptr(x), _ptr(y), _ptr(z), G, L, _ptr(rho), eps, _kern(kernel),
+                          n_t, _ptr(targets), _ptr(dF), _ptr(dFa), _ptr(dFr), _ptr(ua), _ptr(ur))
     _check(rc, "grad")
     return {"dF": dF, "dFa": dFa, "dFr": dFr, "ua": ua, "ur": ur, "targets": targets}
 
 
-def energy(K, rho, G: int, L: float, eps: float = 0.0):
+def energy(K, rho, G: int, L: float, eps: float = 0.0, kernel: str = "distance"):
     """(F, Fa, Fr) of the objective."""
     K = _f64(K)
     rho = _f64(rho)
     out = np.empty(3)
     x, y, z = (np.ascontiguousarray(K[c]) for c in range(3))
-    rc = _load().orc_energy(K.shape[1], _ptr(x), _ptr(y), _ptr(z), G, L, _ptr(rho), eps, _ptr(out))
+    rc = _load().orc_energy(K.shape[1], _ptr(x), _ptr(y), _ptr(z), G, L, _ptr(rho), eps,
+                            _kern(kernel), _ptr(out))
     _check(rc, "energy")
     return tuple(float(v) for v in out)
 
 
-def rho_self_energy(rho, G: int, L: float, eps: float = 0.0) -> float:
+def rho_self_energy(rho, G: int, L: float, eps: float = 0.0, kernel: str = "distance") -> float:
     rho = _f64(rho)
     out = np.empty(1)
-    _check(_load().orc_rho_self_energy(G, L, _ptr(rho), eps, _ptr(out)), "rho_self_energy")
+    _check(_load().orc_rho_self_energy(G, L, _ptr(rho), eps, _kern(kernel), _ptr(out)), "rho_self_energy")
     return float(out[0])
 
 
@@ -158,15 +168,15 @@ def constraint_check(K, n_shots: int, n_samples: int, L: float, a: float, b: flo
 
 
 def step(K, rho, n_shots, n_samples, G, L, a, b, te, n_pit, k_prev, g_prev, it, eta_fixed,
-         eps: float = 0.0, rotation_variant: bool = False):
+         eps: float = 0.0, rotation_variant: bool = False, kernel: str = "distance"):
     """One projected gradient step.  Returns (K_new, k_prev, g_prev, info dict)."""
     K = _f64(K).copy()
     k_prev = _f64(k_prev).copy()
     g_prev = _f64(g_prev).copy()
     rho = _f64(rho)
     info = np.empty(10)
-    rc = _load().orc_step(n_shots, n_samples, _ptr(K), G, L, _ptr(rho), eps, a, b, te, n_pit,
-                          int(rotation_variant), _ptr(k_prev), _ptr(g_prev), it, eta_fixed,
+    rc = _load().orc_step(n_shots, n_samples, _ptr(K), G, L, _ptr(rho), eps, _kern(kernel), a, b,
+                          te, n_pit, int(rotation_variant), _ptr(k_prev), _ptr(g_prev), it, eta_fixed,
                           _ptr(info))
     _check(rc, "step")
     d = {"eta": info[0], "F": info[1], "Fa": info[2], "Fr": info[3],
@@ -174,7 +184,7 @@ def step(K, rho, n_shots, n_samples, G, L, a, b, te, n_pit, k_prev, g_prev, it, 
     return K, k_prev, g_prev, d
 
 
-def fd_directional(K, rho, G, L, delta, h, eps: float = 0.0) -> float:
+def fd_directional(K, rho, G, L, delta, h, eps: float = 0.0, kernel: str = "distance") -> float:
     """(F(K + h delta) - F(K - h delta)) / (2h), cancellation-free."""
     K = _f64(K)
     rho = _f64(rho)
@@ -182,16 +192,16 @@ def fd_directional(K, rho, G, L, delta, h, eps: float = 0.0) -> float:
     out = np.empty(1)
     x, y, z = (np.ascontiguousarray(K[c]) for c in range(3))
     rc = _load().orc_fd_directional(K.shape[1], _ptr(x), _ptr(y), _ptr(z), G, L, _ptr(rho),
-                                    eps, _ptr(delta), h, _ptr(out))
+                                    eps, _kern(kernel), _ptr(delta), h, _ptr(out))
     _check(rc, "fd_directional")
     return float(out[0])
 
 
-def field(rho, G: int, L: float, eps: float = 0.0) -> np.ndarray:
+def field(rho, G: int, L: float, eps: float = 0.0, kernel: str = "distance") -> np.ndarray:
     """Node field of the grid attraction, shape ((G+2)^3, 4): U, dU/dx, dU/dy, dU/dz."""
     rho = _f64(rho)
     out = np.empty(((G + 2) ** 3, 4))
-    _check(_load().orc_field(G, L, _ptr(rho), eps, _ptr(out)), "field")
+    _check(_load().orc_field(G, L, _ptr(rho), eps, _kern(kernel), _ptr(out)), "field")
     return out
 
 
@@ -207,7 +217,8 @@ def interpolate(node_field, G: int, L: float, P) -> np.ndarray:
     return out
 
 
-def grad_field(K, rho, G: int, L: float, eps: float = 0.0, targets=None):
+def grad_field(K, rho, G: int, L: float, eps: float = 0.0, targets=None,
+               kernel: str = "distance"):
     """Gradient with the grid attraction (node field + trilinear interpolant) at targets."""
     K = _f64(K)
     rho = _f64(rho)
@@ -219,8 +230,8 @@ def grad_field(K, rho, G: int, L: float, eps: float = 0.0, targets=None):
     dF, dFa, dFr = (np.empty((3, n_t)) for _ in range(3))
     ua, ur = np.empty(n_t), np.empty(n_t)
     x, y, z = (np.ascontiguousarray(K[c]) for c in range(3))
-    rc = _load().orc_grad_field(p, _ptr(x), _ptr(y), _ptr(z), G, L, _ptr(rho), eps, n_t,
-                                _ptr(targets), _ptr(dF), _ptr(dFa), _ptr(dFr), _ptr(ua), _ptr(ur))
+    rc = _load().orc_grad_field(p, _ptr(x), _ptr(y), _ptr(z), G, L, _ptr(rho), eps, _kern(kernel),
+                                n_t, _ptr(targets), _ptr(dF), _ptr(dFa), _ptr(dFr), _ptr(ua), _ptr(ur))
     _check(rc, "grad_field")
     return {"dF": dF, "dFa": dFa, "dFr": dFr, "ua": ua, "ur": ur, "targets": targets}
 
@@ -234,7 +245,7 @@ def upsample(K, n_shots: int, n_samples: int) -> np.ndarray:
 
 
 def multiresolution(K0, rho, n_shots, n_samples_coarse, levels, G, L, a, b, te, n_pit, n_git,
-                    eta_scale=0.25, final_level=True, eps=0.0):
+                    eta_scale=0.25, final_level=True, eps=0.0, kernel="distance"):
     """Algorithm 1: projected gradient iterations on decimated shots, warm restart by
     linear up-sampling, bounds halved per level.  K0 holds the coarsest shots
     (n_samples_coarse each); a, b are the full-resolution per-raster bounds, scaled
@@ -249,7 +260,7 @@ def multiresolution(K0, rho, n_shots, n_samples_coarse, levels, G, L, a, b, te, 
         kp, gp = np.zeros_like(K), np.zeros_like(K)
         for it in range(n_git):
             K, kp, gp, info = step(K, rho, n_shots, Ns, G, L, ad, bd, te, n_pit, kp, gp, it, eta,
-                                   eps)
+                                   eps, kernel=kernel)
             recs.append(dict(level=d, iter=it, **info))
         if d > 0:
             K = upsample(K, n_shots, Ns)

@@ -12,7 +12,9 @@
  * Definitions followed (all from the paper's Theory section):
  *   - objective F = F^a - F^r ("3D SPARKLING formulation": attraction term
  *     F^a = (1/p) sum_i integral H(x - K[i]) rho(x) dx, repulsion term
- *     F^r = 1/(2p^2) sum_{i,j} H(K[i] - K[j]), H = Euclidean norm);
+ *     F^r = 1/(2p^2) sum_{i,j} H(K[i] - K[j]), H = Euclidean norm, or the
+ *     logarithm of the norm that the same section names as an alternative,
+ *     regularised by eps > 0);
  *   - the attraction integral taken over the discretised density (Sec.
  *     "Evaluating F^a and its gradient": rho sampled on a grid), evaluated as
  *     the direct weighted sum over grid cells;
@@ -68,23 +70,41 @@ static double cs_get(const csum *a) { return a->s + a->c; }
 
 /* ------------------------------------------------------------------ */
 /* Kernel H and its gradient.                                          */
-/* H(d) = |d|_2 (eps = 0) or sqrt(|d|^2 + eps^2) (regularised kernel of */
-/* Sec. "Choice of step size").  grad H(d) = d / H(d), and 0 at d = 0.  */
+/* kern = 0 (distance): H(d) = |d|_2 (eps = 0) or sqrt(|d|^2 + eps^2)  */
+/*   (regularised kernel of Sec. "Choice of step size");               */
+/*   grad H(d) = d / H(d), and 0 at d = 0.                             */
+/* kern = 1 (logarithmic, the alternative kernel the "3D SPARKLING      */
+/*   formulation" mentions), regularised: H(d) = log sqrt(|d|^2 + eps^2) */
+/*   = log(|d|^2 + eps^2) / 2, grad H(d) = d / (|d|^2 + eps^2); eps > 0. */
 /* ------------------------------------------------------------------ */
-static double kernel_h(double dx, double dy, double dz, double eps)
+static int bad_kernel(double eps, int kern)
 {
-    return sqrt(dx * dx + dy * dy + dz * dz + eps * eps);
+    if (!(eps >= 0.0))
+        return 1;
+    if (kern == 0)
+        return 0;
+    return kern != 1 || !(eps > 0.0);
 }
 
-static void kernel_grad(double dx, double dy, double dz, double eps, double out[3])
+static double kernel_h(double dx, double dy, double dz, double eps, int kern)
 {
-    double h = kernel_h(dx, dy, dz, eps);
-    if (h == 0.0) {
+    double s = dx * dx + dy * dy + dz * dz + eps * eps;
+    return kern == 1 ? 0.5 * log(s) : sqrt(s);
+}
+
+static void kernel_grad(double dx, double dy, double dz, double eps, int kern, double out[3])
+{
+    double den;
+    if (kern == 1)
+        den = dx * dx + dy * dy + dz * dz + eps * eps;
+    else
+        den = kernel_h(dx, dy, dz, eps, kern);
+    if (den == 0.0) {
         out[0] = out[1] = out[2] = 0.0;
     } else {
-        out[0] = dx / h;
-        out[1] = dy / h;
-        out[2] = dz / h;
+        out[0] = dx / den;
+        out[1] = dy / den;
+        out[2] = dz / den;
     }
 }
 
@@ -103,7 +123,7 @@ static double cell_centre(int64_t idx, int64_t G, double L)
 /* Component c of target t is stored at [c * n_t + t].                   */
 /* ------------------------------------------------------------------ */
 static void target_sums(int64_t p, const double *kx, const double *ky, const double *kz,
-                        int64_t G, double L, const double *rho, double eps,
+                        int64_t G, double L, const double *rho, double eps, int kern,
                         int64_t i, double *ua, double ga[3], double *ur, double gr[3])
 {
     csum sa = {0, 0}, sr = {0, 0};
@@ -119,8 +139,8 @@ static void target_sums(int64_t p, const double *kx, const double *ky, const dou
                 double xv = cell_centre(ix, G, L);
                 double w = rho[ix + G * (iy + G * iz)];
                 double dx = xi - xv, dy = yi - yv, dz = zi - zv;
-                cs_add(&sa, w * kernel_h(dx, dy, dz, eps));
-                kernel_grad(dx, dy, dz, eps, g);
+                cs_add(&sa, w * kernel_h(dx, dy, dz, eps, kern));
+                kernel_grad(dx, dy, dz, eps, kern, g);
                 for (int c = 0; c < 3; ++c)
                     cs_add(&a3[c], w * g[c]);
             }
@@ -128,8 +148,8 @@ static void target_sums(int64_t p, const double *kx, const double *ky, const dou
     }
     for (int64_t j = 0; j < p; ++j) {
         double dx = xi - kx[j], dy = yi - ky[j], dz = zi - kz[j];
-        cs_add(&sr, kernel_h(dx, dy, dz, eps));
-        kernel_grad(dx, dy, dz, eps, g);
+        cs_add(&sr, kernel_h(dx, dy, dz, eps, kern));
+        kernel_grad(dx, dy, dz, eps, kern, g);
         for (int c = 0; c < 3; ++c)
             cs_add(&r3[c], g[c]);
     }
@@ -153,11 +173,11 @@ static void target_sums(int64_t p, const double *kx, const double *ky, const dou
  * [c * n_t + t].
  */
 int orc_grad(int64_t p, const double *kx, const double *ky, const double *kz,
-             int64_t G, double L, const double *rho, double eps,
+             int64_t G, double L, const double *rho, double eps, int kern,
              int64_t n_t, const int64_t *targets,
              double *dF, double *dFa, double *dFr, double *ua, double *ur)
 {
-    if (p < 1 || G < 1 || n_t < 0 || !kx || !ky || !kz || !rho || !targets || eps < 0.0)
+    if (p < 1 || G < 1 || n_t < 0 || !kx || !ky || !kz || !rho || !targets || bad_kernel(eps, kern))
         return -1;
     for (int64_t t = 0; t < n_t; ++t)
         if (targets[t] < 0 || targets[t] >= p)
@@ -167,7 +187,7 @@ int orc_grad(int64_t p, const double *kx, const double *ky, const double *kz,
 #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t t = 0; t < n_t; ++t) {
         double a, r, ga[3], gr[3];
-        target_sums(p, kx, ky, kz, G, L, rho, eps, targets[t], &a, ga, &r, gr);
+        target_sums(p, kx, ky, kz, G, L, rho, eps, kern, targets[t], &a, ga, &r, gr);
         for (int c = 0; c < 3; ++c) {
             double fa = ga[c] * inv_p, fr = gr[c] * inv_p2;
             if (dFa) dFa[c * n_t + t] = fa;
@@ -188,9 +208,9 @@ int orc_grad(int64_t p, const double *kx, const double *ky, const double *kz,
  * out[0..2] = F, Fa, Fr.
  */
 int orc_energy(int64_t p, const double *kx, const double *ky, const double *kz,
-               int64_t G, double L, const double *rho, double eps, double out[3])
+               int64_t G, double L, const double *rho, double eps, int kern, double out[3])
 {
-    if (p < 1 || G < 1 || !kx || !ky || !kz || !rho || !out || eps < 0.0)
+    if (p < 1 || G < 1 || !kx || !ky || !kz || !rho || !out || bad_kernel(eps, kern))
         return -1;
     double *ua = malloc(sizeof(double) * p), *ur = malloc(sizeof(double) * p);
     int64_t *idx = malloc(sizeof(int64_t) * p);
@@ -200,7 +220,7 @@ int orc_energy(int64_t p, const double *kx, const double *ky, const double *kz,
     }
     for (int64_t i = 0; i < p; ++i)
         idx[i] = i;
-    orc_grad(p, kx, ky, kz, G, L, rho, eps, p, idx, NULL, NULL, NULL, ua, ur);
+    orc_grad(p, kx, ky, kz, G, L, rho, eps, kern, p, idx, NULL, NULL, NULL, ua, ur);
     csum sa = {0, 0}, sr = {0, 0};
     for (int64_t i = 0; i < p; ++i) {
         cs_add(&sa, ua[i]);
@@ -220,9 +240,9 @@ int orc_energy(int64_t p, const double *kx, const double *ky, const double *kz,
  * H(x_u - x_v).  F - E_rho is the non-negative discrepancy between the
  * sample measure and rho (H = |.| is conditionally negative definite).
  */
-int orc_rho_self_energy(int64_t G, double L, const double *rho, double eps, double *out)
+int orc_rho_self_energy(int64_t G, double L, const double *rho, double eps, int kern, double *out)
 {
-    if (G < 1 || !rho || !out || eps < 0.0)
+    if (G < 1 || !rho || !out || bad_kernel(eps, kern))
         return -1;
     int64_t M = G * G * G;
     double *row = malloc(sizeof(double) * M);
@@ -238,7 +258,7 @@ int orc_rho_self_energy(int64_t G, double L, const double *rho, double eps, doub
             double xv = cell_centre(v % G, G, L);
             double yv = cell_centre((v / G) % G, G, L);
             double zv = cell_centre(v / (G * G), G, L);
-            cs_add(&s, rho[v] * kernel_h(xu - xv, yu - yv, zu - zv, eps));
+            cs_add(&s, rho[v] * kernel_h(xu - xv, yu - yv, zu - zv, eps, kern));
         }
         row[u] = rho[u] * cs_get(&s);
     }
@@ -503,7 +523,7 @@ int orc_constraint_check(int64_t Nc, int64_t Ns, const double *kx, const double 
  * info_out[0..9] = eta, F, Fa, Fr, viol[0..3], bb_used, (unused 0).
  */
 int orc_step(int64_t Nc, int64_t Ns, double *K, int64_t G, double L, const double *rho,
-             double eps, double a, double b, int64_t te, int n_pit, int rv,
+             double eps, int kern, double a, double b, int64_t te, int n_pit, int rv,
              double *k_prev, double *g_prev, int64_t iter, double eta_fixed,
              double info_out[10])
 {
@@ -520,7 +540,7 @@ int orc_step(int64_t Nc, int64_t Ns, double *K, int64_t G, double L, const doubl
     }
     for (int64_t i = 0; i < p; ++i)
         idx[i] = i;
-    int rc = orc_grad(p, K, K + p, K + 2 * p, G, L, rho, eps, p, idx, g, NULL, NULL, ua, ur);
+    int rc = orc_grad(p, K, K + p, K + 2 * p, G, L, rho, eps, kern, p, idx, g, NULL, NULL, ua, ur);
     if (rc) {
         free(g); free(idx); free(ua); free(ur);
         return rc;
@@ -573,28 +593,37 @@ int orc_step(int64_t Nc, int64_t Ns, double *K, int64_t G, double L, const doubl
 /* ------------------------------------------------------------------ */
 /* Central finite difference of F along a direction delta, without      */
 /* cancellation:  H(d + h D) - H(d - h D) = 4 h (d . D) /               */
-/* (H(d + h D) + H(d - h D)), exact algebra for H = sqrt(|.|^2 + eps^2). */
+/* (H(d + h D) + H(d - h D)), exact algebra for H = sqrt(|.|^2 + eps^2), */
+/* and the log1p form below for the logarithmic kernel.                 */
 /* Returns (F(K + h delta) - F(K - h delta)) / (2h).  Pairs in which     */
 /* neither sample moves contribute exactly 0 and are skipped; the       */
 /* repulsion double sum is symmetric in (i, j), so an ordered pair with  */
 /* one moving end is counted twice from that end.                        */
 /* ------------------------------------------------------------------ */
 static double pair_diff(double dx, double dy, double dz, double ex, double ey, double ez,
-                        double h, double eps)
+                        double h, double eps, int kern)
 {
-    double hp = kernel_h(dx + h * ex, dy + h * ey, dz + h * ez, eps);
-    double hm = kernel_h(dx - h * ex, dy - h * ey, dz - h * ez, eps);
+    double num = 4.0 * h * ((dx * ex + dy * ey) + dz * ez);
+    if (kern == 1) {
+        /* log kernel: with A = |d + hD|^2 + eps^2 and B = |d - hD|^2 + eps^2,
+         * A - B = 4 h (d . D), so H(+) - H(-) = log1p((A - B) / B) / 2. */
+        double mx = dx - h * ex, my = dy - h * ey, mz = dz - h * ez;
+        double B = mx * mx + my * my + mz * mz + eps * eps;
+        return 0.5 * log1p(num / B);
+    }
+    double hp = kernel_h(dx + h * ex, dy + h * ey, dz + h * ez, eps, kern);
+    double hm = kernel_h(dx - h * ex, dy - h * ey, dz - h * ez, eps, kern);
     double den = hp + hm;
     if (den == 0.0)
         return 0.0;
-    return 4.0 * h * ((dx * ex + dy * ey) + dz * ez) / den;
+    return num / den;
 }
 
 int orc_fd_directional(int64_t p, const double *kx, const double *ky, const double *kz,
-                       int64_t G, double L, const double *rho, double eps,
+                       int64_t G, double L, const double *rho, double eps, int kern,
                        const double *delta /* [3][p] */, double h, double *out)
 {
-    if (p < 1 || G < 1 || !kx || !ky || !kz || !rho || !delta || !out || !(h > 0) || eps < 0.0)
+    if (p < 1 || G < 1 || !kx || !ky || !kz || !rho || !delta || !out || !(h > 0) || bad_kernel(eps, kern))
         return -1;
     const double *ex = delta, *ey = delta + p, *ez = delta + 2 * p;
     double *ta = calloc((size_t)p, sizeof(double)), *tr = calloc((size_t)p, sizeof(double));
@@ -615,12 +644,12 @@ int orc_fd_directional(int64_t p, const double *kx, const double *ky, const doub
                     cs_add(&sa, w * pair_diff(kx[i] - cell_centre(ix, G, L),
                                               ky[i] - cell_centre(iy, G, L),
                                               kz[i] - cell_centre(iz, G, L),
-                                              ex[i], ey[i], ez[i], h, eps));
+                                              ex[i], ey[i], ez[i], h, eps, kern));
                 }
         for (int64_t j = 0; j < p; ++j) {
             int moves_j = (ex[j] != 0.0 || ey[j] != 0.0 || ez[j] != 0.0);
             double dterm = pair_diff(kx[i] - kx[j], ky[i] - ky[j], kz[i] - kz[j],
-                                     ex[i] - ex[j], ey[i] - ey[j], ez[i] - ez[j], h, eps);
+                                     ex[i] - ex[j], ey[i] - ey[j], ez[i] - ez[j], h, eps, kern);
             cs_add(&sr, moves_j ? dterm : 2.0 * dterm);
         }
         ta[i] = cs_get(&sa);
@@ -656,7 +685,7 @@ static double node_coord(int64_t k, int64_t G, double L)
 
 /* U and dU at one point by direct summation over the G^3 cells. */
 static void attraction_at(double x, double y, double z, int64_t G, double L, const double *rho,
-                          double eps, double out[4])
+                          double eps, int kern, double out[4])
 {
     csum u = {0, 0}, d[3] = {{0, 0}, {0, 0}, {0, 0}};
     double g[3];
@@ -666,8 +695,8 @@ static void attraction_at(double x, double y, double z, int64_t G, double L, con
                 double w = rho[ix + G * (iy + G * iz)];
                 double dx = x - cell_centre(ix, G, L), dy = y - cell_centre(iy, G, L),
                        dz = z - cell_centre(iz, G, L);
-                cs_add(&u, w * kernel_h(dx, dy, dz, eps));
-                kernel_grad(dx, dy, dz, eps, g);
+                cs_add(&u, w * kernel_h(dx, dy, dz, eps, kern));
+                kernel_grad(dx, dy, dz, eps, kern, g);
                 for (int c = 0; c < 3; ++c)
                     cs_add(&d[c], w * g[c]);
             }
@@ -677,16 +706,16 @@ static void attraction_at(double x, double y, double z, int64_t G, double L, con
 }
 
 /* Field at every node of the extended grid: out[(node)*4 + {U, Ux, Uy, Uz}]. */
-int orc_field(int64_t G, double L, const double *rho, double eps, double *out)
+int orc_field(int64_t G, double L, const double *rho, double eps, int kern, double *out)
 {
-    if (G < 1 || !rho || !out || eps < 0.0)
+    if (G < 1 || !rho || !out || bad_kernel(eps, kern))
         return -1;
     int64_t Gn = G + 2, Mn = Gn * Gn * Gn;
 #pragma omp parallel for schedule(dynamic, 64)
     for (int64_t n = 0; n < Mn; ++n) {
         int64_t kx = n % Gn, ky = (n / Gn) % Gn, kz = n / (Gn * Gn);
         attraction_at(node_coord(kx, G, L), node_coord(ky, G, L), node_coord(kz, G, L), G, L,
-                      rho, eps, out + 4 * n);
+                      rho, eps, kern, out + 4 * n);
     }
     return 0;
 }
@@ -749,11 +778,11 @@ int orc_interpolate(int64_t G, double L, const double *field, int64_t n, const d
  * the all-pairs sum.  Outputs as orc_grad (ua = interpolated potential).
  */
 int orc_grad_field(int64_t p, const double *kx, const double *ky, const double *kz,
-                   int64_t G, double L, const double *rho, double eps,
+                   int64_t G, double L, const double *rho, double eps, int kern,
                    int64_t n_t, const int64_t *targets,
                    double *dF, double *dFa, double *dFr, double *ua, double *ur)
 {
-    if (p < 1 || G < 1 || n_t < 0 || !kx || !ky || !kz || !rho || !targets || eps < 0.0)
+    if (p < 1 || G < 1 || n_t < 0 || !kx || !ky || !kz || !rho || !targets || bad_kernel(eps, kern))
         return -1;
     for (int64_t t = 0; t < n_t; ++t)
         if (targets[t] < 0 || targets[t] >= p)
@@ -773,7 +802,7 @@ int orc_grad_field(int64_t p, const double *kx, const double *ky, const double *
             for (int dy = 0; dy < 2; ++dy)
                 for (int dx = 0; dx < 2; ++dx)
                     attraction_at(node_coord(k[0] + dx, G, L), node_coord(k[1] + dy, G, L),
-                                  node_coord(k[2] + dz, G, L), G, L, rho, eps,
+                                  node_coord(k[2] + dz, G, L), G, L, rho, eps, kern,
                                   local + 4 * (dx + 2 * (dy + 2 * dz)));
         for (int dz = 0; dz < 2; ++dz)
             for (int dy = 0; dy < 2; ++dy)
@@ -788,8 +817,8 @@ int orc_grad_field(int64_t p, const double *kx, const double *ky, const double *
         double g[3];
         for (int64_t j = 0; j < p; ++j) {
             double dx = kx[i] - kx[j], dy = ky[i] - ky[j], dz = kz[i] - kz[j];
-            cs_add(&sr, kernel_h(dx, dy, dz, eps));
-            kernel_grad(dx, dy, dz, eps, g);
+            cs_add(&sr, kernel_h(dx, dy, dz, eps, kern));
+            kernel_grad(dx, dy, dz, eps, kern, g);
             for (int c = 0; c < 3; ++c)
                 cs_add(&r3[c], g[c]);
         }

@@ -237,6 +237,117 @@ def test_regularised_kernel_diagonal():
 
 
 # --------------------------------------------------------------------------
+# Logarithmic kernel H(d) = log(|d|^2 + eps^2) / 2 (regularised log of the norm)
+# --------------------------------------------------------------------------
+LOG_EPS = 0.02
+
+
+def test_log_kernel_two_points_closed_form():
+    eps = LOG_EPS
+    K = np.array([[0.1, -0.2], [0.0, 0.3], [0.05, 0.0]])
+    d = K[:, 0] - K[:, 1]
+    s = float(d @ d) + eps * eps
+    r = oracle.grad(K, [1.0], 1, 0.5, eps, kernel="log")
+    np.testing.assert_allclose(r["dFr"][:, 0], d / s / 4, rtol=1e-15, atol=1e-16)
+    np.testing.assert_allclose(r["dFr"][:, 1], -d / s / 4, rtol=1e-15, atol=1e-16)
+    _, _, Fr = oracle.energy(K, [1.0], 1, 0.5, eps, kernel="log")
+    # 1/(2p^2) * (2 H(d) + 2 H(0)) with H(0) = log(eps)
+    assert Fr == pytest.approx((0.5 * math.log(s) + math.log(eps)) / 4, rel=1e-14)
+
+
+def test_log_kernel_regular_octahedron():
+    r0, eps = 0.3, LOG_EPS
+    K = np.zeros((3, 6))
+    for k in range(3):
+        K[k, 2 * k] = r0
+        K[k, 2 * k + 1] = -r0
+    g = oracle.grad(K, [1.0], 1, 0.5, eps, kernel="log")["dFr"]
+    # from +r e1: the opposite vertex at distance 2r, four neighbours at r*sqrt(2)
+    expect = (2 * r0 / (4 * r0 ** 2 + eps ** 2) + 4 * r0 / (2 * r0 ** 2 + eps ** 2)) / 36
+    np.testing.assert_allclose(g[:, 0], [expect, 0, 0], rtol=1e-14, atol=1e-16)
+    np.testing.assert_allclose(g[:, 5], [0, 0, -expect], rtol=1e-14, atol=1e-16)
+
+
+def test_log_kernel_equilibrium_uniform_density():
+    G, L = 4, 0.5
+    K = grid_points(G, L)
+    rho = inputs.uniform_density(G)
+    r = oracle.grad(K, rho, G, L, LOG_EPS, kernel="log")
+    scale = np.abs(r["dFa"]).max()
+    assert scale > 1e-3
+    assert np.abs(r["dF"]).max() <= 1e-14 * scale
+    F, _, _ = oracle.energy(K, rho, G, L, LOG_EPS, kernel="log")
+    assert abs(F - oracle.rho_self_energy(rho, G, L, LOG_EPS, kernel="log")) <= 1e-14 * abs(F)
+
+
+def _brute_energy_log(K, rho, G, L, eps):
+    p = K.shape[1]
+    ax = [-L + (i + 0.5) * (2 * L / G) for i in range(G)]
+
+    def h(a, b):
+        return 0.5 * math.log(sum((u - v) ** 2 for u, v in zip(a, b)) + eps * eps)
+    fa = 0.0
+    for i in range(p):
+        for iz in range(G):
+            for iy in range(G):
+                for ix in range(G):
+                    fa += rho[ix + G * (iy + G * iz)] * h(K[:, i], (ax[ix], ax[iy], ax[iz]))
+    fr = sum(h(K[:, i], K[:, j]) for i in range(p) for j in range(p))
+    return fa / p - fr / (2 * p * p), fa / p, fr / (2 * p * p)
+
+
+def test_log_kernel_energy_brute_force():
+    G, L = 3, 0.5
+    K = RNG.uniform(-L, L, (3, 7))
+    rho = RNG.uniform(0, 1, G ** 3)
+    rho /= rho.sum()
+    got = oracle.energy(K, rho, G, L, LOG_EPS, kernel="log")
+    np.testing.assert_allclose(got, _brute_energy_log(K, rho, G, L, LOG_EPS), rtol=1e-13)
+
+
+def test_log_kernel_gradient_matches_brute_force_differences():
+    G, L, eps = 2, 0.5, LOG_EPS
+    K = RNG.uniform(-L, L, (3, 5))
+    rho = RNG.uniform(0, 1, G ** 3)
+    rho /= rho.sum()
+    g = oracle.grad(K, rho, G, L, eps, kernel="log")["dF"]
+    h = 1e-6
+    for c in range(3):
+        for i in range(5):
+            Kp, Km = K.copy(), K.copy()
+            Kp[c, i] += h
+            Km[c, i] -= h
+            fd = (_brute_energy_log(Kp, rho, G, L, eps)[0]
+                  - _brute_energy_log(Km, rho, G, L, eps)[0]) / (2 * h)
+            assert fd == pytest.approx(g[c, i], abs=1e-8)
+
+
+def test_log_kernel_fd_directional():
+    G, L, eps = 4, 0.5, LOG_EPS
+    K = inputs.radial_spokes(8, 16, L, seed=3, jitter=0.05)
+    rho = inputs.radial_density(G, L, 0.1, 2.0)
+    g = oracle.grad(K, rho, G, L, eps, kernel="log")["dF"]
+    for k in range(3):
+        delta = inputs.rademacher(K.shape, 200 + k)
+        fd = oracle.fd_directional(K, rho, G, L, delta, 1e-5, eps, kernel="log")
+        assert fd == pytest.approx(float((g * delta).sum()), rel=1e-5, abs=1e-12)
+    # and against the brute-force energy on a tiny case
+    Ks = RNG.uniform(-L, L, (3, 6))
+    rs = RNG.uniform(0, 1, 8)
+    rs /= rs.sum()
+    delta = inputs.rademacher((3, 6), 7)
+    got = oracle.fd_directional(Ks, rs, 2, L, delta, 1e-4, eps, kernel="log")
+    want = (_brute_energy_log(Ks + 1e-4 * delta, rs, 2, L, eps)[0]
+            - _brute_energy_log(Ks - 1e-4 * delta, rs, 2, L, eps)[0]) / 2e-4
+    assert got == pytest.approx(want, rel=1e-8, abs=1e-12)
+
+
+def test_log_kernel_needs_positive_eps():
+    with pytest.raises(ValueError):
+        oracle.grad(np.zeros((3, 2)), [1.0], 1, 0.5, 0.0, kernel="log")
+
+
+# --------------------------------------------------------------------------
 # Normalised speed/slew bounds (printed scanner constants)
 # --------------------------------------------------------------------------
 def test_alpha_beta_golden():
