@@ -77,9 +77,15 @@ typedef enum {
 
 enum {
     SPK_FLAG_DISCREPANCY = 1,        /* sparkling_energy also returns D = F - E_rho    */
-    SPK_FLAG_ROTATION_VARIANT = 2    /* constraint norms |.| are per-axis maxima (the
+    SPK_FLAG_ROTATION_VARIANT = 2,   /* constraint norms |.| are per-axis maxima (the
                                         l_inf bounds of Sec. "3D K-space sampling")
                                         instead of Euclidean norms                     */
+    SPK_FLAG_LOG_KERNEL = 4          /* H(d) = log(|d|^2 + eps^2) / 2, the logarithmic
+                                        kernel the "3D SPARKLING formulation" names as
+                                        an alternative, regularised; needs eps > 0
+                                        with eps^2 a normal number of the form's type,
+                                        and the plain_fp64 or fp32_comp form
+                                        (SPK_EUNSUPPORTED otherwise)                   */
 };
 
 typedef struct {
@@ -89,7 +95,8 @@ typedef struct {
     int32_t precision;    /* spk_precision                                              */
     int32_t te_index;     /* sample pinned to the origin in every shot; -1 = none       */
     double  half_width;   /* L > 0: sampling box [-L, L]^3 (the paper uses L = 1)       */
-    double  eps;          /* >= 0: H(d) = sqrt(|d|^2 + eps^2); 0 gives H = |d|          */
+    double  eps;          /* >= 0: H(d) = sqrt(|d|^2 + eps^2); 0 gives H = |d|
+                             (log kernel: H(d) = log(|d|^2 + eps^2) / 2, eps > 0)      */
     double  a_max;        /* per-raster-step speed bound (spk_alpha_beta), > 0          */
     double  b_max;        /* per-raster-step slew bound (spk_alpha_beta), > 0           */
     int32_t n_pit;        /* projection iterations, >= 0                                */
@@ -136,6 +143,26 @@ int sparkling_energy(const spk_params *prm, const void *kx, const void *ky, cons
                      const void *rho, double out[4], void *ws, size_t ws_bytes, void *stream);
 
 /*
+ * Bound on the Lipschitz constant of grad F for the regularised kernels (Sec.
+ * "Choice of step size": a fixed step inversely proportional to it gives the
+ * convergence guarantee).  With p samples, regulariser eps > 0 and total
+ * density mass rho_mass = sum_v rho_v (rho_v >= 0; 1 for a normalised
+ * density), every eigenvalue of the Hessian of F lies in
+ *   distance kernel: [-1, rho_mass] / (p eps),
+ *   log kernel     : [-(1 + rho_mass/8), rho_mass + 1/8] / (p eps^2),
+ * since the kernel's Hessian is bounded by [0, 1/eps] (distance) or
+ * [-1/(8 eps^2), 1/eps^2] (log) and the repulsion's quadratic form sums
+ * |v_i - v_j|^2 <= 2p |v|^2 over pairs.  *lipschitz receives the largest
+ * magnitude; the step 1/(*lipschitz) then decreases F by at least
+ * (*lipschitz/2) |K+ - K|^2 per step when the projection is exact (for
+ * instance n_pit = 0 with unbounded speed and slew: box and echo time).
+ * flags: only SPK_FLAG_LOG_KERNEL matters.  Host only.  SPK_EINVAL if p < 1,
+ * eps <= 0, or rho_mass < 0 or not finite.
+ */
+int spk_lipschitz_bound(int64_t p, double eps, double rho_mass, int32_t flags,
+                        double *lipschitz);
+
+/*
  * Node field of the grid attraction (Sec. "Evaluating F^a and its gradient":
  * the discrete convolution of the sampled kernel with the sampled density,
  * computed once per density and evaluated off the grid by the trilinear
@@ -144,7 +171,8 @@ int sparkling_energy(const spk_params *prm, const void *kx, const void *ky, cons
  * n = kx + (G+2)*(ky + (G+2)*kz).  field (device, K's type, 16-byte aligned
  * for float, 32 for double) receives 4*(G+2)^3 values laid out
  * [n][U, dU/dx, dU/dy, dU/dz] with U(x) = sum_v rho_v H(x - x_v), summed
- * directly over the cells in the precision form of prm.  Setting
+ * directly over the cells in the precision form and with the kernel of prm
+ * (a field is valid only with the kernel and eps it was built with).  Setting
  * prm->attraction_field to this buffer makes energy, gradient and step use
  * the interpolant for the attraction (valid for samples inside
  * [-L - h/2, L + h/2]^3; outside, the nearest node layer is extrapolated

@@ -20,6 +20,8 @@ LIB_PATH = _PKG / "libsparkling.so"
 PRECISIONS = {"plain_fp64": 0, "fp32_comp": 1, "fp32_naive": 2, "fp32_acc64": 3}
 FLAG_DISCREPANCY = 1
 FLAG_ROTATION_VARIANT = 2
+FLAG_LOG_KERNEL = 4
+KERNELS = {"distance": 0, "log": FLAG_LOG_KERNEL}
 KIND_REPULSION, KIND_ATTRACTION, KIND_PROJECTION, KIND_OTHER, KIND_INTERPOLATION = 0, 1, 2, 3, 4
 
 _i32, _i64, _dbl, _vp, _sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p, ctypes.c_size_t
@@ -59,6 +61,7 @@ def load_library(path: Path | str | None = None):
         "spk_last_error": ([], ctypes.c_char_p),
         "spk_alpha_beta": ([_dbl] * 8 + [_vp, _vp], ctypes.c_int),
         "spk_workspace_size": ([_vp, _vp], ctypes.c_int),
+        "spk_lipschitz_bound": ([_i64, _dbl, _dbl, _i32, _vp], ctypes.c_int),
         "sparkling_energy": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp], ctypes.c_int),
         "sparkling_field": ([_vp, _vp, _vp, _vp, _sz, _vp], ctypes.c_int),
         "sparkling_grad": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _i64, _vp, _vp, _vp,
@@ -101,6 +104,7 @@ class Params:
     n_pit: int = 200
     discrepancy: bool = False
     rotation_variant: bool = False                   # per-axis speed/slew bounds
+    kernel: str = "distance"                         # "distance" or "log" (needs eps > 0)
     attraction_field: "torch.Tensor | None" = None   # from attraction_field(); None = direct sum
     _c: SpkParams = field(default=None, repr=False, compare=False)
 
@@ -122,8 +126,17 @@ class Params:
                          self.te_index, self.half_width, self.eps, self.a_max, self.b_max,
                          self.n_pit,
                          (FLAG_DISCREPANCY if self.discrepancy else 0)
-                         | (FLAG_ROTATION_VARIANT if self.rotation_variant else 0),
+                         | (FLAG_ROTATION_VARIANT if self.rotation_variant else 0)
+                         | KERNELS[self.kernel],
                          _vp(f.data_ptr()) if f is not None else None)
+
+
+def lipschitz_bound(p: int, eps: float, rho_mass: float = 1.0, kernel: str = "distance") -> float:
+    """Upper bound on the Lipschitz constant of grad F (the fixed step 1/L guarantees descent)."""
+    out = _dbl()
+    _check(load_library().spk_lipschitz_bound(p, eps, rho_mass, KERNELS[kernel],
+                                              ctypes.byref(out)), "spk_lipschitz_bound")
+    return out.value
 
 
 def alpha_beta(gmax, smax, raster_dt, dwell_dt, fov, kmax, gamma_bar, half_width):

@@ -4,6 +4,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cfloat>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -115,8 +117,16 @@ int check_params(const spk_params *prm, bool need_projection)
         return fail(SPK_EINVAL, "eps must be finite and >= 0");
     if (prm->te_index < -1 || prm->te_index >= prm->n_samples)
         return fail(SPK_EINVAL, "te_index must be -1 or in [0, n_samples)");
-    if (prm->flags & ~(SPK_FLAG_DISCREPANCY | SPK_FLAG_ROTATION_VARIANT))
+    if (prm->flags & ~(SPK_FLAG_DISCREPANCY | SPK_FLAG_ROTATION_VARIANT | SPK_FLAG_LOG_KERNEL))
         return fail(SPK_EINVAL, "unknown flags 0x%x", prm->flags);
+    if (prm->flags & SPK_FLAG_LOG_KERNEL) {
+        if (prm->precision != SPK_PLAIN_FP64 && prm->precision != SPK_FP32_COMP)
+            return fail(SPK_EUNSUPPORTED, "the log kernel runs in the plain_fp64 and fp32_comp "
+                                          "forms only");
+        const double tiny = prm->precision == SPK_PLAIN_FP64 ? DBL_MIN : FLT_MIN;
+        if (!(prm->eps * prm->eps >= tiny))
+            return fail(SPK_EINVAL, "the log kernel needs eps > 0 with eps^2 >= %g", tiny);
+    }
     if (prm->attraction_field &&
         reinterpret_cast<uintptr_t>(prm->attraction_field) % (4 * elt_size(prm->precision)))
         return fail(SPK_EINVAL, "attraction_field is not %zu-byte aligned",
@@ -265,6 +275,7 @@ int run_sweep(const spk_params *prm, bool cells, const void *tx, const void *ty,
     const Plan pl = make_plan(prm->precision, cells, p_total, n_src, G);
     SweepLaunch l;
     l.precision = prm->precision;
+    l.kernel = (prm->flags & SPK_FLAG_LOG_KERNEL) ? kKernelLog : kKernelDistance;
     l.energy = energy;
     l.tx = tx;
     l.ty = ty;
@@ -417,6 +428,25 @@ int spk_alpha_beta(double gmax, double smax, double raster_dt, double dwell_dt, 
     const double slew = gamma_bar * smax / kmax;
     *a_max = speed * raster_dt * half_width;
     *b_max = slew * raster_dt * raster_dt * half_width;
+    return SPK_OK;
+}
+
+int spk_lipschitz_bound(int64_t p, double eps, double rho_mass, int32_t flags,
+                        double *lipschitz)
+{
+    if (!lipschitz)
+        return fail(SPK_EINVAL, "lipschitz is NULL");
+    if (p < 1)
+        return fail(SPK_EINVAL, "p must be >= 1");
+    if (!(eps > 0.0) || !std::isfinite(eps))
+        return fail(SPK_EINVAL, "eps must be finite and > 0 (grad F is not Lipschitz at 0)");
+    if (!(rho_mass >= 0.0) || !std::isfinite(rho_mass))
+        return fail(SPK_EINVAL, "rho_mass must be finite and >= 0");
+    const double pd = (double)p;
+    if (flags & SPK_FLAG_LOG_KERNEL)
+        *lipschitz = std::max(1.0 + rho_mass / 8.0, rho_mass + 1.0 / 8.0) / (pd * eps * eps);
+    else
+        *lipschitz = std::max(1.0, rho_mass) / (pd * eps);
     return SPK_OK;
 }
 

@@ -56,8 +56,13 @@ int sweep_targets_per_block(int precision);
 // where a source is a sample (sample sweep) or a row of G cells (cell sweep).
 // Block (x, y) writes its four sums (gx, gy, gz, potential) for target t into
 // part[(y*4 + c)*ld + (t - t0)] as doubles.
+// Pair kernels H of the sweeps.
+constexpr int kKernelDistance = 0;   // sqrt(|d|^2 + eps^2)
+constexpr int kKernelLog = 1;        // log(|d|^2 + eps^2) / 2, eps > 0
+
 struct SweepLaunch {
     int precision = 0;
+    int kernel = kKernelDistance;
     bool energy = false;
     const void *tx = nullptr, *ty = nullptr, *tz = nullptr;
     int64_t t0 = 0, nt = 0;

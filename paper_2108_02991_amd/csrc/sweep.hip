@@ -19,6 +19,13 @@
 // rsqrt, one multiply by rho_v, one add for the row weight and one FMA for
 // the x force; the y and z forces are row weight times offset, once per row.
 //
+// Kernels (template KERN): the distance kernel H(d) = sqrt(|d|^2 + eps^2)
+// above, or the logarithmic kernel H(d) = log(|d|^2 + eps^2) / 2 (the
+// alternative the "3D SPARKLING formulation" mentions; eps > 0), whose pair
+// is w = 1/(|d|^2 + eps^2) (one reciprocal) with the force w d, and the
+// potential log2(|d|^2 + eps^2) accumulated as is and scaled by ln(2)/2 once
+// per slab total.
+//
 // Precision forms (template MODE):
 //   kPlain64 : double coordinates, double math, double running sums;
 //   kComp    : float pair math, float per-tile sums folded into a float
@@ -37,6 +44,7 @@ namespace {
 
 enum : int { kPlain64 = SPK_PLAIN_FP64, kComp = SPK_FP32_COMP, kNaive = SPK_FP32_NAIVE,
              kAcc64 = SPK_FP32_ACC64 };
+enum : int { kDist = kKernelDistance, kLog = kKernelLog };
 
 constexpr int BLK = kSweepBlock;
 
@@ -65,6 +73,35 @@ __device__ inline double rsq(double x)
     const double r = __builtin_fma(-x * y0, y0, 1.0);
     const double c = __builtin_fma(r, 0.375, 0.5);
     return __builtin_fma(y0 * r, c, y0);
+}
+
+__device__ inline float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+// Double reciprocal: the hardware estimate y0 refined once with the
+// third-order step y0 (1 + e + e^2), e = 1 - x y0 (an FMA), leaving O(e^3).
+__device__ inline double rcp(double x)
+{
+    const double y0 = __builtin_amdgcn_rcp(x);
+    const double e = __builtin_fma(-x, y0, 1.0);
+    return __builtin_fma(y0, __builtin_fma(e, e, e), y0);
+}
+// log2 of a normal positive number.
+__device__ inline float lg2(float x) { return __builtin_amdgcn_logf(x); }
+__device__ inline double lg2(double x) { return log2(x); }
+
+// Pair weight of the kernel from the guarded |d|^2.
+template <int KERN, typename T> __device__ inline T pair_weight(T r2)
+{
+    if constexpr (KERN == kLog)
+        return rcp(r2);
+    else
+        return rsq(r2);
+}
+
+// Factor turning the accumulated potential sum into H: 1, or ln(2)/2 for the
+// log kernel, which accumulates log2(|d|^2 + eps^2).
+template <int KERN> __device__ inline double potential_scale()
+{
+    return KERN == kLog ? 0.34657359027997264 : 1.0;
 }
 
 __device__ inline float fmaT(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
@@ -124,7 +161,16 @@ __device__ inline void acc_fma(Acc<MODE> &a, T w, T d)
         a.t = fmaT(w, d, a.t);
 }
 
-template <int MODE, int R, bool ENERGY>
+template <int MODE, typename T>
+__device__ inline void acc_add(Acc<MODE> &a, T x)
+{
+    if constexpr (MODE == kAcc64)
+        a.t += (double)x;
+    else
+        a.t += x;
+}
+
+template <int MODE, int R, bool ENERGY, int KERN>
 __global__ __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(min_waves<MODE>())))
 void sweep_samples_kernel(SweepLaunch l)
 {
@@ -165,12 +211,16 @@ void sweep_samples_kernel(SweepLaunch l)
             for (int r = 0; r < R; ++r) {
                 T dx = xi[r] - s.x, dy = yi[r] - s.y, dz = zi[r] - s.z;
                 T r2 = fmaT(dz, dz, fmaT(dy, dy, fmaT(dx, dx, guard)));
-                T w = rsq(r2);
+                T w = pair_weight<KERN>(r2);
                 acc_fma(gx[r], w, dx);
                 acc_fma(gy[r], w, dy);
                 acc_fma(gz[r], w, dz);
-                if constexpr (ENERGY)
-                    acc_fma(ee[r], w, r2);
+                if constexpr (ENERGY) {
+                    if constexpr (KERN == kLog)
+                        acc_add(ee[r], lg2(r2));
+                    else
+                        acc_fma(ee[r], w, r2);
+                }
             }
         };
         if (n == kSampleTile) {
@@ -219,12 +269,15 @@ void sweep_samples_kernel(SweepLaunch l)
             out[o] = gx[r].total();
             out[l.ld + o] = gy[r].total();
             out[2 * l.ld + o] = gz[r].total();
-            out[3 * l.ld + o] = ENERGY ? ee[r].total() : 0.0;
+            if constexpr (KERN == kLog)
+                out[3 * l.ld + o] = ENERGY ? potential_scale<KERN>() * ee[r].total() : 0.0;
+            else
+                out[3 * l.ld + o] = ENERGY ? ee[r].total() : 0.0;
         }
     }
 }
 
-template <int MODE, int R, bool ENERGY>
+template <int MODE, int R, bool ENERGY, int KERN>
 __global__ __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(min_waves<MODE>())))
 void sweep_cells_kernel(SweepLaunch l)
 {
@@ -290,11 +343,15 @@ void sweep_cells_kernel(SweepLaunch l)
                 for (int r = 0; r < R; ++r) {
                     T dx = xi[r] - v.x;
                     T r2 = fmaT(dx, dx, c[r]);
-                    T w = v.y * rsq(r2);
+                    T w = v.y * pair_weight<KERN>(r2);
                     wrow[r] += w;
                     acc_fma(gx[r], w, dx);
-                    if constexpr (ENERGY)
-                        acc_fma(ee[r], w, r2);
+                    if constexpr (ENERGY) {
+                        if constexpr (KERN == kLog)
+                            acc_fma(ee[r], v.y, lg2(r2));
+                        else
+                            acc_fma(ee[r], w, r2);
+                    }
                 }
             };
             int ix = 0;
@@ -338,37 +395,57 @@ void sweep_cells_kernel(SweepLaunch l)
             out[o] = gx[r].total();
             out[l.ld + o] = gy[r].total();
             out[2 * l.ld + o] = gz[r].total();
-            out[3 * l.ld + o] = ENERGY ? ee[r].total() : 0.0;
+            if constexpr (KERN == kLog)
+                out[3 * l.ld + o] = ENERGY ? potential_scale<KERN>() * ee[r].total() : 0.0;
+            else
+                out[3 * l.ld + o] = ENERGY ? ee[r].total() : 0.0;
         }
     }
 }
 
-template <int MODE, bool ENERGY>
+template <int MODE, bool ENERGY, int KERN>
 hipError_t launch_samples_mode(const SweepLaunch &l, hipStream_t s)
 {
     constexpr int R = lanes_targets<MODE>();
     dim3 grid((unsigned)((l.nt + BLK * R - 1) / (BLK * R)), (unsigned)l.nslabs);
-    hipLaunchKernelGGL((sweep_samples_kernel<MODE, R, ENERGY>), grid, dim3(BLK), 0, s, l);
+    hipLaunchKernelGGL((sweep_samples_kernel<MODE, R, ENERGY, KERN>), grid, dim3(BLK), 0, s, l);
     return hipGetLastError();
 }
 
-template <int MODE, bool ENERGY>
+template <int MODE, bool ENERGY, int KERN>
 hipError_t launch_cells_mode(const SweepLaunch &l, hipStream_t s)
 {
     constexpr int R = lanes_targets<MODE>();
     dim3 grid((unsigned)((l.nt + BLK * R - 1) / (BLK * R)), (unsigned)l.nslabs);
-    hipLaunchKernelGGL((sweep_cells_kernel<MODE, R, ENERGY>), grid, dim3(BLK), 0, s, l);
+    hipLaunchKernelGGL((sweep_cells_kernel<MODE, R, ENERGY, KERN>), grid, dim3(BLK), 0, s, l);
     return hipGetLastError();
 }
 
+template <bool CELLS, bool ENERGY, int MODE, int KERN>
+hipError_t launch_one(const SweepLaunch &l, hipStream_t s)
+{
+    return CELLS ? launch_cells_mode<MODE, ENERGY, KERN>(l, s)
+                 : launch_samples_mode<MODE, ENERGY, KERN>(l, s);
+}
+
+// The log kernel is built for the plain FP64 and compensated FP32 forms only.
 template <bool CELLS, bool ENERGY>
 hipError_t launch_any(const SweepLaunch &l, hipStream_t s)
 {
+    if (l.kernel == kLog) {
+        switch (l.precision) {
+        case kPlain64: return launch_one<CELLS, ENERGY, kPlain64, kLog>(l, s);
+        case kComp: return launch_one<CELLS, ENERGY, kComp, kLog>(l, s);
+        default: return hipErrorInvalidValue;
+        }
+    }
+    if (l.kernel != kDist)
+        return hipErrorInvalidValue;
     switch (l.precision) {
-    case kPlain64: return CELLS ? launch_cells_mode<kPlain64, ENERGY>(l, s) : launch_samples_mode<kPlain64, ENERGY>(l, s);
-    case kComp: return CELLS ? launch_cells_mode<kComp, ENERGY>(l, s) : launch_samples_mode<kComp, ENERGY>(l, s);
-    case kNaive: return CELLS ? launch_cells_mode<kNaive, ENERGY>(l, s) : launch_samples_mode<kNaive, ENERGY>(l, s);
-    case kAcc64: return CELLS ? launch_cells_mode<kAcc64, ENERGY>(l, s) : launch_samples_mode<kAcc64, ENERGY>(l, s);
+    case kPlain64: return launch_one<CELLS, ENERGY, kPlain64, kDist>(l, s);
+    case kComp: return launch_one<CELLS, ENERGY, kComp, kDist>(l, s);
+    case kNaive: return launch_one<CELLS, ENERGY, kNaive, kDist>(l, s);
+    case kAcc64: return launch_one<CELLS, ENERGY, kAcc64, kDist>(l, s);
     default: return hipErrorInvalidValue;
     }
 }

@@ -92,9 +92,24 @@ def test_unknown_precision_and_flags(lib):
     n = ctypes.c_size_t()
     assert lib.spk_workspace_size(ctypes.byref(c), ctypes.byref(n)) == EINVAL
     c = good_params().c()
-    c.flags = 4
+    c.flags = 8
     assert lib.spk_workspace_size(ctypes.byref(c), ctypes.byref(n)) == EINVAL
     assert lib.spk_workspace_size(None, ctypes.byref(n)) == EINVAL
+
+
+def test_log_kernel_validation(lib):
+    n = ctypes.c_size_t()
+    ok = good_params(kernel="log", eps=0.01).c()
+    assert ok.flags == api.FLAG_LOG_KERNEL
+    assert lib.spk_workspace_size(ctypes.byref(ok), ctypes.byref(n)) == 0
+    for bad, code in [(dict(eps=0.0), EINVAL), (dict(eps=1e-30), EINVAL),
+                      (dict(eps=0.01, precision="fp32_naive"), EUNSUPPORTED),
+                      (dict(eps=0.01, precision="fp32_acc64"), EUNSUPPORTED)]:
+        c = good_params(kernel="log", **bad).c()
+        assert lib.spk_workspace_size(ctypes.byref(c), ctypes.byref(n)) == code, bad
+    # FP64 accepts an eps whose square is below the float range
+    c = good_params(kernel="log", eps=1e-30, precision="plain_fp64").c()
+    assert lib.spk_workspace_size(ctypes.byref(c), ctypes.byref(n)) == 0
 
 
 FAKE = 0x10000   # an aligned, never dereferenced address
