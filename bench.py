@@ -31,7 +31,9 @@ if ROOT not in sys.path:
 FP32_VECTOR_PEAK_TFLOPS = 157.3
 # Algorithmic flops per pair of the sweeps with energy: 3 subtractions, 5 for
 # |d|^2, 1 reciprocal square root, 6 for the three force FMAs, 2 for the
-# energy FMA (repulsion); the attraction adds 1 for the density weight.
+# energy FMA (repulsion); the attraction adds 1 for the density weight.  The
+# log kernel swaps the reciprocal square root for a reciprocal and the energy
+# FMA for a log2 and an add: the same count.
 FLOP_PER_PAIR_REPULSION = 17
 FLOP_PER_PAIR_ATTRACTION = 18
 
@@ -54,7 +56,7 @@ def sweep_source_hash() -> str:
     return h.hexdigest()
 
 
-def recorded_traffic(workload: str, precision: str):
+def recorded_traffic(workload: str, precision: str, kernel: str = "distance"):
     """HBM bytes per repulsion launch from the committed counter summary, or None
     when the summary is missing, is for another workload, or the sweep sources
     changed since the counters were taken."""
@@ -65,7 +67,7 @@ def recorded_traffic(workload: str, precision: str):
     except OSError:
         return None
     if (rec.get("source_sha256") != sweep_source_hash() or rec.get("workload") != workload
-            or rec.get("precision") != precision):
+            or rec.get("precision") != precision or rec.get("kernel", "distance") != kernel):
         return None
     return float(rec["traffic_bytes_per_launch"])
 
@@ -84,6 +86,14 @@ def main():
     ap.add_argument("--attraction", choices=["direct", "field"], default="direct",
                     help="attraction by the direct sum over the density cells (default) or by "
                          "trilinear interpolation of a precomputed node field")
+    ap.add_argument("--kernel", choices=["distance", "log"], default="distance",
+                    help="pair kernel H: the distance |d| (default) or log(|d|^2 + eps^2)/2")
+    ap.add_argument("--eps", type=float, default=None,
+                    help="kernel regulariser (default 0 for the distance kernel, a quarter "
+                         "of the mean sample spacing for the log kernel)")
+    ap.add_argument("--eta", choices=["fixed", "lipschitz"], default=None,
+                    help="fixed step: the workload's (default, distance kernel) or 1/L from "
+                         "the Lipschitz bound (default for the log kernel; needs eps > 0)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed region, run a plain 1 GiB device copy three times "
                          "(reference dispatches for HBM byte counters)")
@@ -104,13 +114,21 @@ def main():
     spk.load_library()
     a, b = spk.alpha_beta(configs.GMAX, configs.SMAX, configs.RASTER_DT, configs.DWELL_DT,
                           w.fov, w.kmax, configs.GAMMA_BAR, w.half_width)
+    p_total = w.n_shots * w.n_samples
+    eps = args.eps if args.eps is not None else (
+        0.25 * 2 * w.half_width / p_total ** (1.0 / 3.0) if args.kernel == "log" else 0.0)
     prm = spk.Params(w.n_shots, w.n_samples, w.grid, precision=precision,
-                     half_width=w.half_width, a_max=a, b_max=b, te_index=0, n_pit=w.n_pit)
+                     half_width=w.half_width, eps=eps, a_max=a, b_max=b, te_index=0,
+                     n_pit=w.n_pit, kernel=args.kernel)
     p, M = prm.p, w.n_voxels
 
-    log(f"workload {w.name}: p={p} G={w.grid} precision={precision}")
+    log(f"workload {w.name}: p={p} G={w.grid} precision={precision} kernel={args.kernel} "
+        f"eps={eps:.4g}")
     K_host = w.trajectory()
     rho_host = w.density()
+    eta_rule = args.eta or ("lipschitz" if args.kernel == "log" else "fixed")
+    eta = (1.0 / spk.lipschitz_bound(p, eps, float(rho_host.sum()), args.kernel)
+           if eta_rule == "lipschitz" else w.eta_fixed)
     K = torch.tensor(K_host, dtype=prm.dtype, device=dev)
     rho = torch.tensor(rho_host, dtype=prm.dtype, device=dev)
     state = spk.StepState(prm, dev)
@@ -136,7 +154,7 @@ def main():
 
     it = 0
     for _ in range(args.warmup):
-        spk.step_(K, rho, prm, state, it, w.eta_fixed)
+        spk.step_(K, rho, prm, state, it, eta)
         it += 1
         log(f"warmup step done")
     torch.cuda.synchronize()
@@ -147,7 +165,7 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        infos.append(spk.step_(K, rho, prm, state, it, w.eta_fixed))
+        infos.append(spk.step_(K, rho, prm, state, it, eta))
         it += 1
         log(f"step {it} done: F={infos[-1]['F']:.9e} eta={infos[-1]['eta']:.4g}")
     torch.cuda.synchronize()
@@ -189,6 +207,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "n_shots": w.n_shots, "n_samples": w.n_samples, "p": p,
                    "grid": w.grid, "precision": precision, "n_pit": w.n_pit,
+                   "kernel": args.kernel, "eps": eps, "eta": eta_rule,
                    "attraction": args.attraction, "pairs_per_step": pairs_per_step},
         "s_per_grad_eval": grad_ms / 1e3,
         "kernels": {
@@ -206,7 +225,7 @@ def main():
         },
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK_TFLOPS,
-                     "traffic": recorded_traffic(w.name, precision)},
+                     "traffic": recorded_traffic(w.name, precision, args.kernel)},
         "last_step": {k: (v.tolist() if isinstance(v, np.ndarray) else v)
                       for k, v in infos[-1].items()},
     }
@@ -225,7 +244,8 @@ def main():
 
     if args.cpu_seconds > 0:
         result["cpu_baseline"] = cpu_baseline(w, K, rho, args.cpu_seconds,
-                                              field=args.attraction == "field")
+                                              field=args.attraction == "field", eps=eps,
+                                              kernel=args.kernel)
 
     print(json.dumps(result), flush=True)
 
@@ -241,7 +261,7 @@ def fp64_comparison(spk, torch, w, prm, K, rho, fraction, dev):
     nt = max(1024, int(p * fraction))
     nt = min(nt, p)
     prm64 = spk.Params(prm.n_shots, prm.n_samples, prm.grid, precision="plain_fp64",
-                       half_width=prm.half_width)
+                       half_width=prm.half_width, eps=prm.eps, kernel=prm.kernel)
     K64 = K.double()
     rho64 = rho.double()
     spk.workspace(prm64, dev)
@@ -267,7 +287,7 @@ def fp64_comparison(spk, torch, w, prm, K, rho, fraction, dev):
             "fp32_comp_rel_l2_vs_fp64": d}
 
 
-def cpu_baseline(w, K, rho, seconds, field=False):
+def cpu_baseline(w, K, rho, seconds, field=False, eps=0.0, kernel="distance"):
     """The FP64 oracle on a bounded sample of targets (all sources each).
 
     With field=True the oracle's grid attraction is timed instead (the 8
@@ -288,7 +308,7 @@ def cpu_baseline(w, K, rho, seconds, field=False):
     while done < pool.size and (done == 0 or dt < seconds):
         batch = pool[done:done + 64]
         t0 = time.perf_counter()
-        fn(Kh, rh, w.grid, w.half_width, 0.0, batch)
+        fn(Kh, rh, w.grid, w.half_width, eps, batch, kernel=kernel)
         dt += time.perf_counter() - t0
         done += batch.size
     targets = pool[:done]
@@ -297,7 +317,7 @@ def cpu_baseline(w, K, rho, seconds, field=False):
     what = ("the grid attraction of 8 nodes x all cells" if field else f"all {w.n_voxels} cells")
     return {"value": pairs / dt, "unit": "pair-interactions/s", "cores": oracle.num_threads(),
             "kind": "oracle", "sample": f"{targets.size} random targets of {w.name}, each against "
-            f"all {p} samples and {what} (FP64, compensated sums), {dt:.1f} s",
+            f"all {p} samples and {what} ({kernel} kernel, FP64, compensated sums), {dt:.1f} s",
             "s_per_grad_eval_extrapolated": float(p) * dt / targets.size}
 
 

@@ -23,24 +23,35 @@ import torch
 from . import api, configs
 
 
+def fixed_step(prm: api.Params, rho_mass: float, rule: str, eta_fixed: float) -> float:
+    """The fixed step of the first iterations: the workload's value ("fixed"), or
+    1/L from the Lipschitz bound of the regularised kernel ("lipschitz")."""
+    if rule == "lipschitz":
+        return 1.0 / api.lipschitz_bound(prm.p, prm.eps, rho_mass, prm.kernel)
+    return eta_fixed
+
+
 def run(workload: configs.Workload, precision: str, iters: int, device="cuda:0",
-        out=None, log_every: int = 1, rotation_variant: bool = False):
+        out=None, log_every: int = 1, rotation_variant: bool = False, kernel: str = "distance",
+        eps: float = 0.0, eta_rule: str = "fixed"):
     """Runs `iters` projected gradient steps; returns the list of records."""
     dev = torch.device(device)
     a, b = api.alpha_beta(configs.GMAX, configs.SMAX, configs.RASTER_DT, configs.DWELL_DT,
                           workload.fov, workload.kmax, configs.GAMMA_BAR, workload.half_width)
     prm = api.Params(workload.n_shots, workload.n_samples, workload.grid, precision=precision,
-                     half_width=workload.half_width, a_max=a, b_max=b, te_index=0,
-                     n_pit=workload.n_pit, rotation_variant=rotation_variant)
+                     half_width=workload.half_width, eps=eps, a_max=a, b_max=b, te_index=0,
+                     n_pit=workload.n_pit, rotation_variant=rotation_variant, kernel=kernel)
+    rho_host = workload.density()
     K = torch.tensor(workload.trajectory(), dtype=prm.dtype, device=dev)
-    rho = torch.tensor(workload.density(), dtype=prm.dtype, device=dev)
+    rho = torch.tensor(rho_host, dtype=prm.dtype, device=dev)
+    eta = fixed_step(prm, float(rho_host.sum()), eta_rule, workload.eta_fixed)
     viol0 = api.project_(K, prm)
     state = api.StepState(prm, dev)
     records = []
     for it in range(iters):
         torch.cuda.synchronize(dev)
         t0 = time.perf_counter()
-        info = api.step_(K, rho, prm, state, it, workload.eta_fixed)
+        info = api.step_(K, rho, prm, state, it, eta)
         torch.cuda.synchronize(dev)
         rec = {"iter": it, "precision": precision, "F": info["F"], "Fa": info["Fa"],
                "Fr": info["Fr"], "eta": info["eta"], "bb_used": info["bb_used"],
@@ -65,7 +76,7 @@ def run(workload: configs.Workload, precision: str, iters: int, device="cuda:0",
 
 def multiresolution(K0: torch.Tensor, rho: torch.Tensor, prm_full: api.Params, levels: int,
                     n_git: int, final_level: bool = True, eta_scale: float = 0.25, out=None,
-                    log_every: int = 0):
+                    log_every: int = 0, eta_rule: str = "fixed"):
     """Algorithm 1 (multi-resolution SPARKLING) on the GPU.
 
     K0 holds the coarsest shots, prm_full.n_samples >> levels samples each.  At
@@ -75,7 +86,9 @@ def multiresolution(K0: torch.Tensor, rho: torch.Tensor, prm_full: api.Params, l
     Barzilai-Borwein after (state reset per level, eta_fixed from the level's
     p), and the result is up-sampled to twice the samples as the warm start of
     the next level.  With final_level=True the full resolution (d = 0) is
-    optimised as well.  Returns the final K and the per-iteration records.
+    optimised as well.  eta_rule="lipschitz" takes the fixed step 1/L of the
+    regularised kernel at each level instead.  Returns the final K and the
+    per-iteration records.
     """
     if prm_full.n_samples % (1 << levels):
         raise ValueError("n_samples must be divisible by 2^levels")
@@ -87,11 +100,12 @@ def multiresolution(K0: torch.Tensor, rho: torch.Tensor, prm_full: api.Params, l
                          half_width=prm_full.half_width, eps=prm_full.eps,
                          a_max=prm_full.a_max * 2.0 ** d, b_max=prm_full.b_max * 2.0 ** d,
                          te_index=prm_full.te_index, n_pit=prm_full.n_pit,
-                         rotation_variant=prm_full.rotation_variant,
+                         rotation_variant=prm_full.rotation_variant, kernel=prm_full.kernel,
                          attraction_field=prm_full.attraction_field)
         if K.shape[1] != prm.p:
             raise ValueError(f"level {d}: K has {K.shape[1]} samples, expected {prm.p}")
-        eta = eta_scale * (2.0 * prm.half_width) * float(prm.p) ** (2.0 / 3.0)
+        eta = fixed_step(prm, float(rho.sum().item()), eta_rule,
+                         eta_scale * (2.0 * prm.half_width) * float(prm.p) ** (2.0 / 3.0))
         state = api.StepState(prm, K.device)
         for it in range(n_git):
             torch.cuda.synchronize(K.device)
@@ -127,6 +141,10 @@ def main():
                     help="evaluate the attraction by the grid interpolant")
     ap.add_argument("--rotation-variant", action="store_true",
                     help="per-axis gradient and slew bounds instead of Euclidean ones")
+    ap.add_argument("--kernel", choices=["distance", "log"], default="distance")
+    ap.add_argument("--eps", type=float, default=0.0, help="kernel regulariser")
+    ap.add_argument("--eta", choices=["fixed", "lipschitz"], default="fixed",
+                    help="fixed step of the first iterations: the workload's, or 1/L")
     args = ap.parse_args()
     w = configs.WORKLOADS[args.workload]
     precision = args.precision or w.precision
@@ -136,7 +154,8 @@ def main():
     try:
         if args.levels == 0 and not args.field:
             run(w, precision, iters, out=out, log_every=args.log_every,
-                rotation_variant=args.rotation_variant)
+                rotation_variant=args.rotation_variant, kernel=args.kernel, eps=args.eps,
+                eta_rule=args.eta)
         else:
             dev = torch.device("cuda:0")
             a, b = api.alpha_beta(configs.GMAX, configs.SMAX, configs.RASTER_DT,
@@ -144,7 +163,8 @@ def main():
                                   w.half_width)
             prm = api.Params(w.n_shots, w.n_samples, w.grid, precision=precision,
                              half_width=w.half_width, a_max=a, b_max=b, te_index=0,
-                             n_pit=w.n_pit, rotation_variant=args.rotation_variant)
+                             n_pit=w.n_pit, rotation_variant=args.rotation_variant,
+                             kernel=args.kernel, eps=args.eps)
             from . import inputs
             K0 = inputs.radial_spokes(w.n_shots, w.n_samples >> args.levels, w.half_width,
                                       w.seed, w.jitter)
@@ -157,7 +177,7 @@ def main():
                 print(f"[driver] node field in {time.perf_counter() - t0:.2f} s",
                       file=sys.stderr, flush=True)
             K, recs = multiresolution(K0, rho, prm, args.levels, iters, out=out,
-                                      log_every=args.log_every)
+                                      log_every=args.log_every, eta_rule=args.eta)
             torch.cuda.synchronize(dev)
             total = time.perf_counter() - t0
             F, _, _, _ = api.energy(K, rho, prm)
