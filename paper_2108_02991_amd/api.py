@@ -170,6 +170,11 @@ def workspace(prm: Params, device) -> torch.Tensor:
     return ws
 
 
+def release_workspaces():
+    """Drop the cached device workspaces (they only grow otherwise)."""
+    _ws_cache.clear()
+
+
 def _stream(t: torch.Tensor):
     return _vp(torch.cuda.current_stream(t.device).cuda_stream)
 

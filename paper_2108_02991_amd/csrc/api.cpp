@@ -169,6 +169,8 @@ struct Plan {
 constexpr double kMaxPairsPerLaunch = 1099511627776.0;   // 2^40
 // Blocks a launch should have to fill 256 CUs several times over.
 constexpr int64_t kWantBlocks = 2048;
+// Slabs one launch may carry (the grid's y extent).
+constexpr int64_t kMaxSlabsPerLaunch = 65535;
 
 Plan make_plan(int precision, bool cells, int64_t p_total, int64_t n_src, int64_t G)
 {
@@ -190,16 +192,23 @@ Plan make_plan(int precision, bool cells, int64_t p_total, int64_t n_src, int64_
     pl.slab = slab;
     pl.nslab = (n_src + slab - 1) / slab;
     const int64_t fit = (int64_t)(max_pairs / (per_src * (double)slab));
-    pl.per_launch = std::max<int64_t>(1, std::min<int64_t>(pl.nslab, fit));
+    pl.per_launch = std::max<int64_t>(1, std::min({pl.nslab, fit, kMaxSlabsPerLaunch}));
     return pl;
 }
 
 // Workspace layout (offsets from a 256-byte aligned base).
 struct Layout {
     size_t acc_a = 0, acc_r = 0, part = 0, red = 0, scal = 0, grad = 0, viol = 0, cells = 0;
+    size_t chunk_sums = 0;
     size_t total = 0;
     int64_t ld = 0;
+    int64_t part_rows = 0;   // capacity of the slab partials, in rows of 4 doubles
 };
+
+// Targets per pass of the sweeps whose targets are grid points (the node
+// field, the cell centres of the self-energy), so that the accumulators
+// stay at max(p, this) rows however large the grid is.
+constexpr int64_t kGridTargetChunk = int64_t(1) << 21;
 
 size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
@@ -211,15 +220,18 @@ Layout make_layout(const spk_params *prm)
     const int64_t p = prm->n_shots * prm->n_samples;
     const int64_t G = prm->grid, M = G * G * G, Mn = field_nodes(G);
     const bool disc = prm->flags & SPK_FLAG_DISCREPANCY;
-    // targets of one sweep: the samples, or the nodes of the field precompute
-    // (which also covers the cell centres of the self-energy, M < Mn)
-    const int64_t nt = std::max(p, Mn);
+    // targets of one sweep call: the samples, or one pass of field nodes
+    // (which also covers a pass of cell centres of the self-energy, M < Mn)
+    const int64_t cn = std::min(Mn, kGridTargetChunk), cm = std::min(M, kGridTargetChunk);
+    const int64_t nt = std::max(p, cn);
+    // slab partials: targets of a call times the slabs of one launch, per sweep kind
     const Plan pr = make_plan(prm->precision, false, p, p, G);
     const Plan pa = make_plan(prm->precision, true, p, G * G, G);
-    int64_t pl = std::max(pr.per_launch, pa.per_launch);
-    pl = std::max(pl, make_plan(prm->precision, true, Mn, G * G, G).per_launch);
+    int64_t part_rows = p * std::max(pr.per_launch, pa.per_launch);
+    part_rows = std::max(part_rows, cn * make_plan(prm->precision, true, Mn, G * G, G).per_launch);
     if (disc)
-        pl = std::max(pl, make_plan(prm->precision, true, M, G * G, G).per_launch);
+        part_rows = std::max(part_rows,
+                             cm * make_plan(prm->precision, true, M, G * G, G).per_launch);
     size_t off = 0;
     auto take = [&](size_t bytes) {
         size_t o = off;
@@ -229,12 +241,14 @@ Layout make_layout(const spk_params *prm)
     L.ld = nt;
     L.acc_a = take(sizeof(double) * 4 * nt);
     L.acc_r = take(sizeof(double) * 4 * nt);
-    L.part = take(sizeof(double) * 4 * nt * pl);
+    L.part = take(sizeof(double) * 4 * part_rows);
+    L.part_rows = part_rows;
     L.red = take(sizeof(double) * reduce_partials_size(std::max(nt, 3 * p)));
     L.scal = take(sizeof(double) * 16);
     L.grad = take(elt_size(prm->precision) * 3 * p);
     L.viol = take(sizeof(double) * 4 * prm->n_shots);
-    L.cells = take(elt_size(prm->precision) * 3 * Mn);
+    L.cells = take(elt_size(prm->precision) * 3 * cn);
+    L.chunk_sums = take(sizeof(double) * ((M + kGridTargetChunk - 1) / kGridTargetChunk));
     L.total = off + 256;   // slack for aligning the caller's base pointer
     return L;
 }
@@ -246,6 +260,7 @@ struct Ws {
     double *acc_r() const { return reinterpret_cast<double *>(base + L.acc_r); }
     double *part() const { return reinterpret_cast<double *>(base + L.part); }
     double *red() const { return reinterpret_cast<double *>(base + L.red); }
+    double *chunk_sums() const { return reinterpret_cast<double *>(base + L.chunk_sums); }
     double *scal() const { return reinterpret_cast<double *>(base + L.scal); }
     void *grad() const { return base + L.grad; }
     double *viol() const { return reinterpret_cast<double *>(base + L.viol); }
@@ -292,12 +307,27 @@ int run_sweep(const spk_params *prm, bool cells, const void *tx, const void *ty,
     l.slab = pl.slab;
     l.src_end = n_src;
     l.part = w.part();
-    l.ld = w.L.ld;
+    l.ld = nt;   // the slab partials of this call: [slab][4][nt]
     const int kind = cells ? SPK_KIND_ATTRACTION : SPK_KIND_REPULSION;
+    // Slab boundaries depend on p_total only.  A call with few targets groups
+    // more slabs per launch (bounded by the partial buffer, the pairs of one
+    // launch and the grid's y extent); the combine still adds every target's
+    // slabs in slab order, so the grouping does not change any result bit.
+    int64_t per_launch = pl.per_launch;
+    if (nt > 0) {
+        const double max_pairs =
+            prm->precision == SPK_PLAIN_FP64 ? kMaxPairsPerLaunch / 2 : kMaxPairsPerLaunch;
+        int64_t more = std::min<int64_t>(pl.nslab, w.L.part_rows / nt);
+        more = std::min<int64_t>(
+            more, std::max<int64_t>(1, (int64_t)(max_pairs / ((double)nt * (double)pl.slab *
+                                                              (double)pl.unit))));
+        more = std::min<int64_t>(more, kMaxSlabsPerLaunch);
+        per_launch = std::max(per_launch, more);
+    }
     bool first = true;
-    for (int64_t s0 = 0; s0 < pl.nslab; s0 += pl.per_launch) {
+    for (int64_t s0 = 0; s0 < pl.nslab; s0 += per_launch) {
         l.src_begin = s0 * pl.slab;
-        l.nslabs = (int)std::min<int64_t>(pl.per_launch, pl.nslab - s0);
+        l.nslabs = (int)std::min<int64_t>(per_launch, pl.nslab - s0);
         const int64_t src_hi = std::min<int64_t>(n_src, (s0 + l.nslabs) * pl.slab);
         const double pairs = (double)nt * (double)(src_hi - l.src_begin) * (double)pl.unit;
         {
@@ -308,7 +338,7 @@ int run_sweep(const spk_params *prm, bool cells, const void *tx, const void *ty,
         }
         {
             Timed tm(SPK_KIND_OTHER, 0.0, s);
-            SPK_HIP(launch_combine(acc, w.part(), l.nslabs, w.L.ld, nt, first, s), "combine");
+            SPK_HIP(launch_combine(acc, w.L.ld, w.part(), nt, l.nslabs, nt, first, s), "combine");
         }
         first = false;
     }
@@ -530,20 +560,26 @@ int sparkling_field(const spk_params *prm, const void *rho, void *field, void *w
         return rc;
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int64_t G = prm->grid, Mn = field_nodes(G);
+    const int64_t cap = std::min(Mn, kGridTargetChunk);
     char *pts = static_cast<char *>(w.cells());
-    void *nx = pts, *ny = pts + al * Mn, *nz = pts + 2 * al * Mn;
-    {
-        Timed tm(SPK_KIND_OTHER, 0.0, s);
-        SPK_HIP(launch_node_coords(prm->precision, G, prm->half_width, nx, ny, nz, s),
-                "node coordinates");
-    }
+    void *nx = pts, *ny = pts + al * cap, *nz = pts + 2 * al * cap;
     spk_params direct = *prm;
     direct.attraction_field = nullptr;
-    if ((rc = run_sweep(&direct, true, nx, ny, nz, 0, Mn, Mn, nullptr, nullptr, nullptr, rho, true,
-                        w, w.acc_a(), s)))
-        return rc;
-    Timed tm(SPK_KIND_OTHER, 0.0, s);
-    SPK_HIP(launch_field_pack(prm->precision, w.acc_a(), w.L.ld, Mn, field, s), "field pack");
+    // passes of at most `cap` nodes; the sweep plan depends on Mn only
+    for (int64_t n0 = 0; n0 < Mn; n0 += cap) {
+        const int64_t n = std::min(cap, Mn - n0);
+        {
+            Timed tm(SPK_KIND_OTHER, 0.0, s);
+            SPK_HIP(launch_node_coords(prm->precision, G, prm->half_width, n0, n, nx, ny, nz, s),
+                    "node coordinates");
+        }
+        if ((rc = run_sweep(&direct, true, nx, ny, nz, 0, n, Mn, nullptr, nullptr, nullptr, rho,
+                            true, w, w.acc_a(), s)))
+            return rc;
+        Timed tm(SPK_KIND_OTHER, 0.0, s);
+        SPK_HIP(launch_field_pack(prm->precision, w.acc_a(), w.L.ld, n0, n, field, s),
+                "field pack");
+    }
     return SPK_OK;
 }
 
@@ -569,36 +605,50 @@ int sparkling_energy(const spk_params *prm, const void *kx, const void *ky, cons
     if ((rc = reduce_energy(w, p, s)))
         return rc;
     const bool disc = prm->flags & SPK_FLAG_DISCREPANCY;
+    double self_sum = 0.0;
     if (disc) {
-        // E_rho = 1/2 sum_v rho_v sum_u rho_u H(x_v - x_u): a cell sweep whose
-        // targets are the cell centres themselves.
+        // E_rho = 1/2 sum_v rho_v sum_u rho_u H(x_v - x_u): cell sweeps whose
+        // targets are the cell centres themselves, in passes of at most `cap`
+        // cells; each pass's weighted sum lands in its own slot, and the
+        // slots are added in pass order on the host.
         const int64_t G = prm->grid, M = G * G * G;
+        const int64_t cap = std::min(M, kGridTargetChunk);
+        const int64_t passes = (M + cap - 1) / cap;
         char *cells = static_cast<char *>(w.cells());
-        void *cx = cells, *cy = cells + al * M, *cz = cells + 2 * al * M;
-        {
-            Timed tm(SPK_KIND_OTHER, 0.0, s);
-            SPK_HIP(launch_cell_centres(prm->precision, G, prm->half_width, cx, cy, cz, s),
-                    "cell centres");
-        }
+        void *cx = cells, *cy = cells + al * cap, *cz = cells + 2 * al * cap;
         spk_params direct = *prm;
         direct.attraction_field = nullptr;
-        if ((rc = run_sweep(&direct, true, cx, cy, cz, 0, M, M, nullptr, nullptr, nullptr, rho,
-                            true, w, w.acc_a(), s)))
+        for (int64_t k = 0; k < passes; ++k) {
+            const int64_t v0 = k * cap, n = std::min(cap, M - v0);
+            {
+                Timed tm(SPK_KIND_OTHER, 0.0, s);
+                SPK_HIP(launch_cell_centres(prm->precision, G, prm->half_width, v0, n, cx, cy, cz,
+                                            s),
+                        "cell centres");
+            }
+            if ((rc = run_sweep(&direct, true, cx, cy, cz, 0, n, M, nullptr, nullptr, nullptr,
+                                rho, true, w, w.acc_a(), s)))
+                return rc;
+            Timed tm(SPK_KIND_OTHER, 0.0, s);
+            SPK_HIP(launch_wsum(static_cast<const char *>(rho) + al * v0, prm->precision,
+                                w.acc_a() + 3 * w.L.ld, n, w.red(), w.chunk_sums() + k, s),
+                    "self-energy reduction");
+        }
+        std::vector<double> part((size_t)passes);
+        if ((rc = copy_to_host(part.data(), w.chunk_sums(), (size_t)passes, s)))
             return rc;
-        Timed tm(SPK_KIND_OTHER, 0.0, s);
-        SPK_HIP(launch_wsum(rho, prm->precision, w.acc_a() + 3 * w.L.ld, M, w.red(),
-                            w.scal() + 2, s),
-                "self-energy reduction");
+        for (double v : part)
+            self_sum += v;
     }
-    double sums[4];
-    if ((rc = copy_to_host(sums, w.scal(), disc ? 3 : 2, s)))
+    double sums[2];
+    if ((rc = copy_to_host(sums, w.scal(), 2, s)))
         return rc;
     double e3[3];
     energies_from_sums(p, sums, e3);
     out[0] = e3[0];
     out[1] = e3[1];
     out[2] = e3[2];
-    out[3] = disc ? e3[0] - 0.5 * sums[2] : NAN;
+    out[3] = disc ? e3[0] - 0.5 * self_sum : NAN;
     return SPK_OK;
 }
 

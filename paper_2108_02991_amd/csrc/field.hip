@@ -25,25 +25,27 @@ __device__ inline double node_coord(int64_t k, int64_t G, double L)
 }
 
 template <typename T>
-__global__ __launch_bounds__(EW) void node_coords_kernel(int64_t G, double L, T *nx, T *ny, T *nz)
+__global__ __launch_bounds__(EW) void node_coords_kernel(int64_t G, double L, int64_t n0,
+                                                         int64_t cnt, T *nx, T *ny, T *nz)
 {
     const int64_t Gn = G + 2;
-    const int64_t n = (int64_t)blockIdx.x * EW + threadIdx.x;
-    if (n >= Gn * Gn * Gn)
+    const int64_t i = (int64_t)blockIdx.x * EW + threadIdx.x;
+    if (i >= cnt)
         return;
-    nx[n] = (T)node_coord(n % Gn, G, L);
-    ny[n] = (T)node_coord((n / Gn) % Gn, G, L);
-    nz[n] = (T)node_coord(n / (Gn * Gn), G, L);
+    const int64_t n = n0 + i;
+    nx[i] = (T)node_coord(n % Gn, G, L);
+    ny[i] = (T)node_coord((n / Gn) % Gn, G, L);
+    nz[i] = (T)node_coord(n / (Gn * Gn), G, L);
 }
 
 template <typename T>
-__global__ __launch_bounds__(EW) void field_pack_kernel(const double *acc, int64_t ld, int64_t Mn,
-                                                        Q4<T> *field)
+__global__ __launch_bounds__(EW) void field_pack_kernel(const double *acc, int64_t ld,
+                                                        int64_t cnt, Q4<T> *field)
 {
-    const int64_t n = (int64_t)blockIdx.x * EW + threadIdx.x;
-    if (n >= Mn)
+    const int64_t i = (int64_t)blockIdx.x * EW + threadIdx.x;
+    if (i >= cnt)
         return;
-    field[n] = Q4<T>{(T)acc[3 * ld + n], (T)acc[n], (T)acc[ld + n], (T)acc[2 * ld + n]};
+    field[i] = Q4<T>{(T)acc[3 * ld + i], (T)acc[i], (T)acc[ld + i], (T)acc[2 * ld + i]};
 }
 
 // Lower node and upper weight along one axis: t = (x - X_0)/h, k0 = floor(t)
@@ -101,28 +103,31 @@ inline unsigned ew_blocks(int64_t n) { return (unsigned)((n + EW - 1) / EW); }
 
 }  // namespace
 
-hipError_t launch_node_coords(int precision, int64_t G, double L, void *nx, void *ny, void *nz,
-                              hipStream_t s)
+hipError_t launch_node_coords(int precision, int64_t G, double L, int64_t n0, int64_t n, void *nx,
+                              void *ny, void *nz, hipStream_t s)
 {
-    const int64_t Mn = (G + 2) * (G + 2) * (G + 2);
+    if (n <= 0)
+        return hipSuccess;
     if (precision == SPK_PLAIN_FP64)
-        hipLaunchKernelGGL(node_coords_kernel<double>, dim3(ew_blocks(Mn)), dim3(EW), 0, s, G, L,
-                           (double *)nx, (double *)ny, (double *)nz);
+        hipLaunchKernelGGL(node_coords_kernel<double>, dim3(ew_blocks(n)), dim3(EW), 0, s, G, L,
+                           n0, n, (double *)nx, (double *)ny, (double *)nz);
     else
-        hipLaunchKernelGGL(node_coords_kernel<float>, dim3(ew_blocks(Mn)), dim3(EW), 0, s, G, L,
-                           (float *)nx, (float *)ny, (float *)nz);
+        hipLaunchKernelGGL(node_coords_kernel<float>, dim3(ew_blocks(n)), dim3(EW), 0, s, G, L,
+                           n0, n, (float *)nx, (float *)ny, (float *)nz);
     return hipGetLastError();
 }
 
-hipError_t launch_field_pack(int precision, const double *acc, int64_t ld, int64_t Mn, void *field,
-                             hipStream_t s)
+hipError_t launch_field_pack(int precision, const double *acc, int64_t ld, int64_t n0, int64_t n,
+                             void *field, hipStream_t s)
 {
+    if (n <= 0)
+        return hipSuccess;
     if (precision == SPK_PLAIN_FP64)
-        hipLaunchKernelGGL(field_pack_kernel<double>, dim3(ew_blocks(Mn)), dim3(EW), 0, s, acc, ld,
-                           Mn, (Q4<double> *)field);
+        hipLaunchKernelGGL(field_pack_kernel<double>, dim3(ew_blocks(n)), dim3(EW), 0, s, acc, ld,
+                           n, (Q4<double> *)field + n0);
     else
-        hipLaunchKernelGGL(field_pack_kernel<float>, dim3(ew_blocks(Mn)), dim3(EW), 0, s, acc, ld,
-                           Mn, (Q4<float> *)field);
+        hipLaunchKernelGGL(field_pack_kernel<float>, dim3(ew_blocks(n)), dim3(EW), 0, s, acc, ld,
+                           n, (Q4<float> *)field + n0);
     return hipGetLastError();
 }
 

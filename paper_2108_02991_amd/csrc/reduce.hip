@@ -13,8 +13,9 @@ constexpr int EW = 256;        // threads per elementwise block
 
 inline unsigned ew_blocks(int64_t n) { return (unsigned)((n + EW - 1) / EW); }
 
-__global__ __launch_bounds__(EW) void combine_kernel(double *acc, const double *part, int nslabs,
-                                                     int64_t ld, int64_t nt, int init)
+__global__ __launch_bounds__(EW) void combine_kernel(double *acc, int64_t ld, const double *part,
+                                                     int64_t part_ld, int nslabs, int64_t nt,
+                                                     int init)
 {
     const int64_t e = (int64_t)blockIdx.x * EW + threadIdx.x;
     if (e >= 4 * nt)
@@ -23,7 +24,7 @@ __global__ __launch_bounds__(EW) void combine_kernel(double *acc, const double *
     const int64_t o = c * ld + t;
     double v = init ? 0.0 : acc[o];
     for (int y = 0; y < nslabs; ++y)
-        v += part[((int64_t)y * 4 + c) * ld + t];
+        v += part[((int64_t)y * 4 + c) * part_ld + t];
     acc[o] = v;
 }
 
@@ -168,14 +169,16 @@ __device__ inline double cell_centre(int64_t i, int64_t G, double L)
 }
 
 template <typename T>
-__global__ __launch_bounds__(EW) void cell_centres_kernel(int64_t G, double L, T *cx, T *cy, T *cz)
+__global__ __launch_bounds__(EW) void cell_centres_kernel(int64_t G, double L, int64_t v0,
+                                                          int64_t cnt, T *cx, T *cy, T *cz)
 {
-    const int64_t v = (int64_t)blockIdx.x * EW + threadIdx.x;
-    if (v >= G * G * G)
+    const int64_t i = (int64_t)blockIdx.x * EW + threadIdx.x;
+    if (i >= cnt)
         return;
-    cx[v] = (T)cell_centre(v % G, G, L);
-    cy[v] = (T)cell_centre((v / G) % G, G, L);
-    cz[v] = (T)cell_centre(v / (G * G), G, L);
+    const int64_t v = v0 + i;
+    cx[i] = (T)cell_centre(v % G, G, L);
+    cy[i] = (T)cell_centre((v / G) % G, G, L);
+    cz[i] = (T)cell_centre(v / (G * G), G, L);
 }
 
 template <typename T>
@@ -236,13 +239,13 @@ hipError_t launch_upsample(int precision, const void *kx, const void *ky, const 
     return hipGetLastError();
 }
 
-hipError_t launch_combine(double *acc, const double *part, int nslabs, int64_t ld, int64_t nt,
-                          bool init, hipStream_t s)
+hipError_t launch_combine(double *acc, int64_t ld, const double *part, int64_t part_ld,
+                          int nslabs, int64_t nt, bool init, hipStream_t s)
 {
     if (nt <= 0)
         return hipSuccess;
-    hipLaunchKernelGGL(combine_kernel, dim3(ew_blocks(4 * nt)), dim3(EW), 0, s, acc, part, nslabs,
-                       ld, nt, init ? 1 : 0);
+    hipLaunchKernelGGL(combine_kernel, dim3(ew_blocks(4 * nt)), dim3(EW), 0, s, acc, ld, part,
+                       part_ld, nslabs, nt, init ? 1 : 0);
     return hipGetLastError();
 }
 
@@ -283,16 +286,17 @@ hipError_t launch_wsum(const void *w, int precision, const double *x, int64_t n,
     return run_sum(WeightedF<float>{(const float *)w, x}, n, partials, out, s);
 }
 
-hipError_t launch_cell_centres(int precision, int64_t G, double L, void *cx, void *cy, void *cz,
-                               hipStream_t s)
+hipError_t launch_cell_centres(int precision, int64_t G, double L, int64_t v0, int64_t n,
+                               void *cx, void *cy, void *cz, hipStream_t s)
 {
-    const int64_t M = G * G * G;
+    if (n <= 0)
+        return hipSuccess;
     if (precision == SPK_PLAIN_FP64)
-        hipLaunchKernelGGL(cell_centres_kernel<double>, dim3(ew_blocks(M)), dim3(EW), 0, s, G, L,
-                           (double *)cx, (double *)cy, (double *)cz);
+        hipLaunchKernelGGL(cell_centres_kernel<double>, dim3(ew_blocks(n)), dim3(EW), 0, s, G, L,
+                           v0, n, (double *)cx, (double *)cy, (double *)cz);
     else
-        hipLaunchKernelGGL(cell_centres_kernel<float>, dim3(ew_blocks(M)), dim3(EW), 0, s, G, L,
-                           (float *)cx, (float *)cy, (float *)cz);
+        hipLaunchKernelGGL(cell_centres_kernel<float>, dim3(ew_blocks(n)), dim3(EW), 0, s, G, L,
+                           v0, n, (float *)cx, (float *)cy, (float *)cz);
     return hipGetLastError();
 }
 

@@ -80,9 +80,10 @@ struct SweepLaunch {
 hipError_t launch_sweep_samples(const SweepLaunch &l, hipStream_t s);
 hipError_t launch_sweep_cells(const SweepLaunch &l, hipStream_t s);
 
-// acc[c*ld + t] = (init ? 0 : acc[c*ld + t]) + part[0][c][t] + ... + part[n-1][c][t]
-hipError_t launch_combine(double *acc, const double *part, int nslabs, int64_t ld, int64_t nt,
-                          bool init, hipStream_t s);
+// acc[c*ld + t] = (init ? 0 : acc[c*ld + t]) + part[0][c][t] + ... + part[n-1][c][t],
+// with part[y][c][t] at part[(y*4 + c)*part_ld + t].
+hipError_t launch_combine(double *acc, int64_t ld, const double *part, int64_t part_ld,
+                          int nslabs, int64_t nt, bool init, hipStream_t s);
 
 // g[c][t] = acc_a[c][t] * inv_p - acc_r[c][t] * inv_p2 (cast to the precision's type);
 // pot_a/pot_r (nullable) receive row 3 of acc_a/acc_r.
@@ -100,17 +101,20 @@ hipError_t launch_sum2(const double *x0, const double *x1, int64_t n, double *pa
 hipError_t launch_wsum(const void *w, int precision, const double *x, int64_t n,
                        double *partials, double *out, hipStream_t s);
 
-// Voxel-centre coordinates of the G^3 grid (x fastest) into cx, cy, cz (precision type).
-hipError_t launch_cell_centres(int precision, int64_t G, double L, void *cx, void *cy, void *cz,
-                               hipStream_t s);
+// Voxel-centre coordinates of cells v0 .. v0+n-1 of the G^3 grid (x fastest)
+// into cx, cy, cz[0 .. n-1] (precision type).
+hipError_t launch_cell_centres(int precision, int64_t G, double L, int64_t v0, int64_t n,
+                               void *cx, void *cy, void *cz, hipStream_t s);
 
 // Grid attraction: node coordinates (G+2 per axis), packing of node sums into
 // the [n][4] field, and the trilinear interpolant writing the four attraction
 // sums of targets [t0, t0+nt) into acc rows (like a cell sweep would).
-hipError_t launch_node_coords(int precision, int64_t G, double L, void *nx, void *ny, void *nz,
-                              hipStream_t s);
-hipError_t launch_field_pack(int precision, const double *acc, int64_t ld, int64_t Mn, void *field,
-                             hipStream_t s);
+// Node coordinates of nodes n0 .. n0+n-1 into nx, ny, nz[0 .. n-1]; packing of
+// acc rows 0 .. n-1 into field nodes n0 .. n0+n-1.
+hipError_t launch_node_coords(int precision, int64_t G, double L, int64_t n0, int64_t n, void *nx,
+                              void *ny, void *nz, hipStream_t s);
+hipError_t launch_field_pack(int precision, const double *acc, int64_t ld, int64_t n0, int64_t n,
+                             void *field, hipStream_t s);
 hipError_t launch_interpolate(int precision, const void *kx, const void *ky, const void *kz,
                               int64_t t0, int64_t nt, int64_t G, double L, const void *field,
                               double *acc, int64_t ld, hipStream_t s);

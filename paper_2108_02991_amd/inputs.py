@@ -48,6 +48,16 @@ def uniform_density(G: int) -> np.ndarray:
     return np.full(G ** 3, 1.0 / G ** 3)
 
 
+def separable_density(G: int, seed: int, dtype=np.float64) -> np.ndarray:
+    """Random positive weights a[ix] b[iy] c[iz] on the G^3 grid (x fastest),
+    normalised to sum 1: non-uniform in every axis yet cheap at very large G."""
+    rng = np.random.default_rng(seed)
+    a, b, c = (rng.uniform(0.5, 1.5, G) for _ in range(3))
+    a, b, c = a / a.sum(), b / b.sum(), c / c.sum()
+    out = np.multiply.outer(np.multiply.outer(c, b), a).astype(dtype, copy=False)
+    return out.reshape(-1)
+
+
 def radial_spokes(n_shots: int, n_samples: int, L: float, seed: int,
                   jitter: float = 0.0) -> np.ndarray:
     """Centre-out radial spokes with uniform random directions, optionally jittered.
