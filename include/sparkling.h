@@ -59,6 +59,10 @@
 extern "C" {
 #endif
 
+/* The library is built with hidden visibility; these declarations are its
+ * exported interface. */
+#pragma GCC visibility push(default)
+
 typedef enum {
     SPK_OK = 0,
     SPK_EINVAL = -1,        /* bad argument; nothing launched                     */
@@ -284,6 +288,8 @@ enum {
 int spk_timing_enable(int on);
 int spk_timing_query(int kind, double *total_ms, int64_t *launches, double *pairs);
 int spk_timing_reset(void);
+
+#pragma GCC visibility pop
 
 #ifdef __cplusplus
 }

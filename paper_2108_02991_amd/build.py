@@ -23,6 +23,8 @@ SOURCES = ["sweep.hip", "reduce.hip", "project.hip", "field.hip", "api.cpp"]
 # turned into v_pk_* FP32 operations on this target.
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result",
+    # host symbols other than the C ABI stay out of the dynamic symbol table
+    "-Xarch_host", "-fvisibility=hidden",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", str(ROOT / "include"), "-I", str(CSRC),
 ]

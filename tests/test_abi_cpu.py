@@ -41,6 +41,19 @@ def test_every_declared_symbol_is_exported(lib):
         assert hasattr(lib, n), n
 
 
+def test_only_the_c_abi_is_exported(lib):
+    import shutil
+    import subprocess
+    nm = shutil.which("nm")
+    if nm is None:
+        pytest.skip("nm is not available")
+    out = subprocess.run([nm, "-D", "--defined-only", str(api.LIB_PATH)], capture_output=True,
+                         text=True, check=True).stdout
+    text = {ln.split()[-1] for ln in out.splitlines() if len(ln.split()) == 3
+            and ln.split()[1] == "T"}
+    assert text == set(declared_functions())
+
+
 def test_status_strings(lib):
     for code in (0, -1, -2, -3, -4, -5):
         assert lib.spk_status_string(code)
