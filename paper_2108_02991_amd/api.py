@@ -8,6 +8,7 @@ is no fallback path.
 from __future__ import annotations
 
 import ctypes
+import dataclasses
 from dataclasses import dataclass, field
 from pathlib import Path
 
@@ -350,7 +351,7 @@ class SparklingEnergy(torch.autograd.Function):
     def forward(ctx, K, rho, prm: Params, chunk: int = 8192):
         F, _, _, _ = energy(K, rho, prm)
         ctx.save_for_backward(K, rho)
-        ctx.prm = prm
+        ctx.prm = dataclasses.replace(prm)   # later changes to prm do not reach backward
         ctx.chunk = chunk
         return torch.tensor(F, dtype=torch.float64, device=K.device)
 

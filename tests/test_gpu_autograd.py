@@ -18,6 +18,21 @@ def test_gradcheck_plain_fp64(gpu):
     assert torch.autograd.gradcheck(f, (Kd,), eps=1e-6, atol=1e-9, rtol=1e-6)
 
 
+def test_gradcheck_log_kernel(gpu):
+    K = inputs.uniform_points(48, 0.5, seed=5)
+    rho = inputs.radial_density(4, 0.5, 0.1, 2.0)
+    prm = spk.Params(3, 16, 4, precision="plain_fp64", eps=0.05, kernel="log")
+    Kd, rd = device_problem(K, rho, "plain_fp64", gpu)
+    Kd.requires_grad_(True)
+    f = lambda k: spk.SparklingEnergy.apply(k, rd, prm, 16)
+    assert torch.autograd.gradcheck(f, (Kd,), eps=1e-6, atol=1e-9, rtol=1e-6)
+    F = f(Kd)
+    prm.kernel = "distance"        # a later change of prm does not reach backward
+    F.backward()
+    ref = oracle.grad(K, rho, 4, 0.5, 0.05, kernel="log")["dF"]
+    assert rel_l2(host64(Kd.grad), ref) <= 1e-12
+
+
 def test_coincident_samples_backward_matches_central_differences(gpu):
     """Every shot starts at the origin: the zero subgradient is what central FD sees."""
     K = inputs.radial_spokes(4, 8, 0.5, seed=2, jitter=0.05)

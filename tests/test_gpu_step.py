@@ -105,3 +105,31 @@ def test_per_axis_steps_plain_fp64(gpu):
         assert info["F"] == pytest.approx(oinfo["F"], rel=1e-12)
         assert np.abs(host64(Kd) - Ko).max() <= 1e-10
         np.testing.assert_allclose(info["viol"], oinfo["viol"], rtol=1e-8)
+
+
+def test_c3_step_sampled_shots(gpu):
+    """One step of the benchmark's configuration (4096 x 2048 samples, 192^3 density,
+    FP32-compensated, n_pit = 200), checked on two whole shots: the oracle's gradient
+    rows of those shots, the same descent, and the oracle's projection of each shot."""
+    w = configs.C3
+    K, rho = w.trajectory(), w.density()
+    prm = params_for(w, "fp32_comp")
+    a, b = prm.a_max, prm.b_max
+    Kd, rd = device_problem(K, rho, "fp32_comp", gpu)
+    K0 = host64(Kd)
+    state = spk.StepState(prm, gpu)
+    say("  c3 step")
+    info = spk.step_(Kd, rd, prm, state, 0, w.eta_fixed)
+    K1 = host64(Kd)
+    Ns, last = w.n_samples, w.n_shots - 1
+    t = np.concatenate([np.arange(Ns), last * Ns + np.arange(Ns)])
+    say("  c3 oracle gradient on 2 shots (4096 targets)")
+    g = oracle.grad(K0, host64(rd), w.grid, 0.5, 0.0, t)["dF"]
+    half = K0[:, t] - info["eta"] * g
+    want = oracle.project(half, 2, Ns, 0.5, a, b, 0, w.n_pit)
+    got = K1[:, t]
+    diff = np.abs(got - want).max()
+    say(f"  c3 step: eta {info['eta']:.6g}, max |K_gpu - K_oracle| on 2 shots {diff:.3e}")
+    assert info["eta"] == w.eta_fixed
+    assert diff <= 1e-6     # FP32 storage of K (about 3e-8 at |k| <= 0.5) plus FP32-comp rows
+    assert np.all(got[:, [0, Ns]] == 0.0) and np.abs(got).max() <= 0.5
