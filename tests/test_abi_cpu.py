@@ -86,6 +86,19 @@ def test_workspace_size_monotone(lib):
     assert spk.workspace_size(spk.Params(4096, 2048, 192)) < 2 * 2 ** 30
 
 
+def test_workspace_does_not_scale_with_grid_times_slabs(lib):
+    """Few samples on the largest grid: partials are sized per sweep kind and the
+    grid-target sweeps run in passes, so the workspace stays small."""
+    for prec in ("fp32_comp", "plain_fp64"):
+        for disc in (False, True):
+            n = spk.workspace_size(good_params(n_shots=3, n_samples=100, grid=1024,
+                                               precision=prec, discrepancy=disc))
+            assert n < 2 ** 30, (prec, disc, n)
+    # the samples' accumulators dominate at large p: about 100 bytes per sample
+    big = spk.workspace_size(spk.Params(524289, 2048, 4))
+    assert 90 * 524289 * 2048 < big < 120 * 524289 * 2048
+
+
 @pytest.mark.parametrize("bad", [
     dict(n_shots=0), dict(n_samples=0), dict(grid=0), dict(grid=2000), dict(te_index=16),
     dict(te_index=-2), dict(half_width=0.0), dict(half_width=float("nan")), dict(eps=-1.0),
