@@ -238,7 +238,8 @@ int sparkling_constraint_check(const spk_params *prm, const void *kx, const void
  * as long) is up-sampled by linear interpolation to 2*n_samples samples.
  * Fine sample m sits at coarse position m/2: even m copy coarse sample m/2,
  * odd m average its two neighbours, and the last fine sample continues the
- * last coarse step (1.5 k[N-1] - 0.5 k[N-2]).  kx, ky, kz: device, coarse,
+ * last coarse step (1.5 k[N-1] - 0.5 k[N-2]; a one-sample shot is repeated).
+ * 2p must stay below 2^31.  kx, ky, kz: device, coarse,
  * p elements each; fx, fy, fz: device, 2p elements each, K's type, no
  * aliasing.  Asynchronous.
  */
@@ -265,7 +266,8 @@ typedef struct {
  * kx, ky, kz: in/out.  k_prev, g_prev: device, 3p elements of K's type laid
  * out [3][p], caller-owned state carried between calls (contents ignored
  * while iter < 20).  info: host, in/out.  Synchronises `stream`.
- * Returns SPK_ENONFINITE (after completing the step) if F is not finite.
+ * Returns SPK_ENONFINITE if F at the input K is not finite; K, k_prev and
+ * g_prev are then left unchanged and info holds F, F^a, F^r (eta and viol NaN).
  */
 int sparkling_step(const spk_params *prm, void *kx, void *ky, void *kz, const void *rho,
                    void *k_prev, void *g_prev, spk_step_info *info,

@@ -70,18 +70,32 @@ class Timed {
         std::lock_guard<std::mutex> lk(g_tmu);
         if (!g_timing)
             return;
-        if (hipEventCreate(&a_) != hipSuccess || hipEventCreate(&b_) != hipSuccess)
+        if (hipEventCreate(&a_) != hipSuccess)
             return;
+        if (hipEventCreate(&b_) != hipSuccess) {
+            hipEventDestroy(a_);
+            return;
+        }
         on_ = hipEventRecord(a_, s_) == hipSuccess;
+        if (!on_) {
+            hipEventDestroy(a_);
+            hipEventDestroy(b_);
+        }
     }
     ~Timed()
     {
         if (!on_)
             return;
         std::lock_guard<std::mutex> lk(g_tmu);
-        if (hipEventRecord(b_, s_) == hipSuccess)
+        if (hipEventRecord(b_, s_) == hipSuccess) {
             g_pending.push_back({a_, b_, kind_, pairs_});
+        } else {
+            hipEventDestroy(a_);
+            hipEventDestroy(b_);
+        }
     }
+    Timed(const Timed &) = delete;
+    Timed &operator=(const Timed &) = delete;
 
   private:
     int kind_;
@@ -104,7 +118,7 @@ int check_params(const spk_params *prm, bool need_projection)
         return fail(SPK_EINVAL, "n_shots must be >= 1 (got %lld)", (long long)prm->n_shots);
     if (prm->n_samples < 1)
         return fail(SPK_EINVAL, "n_samples must be >= 1 (got %lld)", (long long)prm->n_samples);
-    if (prm->n_shots > (int64_t(1) << 31) / prm->n_samples)
+    if (prm->n_shots > ((int64_t(1) << 31) - 1) / prm->n_samples)
         return fail(SPK_EINVAL, "p = n_shots * n_samples must stay below 2^31");
     if (prm->grid < 1 || prm->grid > kMaxGrid)
         return fail(SPK_EINVAL, "grid must be in [1, %lld] (got %lld)", (long long)kMaxGrid,
@@ -115,6 +129,8 @@ int check_params(const spk_params *prm, bool need_projection)
         return fail(SPK_EINVAL, "half_width must be finite and > 0");
     if (!(prm->eps >= 0.0) || !std::isfinite(prm->eps))
         return fail(SPK_EINVAL, "eps must be finite and >= 0");
+    if (!(prm->eps * prm->eps <= (prm->precision == SPK_PLAIN_FP64 ? DBL_MAX : FLT_MAX) / 4))
+        return fail(SPK_EINVAL, "eps^2 must stay finite in the form's type");
     if (prm->te_index < -1 || prm->te_index >= prm->n_samples)
         return fail(SPK_EINVAL, "te_index must be -1 or in [0, n_samples)");
     if (prm->flags & ~(SPK_FLAG_DISCREPANCY | SPK_FLAG_ROTATION_VARIANT | SPK_FLAG_LOG_KERNEL))
@@ -741,6 +757,17 @@ int sparkling_step(const spk_params *prm, void *kx, void *ky, void *kz, const vo
         return rc;
     double e3[3];
     energies_from_sums(p, sc, e3);
+    if (!std::isfinite(e3[0])) {
+        // nothing is updated: K and the caller's step state stay as they were
+        info->eta = NAN;
+        info->F = e3[0];
+        info->Fa = e3[1];
+        info->Fr = e3[2];
+        for (int c = 0; c < 4; ++c)
+            info->viol[c] = NAN;
+        info->bb_used = 0;
+        return fail(SPK_ENONFINITE, "energy is not finite (F = %g); K left unchanged", e3[0]);
+    }
     double eta = info->eta_fixed;
     int used = 0;
     if (bb) {
@@ -770,8 +797,6 @@ int sparkling_step(const spk_params *prm, void *kx, void *ky, void *kz, const vo
     for (int c = 0; c < 4; ++c)
         info->viol[c] = v[c];
     info->bb_used = used;
-    if (!std::isfinite(e3[0]))
-        return fail(SPK_ENONFINITE, "energy is not finite (F = %g)", e3[0]);
     return SPK_OK;
 }
 
@@ -783,7 +808,7 @@ int sparkling_upsample(const spk_params *prm, const void *kx, const void *ky, co
     if (rc)
         return rc;
     const int64_t p = prm->n_shots * prm->n_samples;
-    if (p > (int64_t(1) << 30))
+    if (2 * p > (int64_t(1) << 31) - 1)
         return fail(SPK_EINVAL, "the up-sampled trajectory must stay below 2^31 samples");
     const size_t al = elt_size(prm->precision);
     if ((rc = check_k(prm, kx, ky, kz)) || (rc = check_ptr(fx, "fx", al)) ||
@@ -808,17 +833,25 @@ int spk_timing_query(int kind, double *total_ms, int64_t *launches, double *pair
     if (kind < 0 || kind >= kKinds)
         return fail(SPK_EINVAL, "unknown timing kind %d", kind);
     std::lock_guard<std::mutex> lk(g_tmu);
+    // Fold every pending launch into the totals; the events are released
+    // whatever happens, so a failed query never counts a launch twice.
+    bool ok = true;
     for (const TimedLaunch &t : g_pending) {
         float ms = 0.f;
-        if (hipEventSynchronize(t.b) != hipSuccess || hipEventElapsedTime(&ms, t.a, t.b) != hipSuccess)
-            return fail(SPK_EDEVICE, "timing event query failed");
-        g_ms[t.kind] += ms;
-        g_launches[t.kind] += 1;
-        g_pairs[t.kind] += t.pairs;
+        if (ok && (hipEventSynchronize(t.b) != hipSuccess ||
+                   hipEventElapsedTime(&ms, t.a, t.b) != hipSuccess))
+            ok = false;
+        if (ok) {
+            g_ms[t.kind] += ms;
+            g_launches[t.kind] += 1;
+            g_pairs[t.kind] += t.pairs;
+        }
         hipEventDestroy(t.a);
         hipEventDestroy(t.b);
     }
     g_pending.clear();
+    if (!ok)
+        return fail(SPK_EDEVICE, "timing event query failed; pending launches dropped");
     if (total_ms)
         *total_ms = g_ms[kind];
     if (launches)

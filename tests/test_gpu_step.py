@@ -82,9 +82,14 @@ def test_nonfinite_energy_reported(gpu):
     K[0, 5] = np.nan
     Kd, rd = device_problem(K, inputs.radial_density(4, 0.5, 0.05, 2.0), "fp32_comp", gpu)
     state = spk.StepState(prm, gpu)
+    before = host64(Kd)
+    kp, gp = state.k_prev.clone(), state.g_prev.clone()
     with pytest.raises(spk.SparklingError) as e:
         spk.step_(Kd, rd, prm, state, 0, 1.0)
     assert e.value.status == -5
+    # nothing was updated
+    np.testing.assert_array_equal(host64(Kd), before)
+    assert torch.equal(state.k_prev, kp) and torch.equal(state.g_prev, gp)
 
 
 def test_per_axis_steps_plain_fp64(gpu):
