@@ -274,11 +274,28 @@ int sparkling_step(const spk_params *prm, void *kx, void *ky, void *kz, const vo
                    void *ws, size_t ws_bytes, void *stream);
 
 /*
+ * The step of sparkling_step with no host synchronisation, for loops that run
+ * many steps per host round trip or replay a captured HIP graph.  The same
+ * kernels run in the same order; the step size is chosen on the device by the
+ * same rule, so K, k_prev and g_prev evolve bit for bit as with
+ * sparkling_step.  info_dev: device, 10 doubles, receives {eta, F, F^a, F^r,
+ * viol[4], bb_used, 0}.  If F is not finite, eta is NaN and K, k_prev and
+ * g_prev are left unchanged (the constraint check still reports on K).  The
+ * launch sequence depends on iter only through iter >= 20, so one captured
+ * graph serves every iteration of a phase.  Enqueues kernels only: no host
+ * copy, no synchronisation, no allocation, no memset.
+ */
+int sparkling_step_async(const spk_params *prm, void *kx, void *ky, void *kz, const void *rho,
+                         void *k_prev, void *g_prev, int64_t iter, double eta_fixed,
+                         double *info_dev, void *ws, size_t ws_bytes, void *stream);
+
+/*
  * Kernel timing.  While enabled, every kernel launch of the kinds below is
  * bracketed by HIP events on the stream it runs on; spk_timing_query()
  * waits for those events and returns, for one kind, the summed duration in
  * ms, the launch count and the pair interactions processed.  Timing state is
- * process-global and guarded by a mutex.
+ * process-global and guarded by a mutex.  Launches on a stream that is being
+ * captured into a graph are not timed.
  */
 enum {
     SPK_KIND_REPULSION = 0,   /* all-pairs sample sweep                   */

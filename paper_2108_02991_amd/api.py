@@ -70,6 +70,8 @@ def load_library(path: Path | str | None = None):
         "sparkling_project": ([_vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp], ctypes.c_int),
         "sparkling_constraint_check": ([_vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp], ctypes.c_int),
         "sparkling_step": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp], ctypes.c_int),
+        "sparkling_step_async": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _dbl, _vp, _vp, _sz,
+                                  _vp], ctypes.c_int),
         "sparkling_upsample": ([_vp] * 8, ctypes.c_int),
         "spk_timing_enable": ([ctypes.c_int], ctypes.c_int),
         "spk_timing_query": ([ctypes.c_int, _vp, _vp, _vp], ctypes.c_int),
@@ -321,6 +323,60 @@ def step_(K: torch.Tensor, rho: torch.Tensor, prm: Params, state: StepState, it:
     _check(rc, "sparkling_step")
     return {"eta": info.eta, "F": info.F, "Fa": info.Fa, "Fr": info.Fr,
             "viol": np.array(info.viol[:]), "bb_used": bool(info.bb_used)}
+
+
+INFO_FIELDS = ("eta", "F", "Fa", "Fr", "viol0", "viol1", "viol2", "viol3", "bb_used")
+
+
+def step_async_(K: torch.Tensor, rho: torch.Tensor, prm: Params, state: StepState, it: int,
+                eta_fixed: float, info: torch.Tensor, ws: torch.Tensor | None = None):
+    """Enqueue one projected gradient step on K's current stream with no host
+    synchronisation; info (a float64 device tensor of 10) receives eta, F, Fa,
+    Fr, the 4 violations and bb_used.  Pass ws to pin the workspace (needed
+    when the call is captured into a graph)."""
+    _check_k(K, prm)
+    _check_rho(rho, prm)
+    _check_k(state.k_prev, prm, "k_prev")
+    _check_k(state.g_prev, prm, "g_prev")
+    if (not info.is_cuda or info.dtype != torch.float64 or info.numel() < 10
+            or not info.is_contiguous()):
+        raise ValueError("info must be a contiguous float64 device tensor of at least 10")
+    ws = workspace(prm, K.device) if ws is None else ws
+    c = prm.c()
+    _check(load_library().sparkling_step_async(
+        ctypes.byref(c), *_rows(K), _vp(rho.data_ptr()), _vp(state.k_prev.data_ptr()),
+        _vp(state.g_prev.data_ptr()), it, eta_fixed, _vp(info.data_ptr()), _vp(ws.data_ptr()),
+        ws.numel(), _stream(K)), "sparkling_step_async")
+
+
+def info_dict(info: torch.Tensor) -> dict:
+    """The step info of step_async_ (copied to the host) as step_ returns it."""
+    v = info.detach().cpu().double().numpy()
+    return {"eta": float(v[0]), "F": float(v[1]), "Fa": float(v[2]), "Fr": float(v[3]),
+            "viol": v[4:8].copy(), "bb_used": bool(v[8])}
+
+
+class StepGraph:
+    """One projected gradient step captured in a HIP graph.
+
+    A graph serves one phase of the step-size rule: the fixed step (iterations
+    below 20) or Barzilai-Borwein (20 and above).  K, rho, the step state, the
+    info tensor and a private workspace are bound at capture and must stay
+    alive; every replay advances K in place by one step and overwrites info.
+    """
+
+    def __init__(self, K: torch.Tensor, rho: torch.Tensor, prm: Params, state: StepState,
+                 eta_fixed: float, barzilai_borwein: bool):
+        self.K, self.rho, self.prm, self.state = K, rho, dataclasses.replace(prm), state
+        self.info = torch.zeros(16, dtype=torch.float64, device=K.device)
+        self.ws = torch.empty(workspace_size(prm), dtype=torch.uint8, device=K.device)
+        self.graph = torch.cuda.CUDAGraph()
+        it = 20 if barzilai_borwein else 0
+        with torch.cuda.graph(self.graph):
+            step_async_(K, rho, self.prm, state, it, eta_fixed, self.info, self.ws)
+
+    def replay(self):
+        self.graph.replay()
 
 
 def timing_enable(on: bool = True):

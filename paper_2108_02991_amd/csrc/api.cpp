@@ -70,6 +70,9 @@ class Timed {
         std::lock_guard<std::mutex> lk(g_tmu);
         if (!g_timing)
             return;
+        hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(s_, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone)
+            return;
         if (hipEventCreate(&a_) != hipSuccess)
             return;
         if (hipEventCreate(&b_) != hipSuccess) {
@@ -215,7 +218,7 @@ Plan make_plan(int precision, bool cells, int64_t p_total, int64_t n_src, int64_
 // Workspace layout (offsets from a 256-byte aligned base).
 struct Layout {
     size_t acc_a = 0, acc_r = 0, part = 0, red = 0, scal = 0, grad = 0, viol = 0, cells = 0;
-    size_t chunk_sums = 0;
+    size_t chunk_sums = 0, info = 0;
     size_t total = 0;
     int64_t ld = 0;
     int64_t part_rows = 0;   // capacity of the slab partials, in rows of 4 doubles
@@ -261,6 +264,7 @@ Layout make_layout(const spk_params *prm)
     L.part_rows = part_rows;
     L.red = take(sizeof(double) * reduce_partials_size(std::max(nt, 3 * p)));
     L.scal = take(sizeof(double) * 16);
+    L.info = take(sizeof(double) * 16);
     L.grad = take(elt_size(prm->precision) * 3 * p);
     L.viol = take(sizeof(double) * 4 * prm->n_shots);
     L.cells = take(elt_size(prm->precision) * 3 * cn);
@@ -278,6 +282,7 @@ struct Ws {
     double *red() const { return reinterpret_cast<double *>(base + L.red); }
     double *chunk_sums() const { return reinterpret_cast<double *>(base + L.chunk_sums); }
     double *scal() const { return reinterpret_cast<double *>(base + L.scal); }
+    double *info() const { return reinterpret_cast<double *>(base + L.info); }
     void *grad() const { return base + L.grad; }
     double *viol() const { return reinterpret_cast<double *>(base + L.viol); }
     void *cells() const { return base + L.cells; }
@@ -422,12 +427,13 @@ int constraint_check_into(const spk_params *prm, const void *kx, const void *ky,
     return SPK_OK;
 }
 
-int project_in_place(const spk_params *prm, void *kx, void *ky, void *kz, hipStream_t s)
+int project_in_place(const spk_params *prm, void *kx, void *ky, void *kz, hipStream_t s,
+                     const double *gate = nullptr)
 {
     Timed tm(SPK_KIND_PROJECTION, 0.0, s);
     SPK_HIP(launch_project(prm->precision, kx, ky, kz, prm->n_shots, prm->n_samples,
                            prm->half_width, prm->a_max, prm->b_max, prm->te_index, prm->n_pit,
-                           (prm->flags & SPK_FLAG_ROTATION_VARIANT) != 0, s),
+                           (prm->flags & SPK_FLAG_ROTATION_VARIANT) != 0, gate, s),
             "projection");
     return SPK_OK;
 }
@@ -437,6 +443,70 @@ int copy_to_host(double *dst, const double *src, size_t n, hipStream_t s)
     SPK_HIP(hipMemcpyAsync(dst, src, sizeof(double) * n, hipMemcpyDeviceToHost, s), "copy to host");
     SPK_HIP(hipStreamSynchronize(s), "stream synchronize");
     return SPK_OK;
+}
+
+// Argument checks shared by the two step entry points.
+int check_step(const spk_params *prm, void *kx, void *ky, void *kz, const void *rho,
+               void *k_prev, void *g_prev, int64_t iter, double eta_fixed, void *ws,
+               size_t ws_bytes, Ws *w)
+{
+    int rc = check_params(prm, true);
+    if (rc)
+        return rc;
+    const size_t al = elt_size(prm->precision);
+    if ((rc = check_k(prm, kx, ky, kz)) || (rc = check_ptr(rho, "rho", al)) ||
+        (rc = check_ptr(k_prev, "k_prev", al)) || (rc = check_ptr(g_prev, "g_prev", al)))
+        return rc;
+    if (iter < 0 || !(eta_fixed > 0.0) || !std::isfinite(eta_fixed))
+        return fail(SPK_EINVAL, "iter must be >= 0 and eta_fixed finite and > 0");
+    return bind_ws(prm, ws, ws_bytes, w);
+}
+
+// First half of a step: gradient into the workspace, energy sums, the
+// Barzilai-Borwein dots (iter >= 20) and the step-size rule, all on the
+// device; info_dev[0..3] = eta, F, F^a, F^r and info_dev[8] = BB used.
+int enqueue_step_front(const spk_params *prm, void *kx, void *ky, void *kz, const void *rho,
+                       void *k_prev, void *g_prev, int64_t iter, double eta_fixed,
+                       double *info_dev, const Ws &w, hipStream_t s)
+{
+    const int64_t p = prm->n_shots * prm->n_samples;
+    const size_t al = elt_size(prm->precision);
+    char *g = static_cast<char *>(w.grad());
+    int rc = run_gradient_sums(prm, kx, ky, kz, rho, 0, p, true, w, s);
+    if (rc)
+        return rc;
+    Timed tm(SPK_KIND_OTHER, 0.0, s);
+    const double inv_p = 1.0 / (double)p, inv_p2 = 1.0 / ((double)p * (double)p);
+    SPK_HIP(launch_finalize_grad(prm->precision, w.acc_a(), w.acc_r(), w.L.ld, p, inv_p, inv_p2,
+                                 g, g + al * p, g + 2 * al * p, nullptr, nullptr, s),
+            "finalize gradient");
+    if ((rc = reduce_energy(w, p, s)))
+        return rc;
+    const bool bb = iter >= 20;
+    if (bb)
+        SPK_HIP(launch_bb_dots(prm->precision, kx, ky, kz, k_prev, g, g_prev, p, w.red(),
+                               w.scal() + 2, s),
+                "step dots");
+    SPK_HIP(launch_step_policy(w.scal(), p, eta_fixed, bb, info_dev, s), "step size");
+    return SPK_OK;
+}
+
+// Second half: K <- Pi_Q(K - eta g) with the state saved, both skipped when
+// info_dev[0] (eta) is NaN, then the constraint check into info_dev[4..7].
+int enqueue_step_back(const spk_params *prm, void *kx, void *ky, void *kz, void *k_prev,
+                      void *g_prev, double *info_dev, const Ws &w, hipStream_t s)
+{
+    const int64_t p = prm->n_shots * prm->n_samples;
+    {
+        Timed tm(SPK_KIND_OTHER, 0.0, s);
+        SPK_HIP(launch_axpy_save(prm->precision, kx, ky, kz, k_prev, w.grad(), g_prev, p, 0.0,
+                                 info_dev, s),
+                "step update");
+    }
+    int rc = project_in_place(prm, kx, ky, kz, s, info_dev);
+    if (rc)
+        return rc;
+    return constraint_check_into(prm, kx, ky, kz, w, info_dev + 4, s);
 }
 
 }  // namespace
@@ -716,88 +786,58 @@ int sparkling_step(const spk_params *prm, void *kx, void *ky, void *kz, const vo
                    void *stream)
 {
     g_err.clear();
-    int rc = check_params(prm, true);
-    if (rc)
-        return rc;
-    const size_t al = elt_size(prm->precision);
-    if ((rc = check_k(prm, kx, ky, kz)) || (rc = check_ptr(rho, "rho", al)) ||
-        (rc = check_ptr(k_prev, "k_prev", al)) || (rc = check_ptr(g_prev, "g_prev", al)))
-        return rc;
     if (!info)
         return fail(SPK_EINVAL, "info is NULL");
-    if (info->iter < 0 || !(info->eta_fixed > 0.0) || !std::isfinite(info->eta_fixed))
-        return fail(SPK_EINVAL, "info: iter must be >= 0 and eta_fixed finite and > 0");
     Ws w;
-    if ((rc = bind_ws(prm, ws, ws_bytes, &w)))
+    int rc = check_step(prm, kx, ky, kz, rho, k_prev, g_prev, info->iter, info->eta_fixed, ws,
+                        ws_bytes, &w);
+    if (rc)
         return rc;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const int64_t p = prm->n_shots * prm->n_samples;
-    char *g = static_cast<char *>(w.grad());
-
-    if ((rc = run_gradient_sums(prm, kx, ky, kz, rho, 0, p, true, w, s)))
+    if ((rc = enqueue_step_front(prm, kx, ky, kz, rho, k_prev, g_prev, info->iter,
+                                 info->eta_fixed, w.info(), w, s)))
         return rc;
-    {
-        Timed tm(SPK_KIND_OTHER, 0.0, s);
-        const double inv_p = 1.0 / (double)p, inv_p2 = 1.0 / ((double)p * (double)p);
-        SPK_HIP(launch_finalize_grad(prm->precision, w.acc_a(), w.acc_r(), w.L.ld, p, inv_p,
-                                     inv_p2, g, g + al * p, g + 2 * al * p, nullptr, nullptr, s),
-                "finalize gradient");
-    }
-    if ((rc = reduce_energy(w, p, s)))
+    double h[10];
+    if ((rc = copy_to_host(h, w.info(), 4, s)))
         return rc;
-    const bool bb = info->iter >= 20;
-    if (bb) {
-        Timed tm(SPK_KIND_OTHER, 0.0, s);
-        SPK_HIP(launch_bb_dots(prm->precision, kx, ky, kz, k_prev, g, g_prev, p, w.red(),
-                               w.scal() + 2, s),
-                "step dots");
-    }
-    double sc[4];
-    if ((rc = copy_to_host(sc, w.scal(), bb ? 4 : 2, s)))
-        return rc;
-    double e3[3];
-    energies_from_sums(p, sc, e3);
-    if (!std::isfinite(e3[0])) {
+    info->F = h[1];
+    info->Fa = h[2];
+    info->Fr = h[3];
+    if (!std::isfinite(h[1])) {
         // nothing is updated: K and the caller's step state stay as they were
         info->eta = NAN;
-        info->F = e3[0];
-        info->Fa = e3[1];
-        info->Fr = e3[2];
         for (int c = 0; c < 4; ++c)
             info->viol[c] = NAN;
         info->bb_used = 0;
-        return fail(SPK_ENONFINITE, "energy is not finite (F = %g); K left unchanged", e3[0]);
+        return fail(SPK_ENONFINITE, "energy is not finite (F = %g); K left unchanged", h[1]);
     }
-    double eta = info->eta_fixed;
-    int used = 0;
-    if (bb) {
-        const double ss = sc[2], sy = sc[3];
-        if (sy > 0.0 && std::isfinite(ss / sy)) {
-            eta = ss / sy;
-            eta = std::min(std::max(eta, 0.1 * info->eta_fixed), 10.0 * info->eta_fixed);
-            used = 1;
-        }
-    }
-    {
-        Timed tm(SPK_KIND_OTHER, 0.0, s);
-        SPK_HIP(launch_axpy_save(prm->precision, kx, ky, kz, k_prev, g, g_prev, p, eta, s),
-                "step update");
-    }
-    if ((rc = project_in_place(prm, kx, ky, kz, s)))
+    if ((rc = enqueue_step_back(prm, kx, ky, kz, k_prev, g_prev, w.info(), w, s)))
         return rc;
-    if ((rc = constraint_check_into(prm, kx, ky, kz, w, w.scal() + 8, s)))
+    if ((rc = copy_to_host(h, w.info(), 10, s)))
         return rc;
-    double v[4];
-    if ((rc = copy_to_host(v, w.scal() + 8, 4, s)))
-        return rc;
-    info->eta = eta;
-    info->F = e3[0];
-    info->Fa = e3[1];
-    info->Fr = e3[2];
+    info->eta = h[0];
     for (int c = 0; c < 4; ++c)
-        info->viol[c] = v[c];
-    info->bb_used = used;
+        info->viol[c] = h[4 + c];
+    info->bb_used = h[8] != 0.0;
     return SPK_OK;
+}
+
+int sparkling_step_async(const spk_params *prm, void *kx, void *ky, void *kz, const void *rho,
+                         void *k_prev, void *g_prev, int64_t iter, double eta_fixed,
+                         double *info_dev, void *ws, size_t ws_bytes, void *stream)
+{
+    g_err.clear();
+    Ws w;
+    int rc = check_step(prm, kx, ky, kz, rho, k_prev, g_prev, iter, eta_fixed, ws, ws_bytes, &w);
+    if (rc)
+        return rc;
+    if ((rc = check_ptr(info_dev, "info_dev", 8)))
+        return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if ((rc = enqueue_step_front(prm, kx, ky, kz, rho, k_prev, g_prev, iter, eta_fixed, info_dev,
+                                 w, s)))
+        return rc;
+    return enqueue_step_back(prm, kx, ky, kz, k_prev, g_prev, info_dev, w, s);
 }
 
 int sparkling_upsample(const spk_params *prm, const void *kx, const void *ky, const void *kz,

@@ -50,10 +50,14 @@ __device__ inline double shrink_one(double z, double thr)
 template <typename T, int NPT>
 __global__ __launch_bounds__(512) void project_kernel(T *kx, T *ky, T *kz, int64_t Ns, double L,
                                                      double a, double b, int64_t te, int n_pit,
-                                                     int per_axis)
+                                                     int per_axis, const double *gate)
 {
 #pragma clang fp contract(off)
     static_assert(NPT >= 2, "two-sample halo needs NPT >= 2");
+    // a NaN gate (a step that was not taken) leaves every shot as it is; the
+    // whole block leaves before its first barrier
+    if (gate && !(*gate == *gate))
+        return;
     extern __shared__ double xch[];
     const int nth = blockDim.x;
     const int j = threadIdx.x;
@@ -281,45 +285,46 @@ __global__ __launch_bounds__(CB) void check_final_kernel(const double *per_shot,
 template <typename T, int NPT>
 hipError_t launch_project_npt(T *kx, T *ky, T *kz, int64_t n_shots, int64_t Ns, double L,
                               double a, double b, int64_t te, int n_pit, int per_axis,
-                              hipStream_t s)
+                              const double *gate, hipStream_t s)
 {
     int64_t nth = (Ns + NPT - 1) / NPT;
     nth = (nth + 63) / 64 * 64;
     const size_t lds = sizeof(double) * 15 * (size_t)nth;
     hipLaunchKernelGGL((project_kernel<T, NPT>), dim3((unsigned)n_shots), dim3((unsigned)nth), lds,
-                       s, kx, ky, kz, Ns, L, a, b, te, n_pit, per_axis);
+                       s, kx, ky, kz, Ns, L, a, b, te, n_pit, per_axis, gate);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_project_t(T *kx, T *ky, T *kz, int64_t n_shots, int64_t Ns, double L, double a,
-                            double b, int64_t te, int n_pit, int per_axis, hipStream_t s)
+                            double b, int64_t te, int n_pit, int per_axis, const double *gate,
+                            hipStream_t s)
 {
     // at most 512 threads per shot: the halo buffers (15 doubles per thread)
     // stay under 64 KB of LDS
     if (Ns <= 2 * 512)
         return launch_project_npt<T, 2>(kx, ky, kz, n_shots, Ns, L, a, b, te, n_pit,
-                                            per_axis, s);
+                                            per_axis, gate, s);
     if (Ns <= 4 * 512)
         return launch_project_npt<T, 4>(kx, ky, kz, n_shots, Ns, L, a, b, te, n_pit,
-                                            per_axis, s);
+                                            per_axis, gate, s);
     return launch_project_npt<T, 8>(kx, ky, kz, n_shots, Ns, L, a, b, te, n_pit,
-                                            per_axis, s);
+                                            per_axis, gate, s);
 }
 
 }  // namespace
 
 hipError_t launch_project(int precision, void *kx, void *ky, void *kz, int64_t n_shots,
                           int64_t n_samples, double L, double a, double b, int64_t te, int n_pit,
-                          bool per_axis, hipStream_t s)
+                          bool per_axis, const double *gate, hipStream_t s)
 {
     if (n_samples > kMaxProjectSamples)
         return hipErrorInvalidValue;
     if (precision == SPK_PLAIN_FP64)
         return launch_project_t((double *)kx, (double *)ky, (double *)kz, n_shots, n_samples, L,
-                                a, b, te, n_pit, per_axis ? 1 : 0, s);
+                                a, b, te, n_pit, per_axis ? 1 : 0, gate, s);
     return launch_project_t((float *)kx, (float *)ky, (float *)kz, n_shots, n_samples, L, a, b,
-                            te, n_pit, per_axis ? 1 : 0, s);
+                            te, n_pit, per_axis ? 1 : 0, gate, s);
 }
 
 hipError_t launch_constraint_check(int precision, const void *kx, const void *ky, const void *kz,

@@ -183,17 +183,57 @@ __global__ __launch_bounds__(EW) void cell_centres_kernel(int64_t G, double L, i
 
 template <typename T>
 __global__ __launch_bounds__(EW) void axpy_save_kernel(T *kx, T *ky, T *kz, T *kp, const T *g,
-                                                       T *gp, int64_t p, double eta)
+                                                       T *gp, int64_t p, double eta,
+                                                       const double *eta_dev)
 {
     const int64_t e = (int64_t)blockIdx.x * EW + threadIdx.x;
     if (e >= 3 * p)
+        return;
+    // a step size chosen on the device; NaN there means "no update"
+    const double h = eta_dev ? *eta_dev : eta;
+    if (!(h == h))
         return;
     const int64_t c = e / p, i = e - c * p;
     T *k = c == 0 ? kx : (c == 1 ? ky : kz);
     const T kv = k[i], gv = g[e];
     kp[e] = kv;
     gp[e] = gv;
-    k[i] = (T)((double)kv - eta * (double)gv);
+    k[i] = (T)((double)kv - h * (double)gv);
+}
+
+// The step-size rule on the device, from the energy sums scal[0..1] and, in
+// the Barzilai-Borwein phase, the dots scal[2] = s.s and scal[3] = s.y; the
+// same operations, in the same order, as the host-side rule.
+__global__ void step_policy_kernel(const double *scal, int64_t p, double eta_fixed, int bb,
+                                   double *info)
+{
+#pragma clang fp contract(off)
+    if (threadIdx.x != 0 || blockIdx.x != 0)
+        return;
+    const double fa = scal[0] / (double)p;
+    const double fr = scal[1] / (2.0 * (double)p * (double)p);
+    const double F = fa - fr;
+    double eta = eta_fixed;
+    double used = 0.0;
+    if (bb) {
+        const double ss = scal[2], sy = scal[3];
+        const double q = ss / sy;
+        if (sy > 0.0 && q - q == 0.0) {
+            eta = q;
+            eta = fmin(fmax(eta, 0.1 * eta_fixed), 10.0 * eta_fixed);
+            used = 1.0;
+        }
+    }
+    if (!(F - F == 0.0)) {
+        eta = __builtin_nan("");
+        used = 0.0;
+    }
+    info[0] = eta;
+    info[1] = F;
+    info[2] = fa;
+    info[3] = fr;
+    info[8] = used;
+    info[9] = 0.0;
 }
 
 // Dyadic linear up-sampling of shots (fine sample m at coarse position m/2;
@@ -317,17 +357,28 @@ hipError_t launch_bb_dots(int precision, const void *kx, const void *ky, const v
 }
 
 hipError_t launch_axpy_save(int precision, void *kx, void *ky, void *kz, void *k_prev,
-                            const void *g, void *g_prev, int64_t p, double eta, hipStream_t s)
+                            const void *g, void *g_prev, int64_t p, double eta,
+                            const double *eta_dev, hipStream_t s)
 {
     if (precision == SPK_PLAIN_FP64) {
         using T = double;
         hipLaunchKernelGGL(axpy_save_kernel<T>, dim3(ew_blocks(3 * p)), dim3(EW), 0, s, (T *)kx,
-                           (T *)ky, (T *)kz, (T *)k_prev, (const T *)g, (T *)g_prev, p, eta);
+                           (T *)ky, (T *)kz, (T *)k_prev, (const T *)g, (T *)g_prev, p, eta,
+                           eta_dev);
     } else {
         using T = float;
         hipLaunchKernelGGL(axpy_save_kernel<T>, dim3(ew_blocks(3 * p)), dim3(EW), 0, s, (T *)kx,
-                           (T *)ky, (T *)kz, (T *)k_prev, (const T *)g, (T *)g_prev, p, eta);
+                           (T *)ky, (T *)kz, (T *)k_prev, (const T *)g, (T *)g_prev, p, eta,
+                           eta_dev);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_step_policy(const double *scal, int64_t p, double eta_fixed, bool bb,
+                              double *info, hipStream_t s)
+{
+    hipLaunchKernelGGL(step_policy_kernel, dim3(1), dim3(64), 0, s, scal, p, eta_fixed,
+                       bb ? 1 : 0, info);
     return hipGetLastError();
 }
 

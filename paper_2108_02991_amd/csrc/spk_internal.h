@@ -126,7 +126,12 @@ hipError_t launch_bb_dots(int precision, const void *kx, const void *ky, const v
                           double *partials, double *out, hipStream_t s);
 // k_prev = K; g_prev = g; K = K - eta * g (computed in double).
 hipError_t launch_axpy_save(int precision, void *kx, void *ky, void *kz, void *k_prev,
-                            const void *g, void *g_prev, int64_t p, double eta, hipStream_t s);
+                            const void *g, void *g_prev, int64_t p, double eta,
+                            const double *eta_dev, hipStream_t s);
+// info[0] = eta, info[1..3] = F, F^a, F^r, info[8] = BB used, info[9] = 0, from the
+// energy sums scal[0..1] and (bb) the dots scal[2..3]; eta is NaN when F is not finite.
+hipError_t launch_step_policy(const double *scal, int64_t p, double eta_fixed, bool bb,
+                              double *info, hipStream_t s);
 
 // Dyadic linear up-sampling: coarse shots of N samples -> fine shots of 2N.
 hipError_t launch_upsample(int precision, const void *kx, const void *ky, const void *kz, void *fx,
@@ -134,9 +139,10 @@ hipError_t launch_upsample(int precision, const void *kx, const void *ky, const 
 
 // Projection and constraint check (one block per shot).  per_axis selects the
 // per-axis maximum instead of the Euclidean norm in the speed and slew bounds.
+// gate (nullable, device): a NaN there skips the projection (a step not taken).
 hipError_t launch_project(int precision, void *kx, void *ky, void *kz, int64_t n_shots,
                           int64_t n_samples, double L, double a, double b, int64_t te,
-                          int n_pit, bool per_axis, hipStream_t s);
+                          int n_pit, bool per_axis, const double *gate, hipStream_t s);
 // per_shot: n_shots*4 doubles; out: 4 doubles.
 hipError_t launch_constraint_check(int precision, const void *kx, const void *ky, const void *kz,
                                    int64_t n_shots, int64_t n_samples, double L, double a,

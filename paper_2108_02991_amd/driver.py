@@ -33,8 +33,12 @@ def fixed_step(prm: api.Params, rho_mass: float, rule: str, eta_fixed: float) ->
 
 def run(workload: configs.Workload, precision: str, iters: int, device="cuda:0",
         out=None, log_every: int = 1, rotation_variant: bool = False, kernel: str = "distance",
-        eps: float = 0.0, eta_rule: str = "fixed"):
-    """Runs `iters` projected gradient steps; returns the list of records."""
+        eps: float = 0.0, eta_rule: str = "fixed", graph: bool = False):
+    """Runs `iters` projected gradient steps; returns the list of records.
+
+    With graph=True the step runs as two captured HIP graphs (fixed-step and
+    Barzilai-Borwein phases) with no host synchronisation between steps; a
+    record is then written only at the logged iterations and at the end."""
     dev = torch.device(device)
     a, b = api.alpha_beta(configs.GMAX, configs.SMAX, configs.RASTER_DT, configs.DWELL_DT,
                           workload.fov, workload.kmax, configs.GAMMA_BAR, workload.half_width)
@@ -48,6 +52,8 @@ def run(workload: configs.Workload, precision: str, iters: int, device="cuda:0",
     viol0 = api.project_(K, prm)
     state = api.StepState(prm, dev)
     records = []
+    if graph:
+        return _run_graph(K, rho, prm, state, eta, iters, precision, viol0, out, log_every)
     for it in range(iters):
         torch.cuda.synchronize(dev)
         t0 = time.perf_counter()
@@ -68,6 +74,46 @@ def run(workload: configs.Workload, precision: str, iters: int, device="cuda:0",
                   file=sys.stderr, flush=True)
     F, _, _, _ = api.energy(K, rho, prm)
     records.append({"final_F": F, "precision": precision})
+    if out is not None:
+        out.write(json.dumps(records[-1]) + "\n")
+        out.flush()
+    return records, K
+
+
+def _run_graph(K, rho, prm, state, eta, iters, precision, viol0, out, log_every):
+    dev = K.device
+    torch.cuda.synchronize(dev)
+    t_cap = time.perf_counter()
+    graphs = {False: api.StepGraph(K, rho, prm, state, eta, barzilai_borwein=False),
+              True: api.StepGraph(K, rho, prm, state, eta, barzilai_borwein=True)}
+    torch.cuda.synchronize(dev)
+    capture_s = time.perf_counter() - t_cap
+    records = []
+    t0 = time.perf_counter()
+    for it in range(iters):
+        g = graphs[it >= 20]
+        g.replay()
+        if (log_every and it % log_every == 0) or it == iters - 1:
+            torch.cuda.synchronize(dev)
+            info = api.info_dict(g.info)
+            rec = {"iter": it, "precision": precision, "graph": True, "F": info["F"],
+                   "Fa": info["Fa"], "Fr": info["Fr"], "eta": info["eta"],
+                   "bb_used": info["bb_used"], "viol": [float(v) for v in info["viol"]],
+                   "elapsed_s": time.perf_counter() - t0}
+            if it == 0:
+                rec["viol_initial_projection"] = [float(v) for v in viol0]
+                rec["capture_s"] = capture_s
+            records.append(rec)
+            if out is not None:
+                out.write(json.dumps(rec) + "\n")
+                out.flush()
+            print(f"[driver] graph {precision} iter {it}: F={info['F']:.12e} "
+                  f"eta={info['eta']:.5g} {rec['elapsed_s']:.3f}s", file=sys.stderr, flush=True)
+    torch.cuda.synchronize(dev)
+    total = time.perf_counter() - t0
+    F, _, _, _ = api.energy(K, rho, prm)
+    records.append({"final_F": F, "precision": precision, "graph": True,
+                    "s_per_iter": total / max(iters, 1)})
     if out is not None:
         out.write(json.dumps(records[-1]) + "\n")
         out.flush()
@@ -145,6 +191,8 @@ def main():
     ap.add_argument("--eps", type=float, default=0.0, help="kernel regulariser")
     ap.add_argument("--eta", choices=["fixed", "lipschitz"], default="fixed",
                     help="fixed step of the first iterations: the workload's, or 1/L")
+    ap.add_argument("--graph", action="store_true",
+                    help="run the single-level loop as captured HIP graphs")
     args = ap.parse_args()
     w = configs.WORKLOADS[args.workload]
     precision = args.precision or w.precision
@@ -155,7 +203,7 @@ def main():
         if args.levels == 0 and not args.field:
             run(w, precision, iters, out=out, log_every=args.log_every,
                 rotation_variant=args.rotation_variant, kernel=args.kernel, eps=args.eps,
-                eta_rule=args.eta)
+                eta_rule=args.eta, graph=args.graph)
         else:
             dev = torch.device("cuda:0")
             a, b = api.alpha_beta(configs.GMAX, configs.SMAX, configs.RASTER_DT,
