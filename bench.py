@@ -40,7 +40,7 @@ FLOP_PER_PAIR_ATTRACTION = 18
 
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "repulsion_sweep_c3_traffic.md")
 SWEEP_SOURCES = [os.path.join(ROOT, "paper_2108_02991_amd", "csrc", f)
-                 for f in ("sweep.hip", "spk_internal.h")]
+                 for f in ("sweep.hip", "sweep.h")]
 
 
 def log(msg):

@@ -7,78 +7,12 @@
 #include <cstdint>
 
 #include "sparkling.h"
+#include "sweep.h"
 
 namespace spk {
 
-// Build-time tunables of the pair sweeps (defaults are the tuned values).
-#ifndef SPK_SWEEP_BLOCK
-#define SPK_SWEEP_BLOCK 256
-#endif
-#ifndef SPK_SAMPLE_TILE
-#define SPK_SAMPLE_TILE 512
-#endif
-#ifndef SPK_TARGETS_F32
-#define SPK_TARGETS_F32 2
-#endif
-#ifndef SPK_TARGETS_F64
-#define SPK_TARGETS_F64 2
-#endif
-#ifndef SPK_SOURCE_UNROLL
-#define SPK_SOURCE_UNROLL 4
-#endif
-// Minimum waves per SIMD the FP32-accumulating sweeps are compiled for (caps
-// VGPRs at 512/waves); 1 leaves the choice to the compiler.  Sweeps with FP64
-// accumulators are not capped.
-#ifndef SPK_SWEEP_WAVES_F32
-#define SPK_SWEEP_WAVES_F32 1
-#endif
-
-// Threads per block of the pair sweeps.
-constexpr int kSweepBlock = SPK_SWEEP_BLOCK;
-// Sources staged in LDS per tile by the sample sweep.
-constexpr int kSampleTile = SPK_SAMPLE_TILE;
-// Targets per lane (register blocking) of the FP32 forms and of plain FP64.
-constexpr int kTargetsF32 = SPK_TARGETS_F32;
-constexpr int kTargetsF64 = SPK_TARGETS_F64;
-// Density cells staged in LDS per tile by the cell sweep (rows of G cells).
-constexpr int kCellTileF32 = 2048;
-constexpr int kCellTileF64 = 1024;
-// Largest grid side supported (one row must fit a tile).
-constexpr int64_t kMaxGrid = 1024;
 // Largest shot length the projection kernel supports.
 constexpr int64_t kMaxProjectSamples = 4096;
-
-// Targets handled by one block of a sweep (blockDim * targets per lane).
-int sweep_targets_per_block(int precision);
-
-// One launch of a pair sweep: a target range against `nslabs` consecutive
-// source slabs.  Slab y covers sources [src_begin + y*slab, min(+slab, src_end))
-// where a source is a sample (sample sweep) or a row of G cells (cell sweep).
-// Block (x, y) writes its four sums (gx, gy, gz, potential) for target t into
-// part[(y*4 + c)*ld + (t - t0)] as doubles.
-// Pair kernels H of the sweeps.
-constexpr int kKernelDistance = 0;   // sqrt(|d|^2 + eps^2)
-constexpr int kKernelLog = 1;        // log(|d|^2 + eps^2) / 2, eps > 0
-
-struct SweepLaunch {
-    int precision = 0;
-    int kernel = kKernelDistance;
-    bool energy = false;
-    const void *tx = nullptr, *ty = nullptr, *tz = nullptr;
-    int64_t t0 = 0, nt = 0;
-    const void *sx = nullptr, *sy = nullptr, *sz = nullptr;  // sample sweep sources
-    const void *rho = nullptr;                                 // cell sweep weights
-    int64_t grid = 1;
-    double half_width = 0.5;
-    double eps = 0.0;
-    int64_t src_begin = 0, slab = 0, src_end = 0;
-    int nslabs = 1;
-    double *part = nullptr;
-    int64_t ld = 0;
-};
-
-hipError_t launch_sweep_samples(const SweepLaunch &l, hipStream_t s);
-hipError_t launch_sweep_cells(const SweepLaunch &l, hipStream_t s);
 
 // acc[c*ld + t] = (init ? 0 : acc[c*ld + t]) + part[0][c][t] + ... + part[n-1][c][t],
 // with part[y][c][t] at part[(y*4 + c)*part_ld + t].

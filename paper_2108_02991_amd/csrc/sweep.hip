@@ -37,7 +37,7 @@
 
 #include <cfloat>
 
-#include "spk_internal.h"
+#include "sweep.h"
 
 namespace spk {
 namespace {
