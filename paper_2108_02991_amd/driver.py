@@ -13,6 +13,7 @@ before the first iteration.
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
 import sys
 import time
@@ -193,8 +194,12 @@ def main():
                     help="fixed step of the first iterations: the workload's, or 1/L")
     ap.add_argument("--graph", action="store_true",
                     help="run the single-level loop as captured HIP graphs")
+    ap.add_argument("--n-pit", type=int, default=None,
+                    help="projection iterations (default: the workload's)")
     args = ap.parse_args()
     w = configs.WORKLOADS[args.workload]
+    if args.n_pit is not None:
+        w = dataclasses.replace(w, n_pit=args.n_pit)
     precision = args.precision or w.precision
     iters = args.iters if args.iters is not None else w.n_iters
     api.load_library()
@@ -229,7 +234,8 @@ def main():
             torch.cuda.synchronize(dev)
             total = time.perf_counter() - t0
             F, _, _, _ = api.energy(K, rho, prm)
-            summary = {"levels": args.levels, "n_git": iters, "precision": precision,
+            summary = {"workload": w.name, "levels": args.levels, "n_git": iters,
+                       "n_pit": w.n_pit, "precision": precision,
                        "field": args.field, "total_s": total, "final_F": F,
                        "s_per_level": {str(d): sum(r["s"] for r in recs if r["level"] == d)
                                        for d in range(args.levels, -1, -1)}}
