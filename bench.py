@@ -100,7 +100,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU only; multi-GPU runs are not supported "
+        print("bench.py: the path runs on one GPU only; multi-GPU runs are not supported "
               f"(asked for {args.gpus})", file=sys.stderr)
         sys.exit(2)
 

@@ -68,7 +68,7 @@ typedef enum {
     SPK_EINVAL = -1,        /* bad argument; nothing launched                     */
     SPK_EWORKSPACE = -2,    /* workspace NULL or smaller than spk_workspace_size  */
     SPK_EDEVICE = -3,       /* a HIP runtime call or launch failed                */
-    SPK_EUNSUPPORTED = -4,  /* valid but outside what this build implements       */
+    SPK_EUNSUPPORTED = -4,  /* valid but outside what the library implements      */
     SPK_ENONFINITE = -5     /* the energy of a step was NaN or infinite           */
 } spk_status;
 

@@ -1,6 +1,6 @@
 """The projected-gradient loop on the 2048 x 1024 workload: FP32-compensated
 against the plain-FP64 GPU run, iteration by iteration (a short prefix of the
-100-iteration run that the driver performs)."""
+100-iteration run of `paper_2108_02991_amd.driver`)."""
 import numpy as np
 import pytest
 
