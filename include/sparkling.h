@@ -108,6 +108,13 @@ typedef struct {
     const void *attraction_field; /* NULL: attraction summed directly over the G^3
                                      cells; else the node field of sparkling_field(),
                                      evaluated by trilinear interpolation            */
+    int32_t far_field_depth;  /* 0: repulsion summed over all p^2 pairs.  2..7: the
+                                 samples' far field by a Chebyshev fast multipole
+                                 method on a uniform octree of 8^depth leaves over
+                                 the samples' bounding cube, the 27 leaves around
+                                 each target summed exactly (plain_fp64 and
+                                 fp32_comp forms; SPK_EUNSUPPORTED otherwise)    */
+    int32_t far_field_order;  /* Chebyshev nodes per axis, 3..6, when depth > 0     */
 } spk_params;
 
 /* Text of a status code (static storage). */

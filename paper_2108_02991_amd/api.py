@@ -31,7 +31,8 @@ _i32, _i64, _dbl, _vp, _sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ct
 class SpkParams(ctypes.Structure):
     _fields_ = [("n_shots", _i64), ("n_samples", _i64), ("grid", _i64), ("precision", _i32),
                 ("te_index", _i32), ("half_width", _dbl), ("eps", _dbl), ("a_max", _dbl),
-                ("b_max", _dbl), ("n_pit", _i32), ("flags", _i32), ("attraction_field", _vp)]
+                ("b_max", _dbl), ("n_pit", _i32), ("flags", _i32), ("attraction_field", _vp),
+                ("far_field_depth", _i32), ("far_field_order", _i32)]
 
 
 class SpkStepInfo(ctypes.Structure):
@@ -109,6 +110,8 @@ class Params:
     rotation_variant: bool = False                   # per-axis speed/slew bounds
     kernel: str = "distance"                         # "distance" or "log" (needs eps > 0)
     attraction_field: "torch.Tensor | None" = None   # from attraction_field(); None = direct sum
+    far_field_depth: int = 0                         # 0: exact repulsion; 2..7: octree depth
+    far_field_order: int = 5                         # Chebyshev nodes per axis (3..6)
     _c: SpkParams = field(default=None, repr=False, compare=False)
 
     @property
@@ -131,7 +134,8 @@ class Params:
                          (FLAG_DISCREPANCY if self.discrepancy else 0)
                          | (FLAG_ROTATION_VARIANT if self.rotation_variant else 0)
                          | KERNELS[self.kernel],
-                         _vp(f.data_ptr()) if f is not None else None)
+                         _vp(f.data_ptr()) if f is not None else None,
+                         self.far_field_depth, self.far_field_order if self.far_field_depth else 0)
 
 
 def lipschitz_bound(p: int, eps: float, rho_mass: float = 1.0, kernel: str = "distance") -> float:
@@ -367,6 +371,8 @@ class StepGraph:
 
     def __init__(self, K: torch.Tensor, rho: torch.Tensor, prm: Params, state: StepState,
                  eta_fixed: float, barzilai_borwein: bool):
+        if prm.far_field_depth:
+            raise ValueError("the far-field step is not captured: its leaf sort issues memsets")
         self.K, self.rho, self.prm, self.state = K, rho, dataclasses.replace(prm), state
         self.info = torch.zeros(16, dtype=torch.float64, device=K.device)
         self.ws = torch.empty(workspace_size(prm), dtype=torch.uint8, device=K.device)

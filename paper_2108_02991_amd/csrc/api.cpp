@@ -146,6 +146,16 @@ int check_params(const spk_params *prm, bool need_projection)
         if (!(prm->eps * prm->eps >= tiny))
             return fail(SPK_EINVAL, "the log kernel needs eps > 0 with eps^2 >= %g", tiny);
     }
+    if (prm->far_field_depth != 0) {
+        if (prm->far_field_depth < 2 || prm->far_field_depth > kFmmMaxDepth)
+            return fail(SPK_EINVAL, "far_field_depth must be 0 or in [2, %d]", kFmmMaxDepth);
+        if (prm->far_field_order < kFmmMinOrder || prm->far_field_order > kFmmMaxOrder)
+            return fail(SPK_EINVAL, "far_field_order must be in [%d, %d]", kFmmMinOrder,
+                        kFmmMaxOrder);
+        if (prm->precision != SPK_PLAIN_FP64 && prm->precision != SPK_FP32_COMP)
+            return fail(SPK_EUNSUPPORTED, "the far field runs in the plain_fp64 and fp32_comp "
+                                          "forms only");
+    }
     if (prm->attraction_field &&
         reinterpret_cast<uintptr_t>(prm->attraction_field) % (4 * elt_size(prm->precision)))
         return fail(SPK_EINVAL, "attraction_field is not %zu-byte aligned",
@@ -219,6 +229,11 @@ Plan make_plan(int precision, bool cells, int64_t p_total, int64_t n_src, int64_
 struct Layout {
     size_t acc_a = 0, acc_r = 0, part = 0, red = 0, scal = 0, grad = 0, viol = 0, cells = 0;
     size_t chunk_sums = 0, info = 0;
+    // far field (only with far_field_depth > 0)
+    size_t fmm_box_part = 0, fmm_box = 0, fmm_keys_in = 0, fmm_keys_out = 0, fmm_vals_in = 0,
+           fmm_vals_out = 0, fmm_xs = 0, fmm_start = 0, fmm_chunks = 0, fmm_chunk_start = 0,
+           fmm_temp = 0, fmm_temp_bytes = 0, fmm_A = 0, fmm_Tm = 0;
+    size_t fmm_W[kFmmMaxDepth + 1] = {}, fmm_L[kFmmMaxDepth + 1] = {};
     size_t total = 0;
     int64_t ld = 0;
     int64_t part_rows = 0;   // capacity of the slab partials, in rows of 4 doubles
@@ -269,6 +284,29 @@ Layout make_layout(const spk_params *prm)
     L.viol = take(sizeof(double) * 4 * prm->n_shots);
     L.cells = take(elt_size(prm->precision) * 3 * cn);
     L.chunk_sums = take(sizeof(double) * ((M + kGridTargetChunk - 1) / kGridTargetChunk));
+    if (prm->far_field_depth > 0) {
+        const int D = prm->far_field_depth, n = prm->far_field_order;
+        const size_t n3 = (size_t)n * n * n;
+        const int64_t nleaves = int64_t(1) << (3 * D);
+        L.fmm_box_part = take(sizeof(double) * 6 * kFmmBoxBlocks);
+        L.fmm_box = take(sizeof(double) * 4);
+        L.fmm_keys_in = take(sizeof(uint32_t) * p);
+        L.fmm_keys_out = take(sizeof(uint32_t) * p);
+        L.fmm_vals_in = take(sizeof(uint32_t) * p);
+        L.fmm_vals_out = take(sizeof(uint32_t) * p);
+        L.fmm_xs = take(elt_size(prm->precision) * 3 * p);
+        L.fmm_start = take(sizeof(int32_t) * (nleaves + 1));
+        L.fmm_chunks = take(sizeof(int32_t) * (nleaves + 1));
+        L.fmm_chunk_start = take(sizeof(int32_t) * (nleaves + 1));
+        L.fmm_temp_bytes = fmm_sort_temp_bytes(p, D);
+        L.fmm_temp = take(L.fmm_temp_bytes);
+        for (int l = 2; l <= D; ++l) {
+            L.fmm_W[l] = take(sizeof(double) * fmm_level_cells(l) * n3);
+            L.fmm_L[l] = take(sizeof(double) * fmm_level_cells(l) * 4 * n3);
+        }
+        L.fmm_A = take(sizeof(double) * 343 * 4 * n3 * n3);
+        L.fmm_Tm = take(sizeof(double) * 8 * n3 * n3);
+    }
     L.total = off + 256;   // slack for aligning the caller's base pointer
     return L;
 }
@@ -283,6 +321,7 @@ struct Ws {
     double *chunk_sums() const { return reinterpret_cast<double *>(base + L.chunk_sums); }
     double *scal() const { return reinterpret_cast<double *>(base + L.scal); }
     double *info() const { return reinterpret_cast<double *>(base + L.info); }
+    template <typename P> P *at(size_t off) const { return reinterpret_cast<P *>(base + off); }
     void *grad() const { return base + L.grad; }
     double *viol() const { return reinterpret_cast<double *>(base + L.viol); }
     void *cells() const { return base + L.cells; }
@@ -366,14 +405,65 @@ int run_sweep(const spk_params *prm, bool cells, const void *tx, const void *ty,
     return SPK_OK;
 }
 
+// The repulsion sums of targets [t0, t0+nt) by the far-field method.
+int run_far_field(const spk_params *prm, const void *kx, const void *ky, const void *kz,
+                  int64_t t0, int64_t nt, bool energy, const Ws &w, hipStream_t s)
+{
+    const Layout &L = w.L;
+    const int64_t p = prm->n_shots * prm->n_samples;
+    FmmLaunch f;
+    f.precision = prm->precision;
+    f.kernel = (prm->flags & SPK_FLAG_LOG_KERNEL) ? kKernelLog : kKernelDistance;
+    f.energy = energy;
+    f.depth = prm->far_field_depth;
+    f.order = prm->far_field_order;
+    f.x = kx;
+    f.y = ky;
+    f.z = kz;
+    f.p = p;
+    f.t0 = t0;
+    f.nt = nt;
+    f.eps = prm->eps;
+    f.acc = w.acc_r();
+    f.ld = L.ld;
+    f.near_tpb = sweep_targets_per_block(prm->precision);
+    f.box_part = w.at<double>(L.fmm_box_part);
+    f.box = w.at<double>(L.fmm_box);
+    f.keys_in = w.at<uint32_t>(L.fmm_keys_in);
+    f.keys_out = w.at<uint32_t>(L.fmm_keys_out);
+    f.vals_in = w.at<uint32_t>(L.fmm_vals_in);
+    f.vals_out = w.at<uint32_t>(L.fmm_vals_out);
+    char *xs = w.at<char>(L.fmm_xs);
+    const size_t al = elt_size(prm->precision);
+    f.xs = xs;
+    f.ys = xs + al * p;
+    f.zs = xs + 2 * al * p;
+    f.start = w.at<int32_t>(L.fmm_start);
+    f.chunks = w.at<int32_t>(L.fmm_chunks);
+    f.chunk_start = w.at<int32_t>(L.fmm_chunk_start);
+    f.temp = w.at<char>(L.fmm_temp);
+    f.temp_bytes = L.fmm_temp_bytes;
+    for (int l = 2; l <= f.depth; ++l) {
+        f.W[l] = w.at<double>(L.fmm_W[l]);
+        f.L[l] = w.at<double>(L.fmm_L[l]);
+    }
+    f.A = w.at<double>(L.fmm_A);
+    f.Tm = w.at<double>(L.fmm_Tm);
+    Timed tm(SPK_KIND_REPULSION, 0.0, s);
+    SPK_HIP(launch_fmm_repulsion(f, s), "far-field repulsion");
+    return SPK_OK;
+}
+
 // Both sweeps for targets [t0, t0+nt) of K; results in w.acc_a() / w.acc_r().
 int run_gradient_sums(const spk_params *prm, const void *kx, const void *ky, const void *kz,
                       const void *rho, int64_t t0, int64_t nt, bool energy, const Ws &w,
                       hipStream_t s)
 {
     const int64_t p = prm->n_shots * prm->n_samples;
-    int rc = run_sweep(prm, false, kx, ky, kz, t0, nt, p, kx, ky, kz, nullptr, energy, w,
-                       w.acc_r(), s);
+    int rc = prm->far_field_depth > 0
+                 ? run_far_field(prm, kx, ky, kz, t0, nt, energy, w, s)
+                 : run_sweep(prm, false, kx, ky, kz, t0, nt, p, kx, ky, kz, nullptr, energy, w,
+                             w.acc_r(), s);
     if (rc)
         return rc;
     if (prm->attraction_field) {

@@ -1,0 +1,667 @@
+// Far field of the repulsion sums by a Chebyshev-interpolation fast multipole
+// method on a uniform octree (the hierarchical far field for very large p; the
+// paper uses a CPU FMM of this family, "Evaluating F^r and its gradient").
+//
+// For target i and every sample j farther than the 27 leaves around i's leaf,
+// H(x_i - x_j) and grad H(x_i - x_j) are replaced by their tensor Chebyshev
+// interpolants of order n in both arguments, summed level by level:
+//   P2P-free upward pass:  W_leaf[m]   = sum_{j in leaf} S_m(x_j)
+//                          W_parent[m] = sum_children sum_l S_m(y_child,l) W_child[l]
+//   interactions (M2L):    L_cell[c][m] = sum_{s in IL(cell)} sum_l K_c(x_m - y_l) W_s[l]
+//                          with IL = children of the parent's neighbours that
+//                          are not neighbours of the cell (189 per cell)
+//   downward pass (L2L):   L_child[c][l] += sum_m S_m(x_child,l) L_parent[c][m]
+//   evaluation (L2P):      far_c(x_i) = sum_m S_m(x_i) L_leaf[c][m]
+// with K_0..2 = the components of grad H and K_3 = H, S_m the product of 1-D
+// Chebyshev interpolation polynomials
+//   S_k(t) = 1/n + (2/n) sum_{i=1}^{n-1} T_i(tbar_k) T_i(t),  tbar_k = cos((2k+1) pi / 2n),
+// and t the coordinate in the cell scaled to [-1, 1].  The near field (27
+// leaves) is summed exactly by the sample sweep's pair arithmetic (sweep.hip).
+//
+// Layout.  Samples are sorted by leaf (stable radix sort of the leaf index,
+// x fastest); leaf k owns sorted samples [start[k], start[k+1]).  The cells of
+// level l (2^l per axis) are split into 8 parity classes; each class is a
+// sub-grid of side Q = 2^l / 2 padded by 2 zero cells on every side (side
+// P = Q + 4).  A target class and an offset of its interaction list then map
+// every target to its source by one constant shift of the padded linear
+// index, so M2L is a GEMM over padded columns: C[col][row] +=
+// A_o[row][k] B[col + shift][k], with rows (component, node) and k the source
+// nodes.  Every stage runs in double precision and in a fixed order.
+
+#include <algorithm>
+#include <cfloat>
+#include <cmath>
+
+#include <hipcub/hipcub.hpp>
+
+#include "spk_internal.h"
+
+namespace spk {
+namespace {
+
+constexpr int EW = 256;
+constexpr int kMaxOrder = 6;
+inline unsigned ew_blocks(int64_t n) { return (unsigned)((n + EW - 1) / EW); }
+
+// Host-computed Chebyshev tables passed by value: tb[i][k] = T_i(tbar_k).
+struct Cheb {
+    int n;
+    double tbar[kMaxOrder];
+    double tb[kMaxOrder][kMaxOrder];
+};
+
+// S_k(t) for k = 0..N-1 (T_i(t) by the three-term recurrence).
+template <int N>
+__device__ inline void cheb_s(const Cheb &ch, double t, double (&s)[N])
+{
+    double tp[N];
+    tp[0] = 1.0;
+    if (N > 1)
+        tp[1] = t;
+#pragma unroll
+    for (int i = 2; i < N; ++i)
+        tp[i] = 2.0 * t * tp[i - 1] - tp[i - 2];
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        double a = 0.0;
+#pragma unroll
+        for (int i = 1; i < N; ++i)
+            a += ch.tb[i][k] * tp[i];
+        s[k] = 1.0 / N + (2.0 / N) * a;
+    }
+}
+
+// S_k(t) for one k.
+template <int N>
+__device__ inline double cheb_s1(const Cheb &ch, int k, double t)
+{
+    double a = 0.0, t0 = 1.0, t1 = t;
+#pragma unroll
+    for (int i = 1; i < N; ++i) {
+        a += ch.tb[i][k] * t1;
+        const double t2 = 2.0 * t * t1 - t0;
+        t0 = t1;
+        t1 = t2;
+    }
+    return 1.0 / N + (2.0 / N) * a;
+}
+
+// ------------------------------------------------------------------ box
+template <typename T>
+__global__ __launch_bounds__(EW) void box_stage1(const T *x, const T *y, const T *z, int64_t p,
+                                                 double *part)
+{
+    __shared__ double red[6][EW];
+    double v[6] = {DBL_MAX, DBL_MAX, DBL_MAX, -DBL_MAX, -DBL_MAX, -DBL_MAX};
+    for (int64_t i = (int64_t)blockIdx.x * EW + threadIdx.x; i < p; i += (int64_t)gridDim.x * EW) {
+        const double c[3] = {(double)x[i], (double)y[i], (double)z[i]};
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            v[a] = c[a] < v[a] ? c[a] : v[a];
+            v[3 + a] = c[a] > v[3 + a] ? c[a] : v[3 + a];
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < 6; ++a)
+        red[a][threadIdx.x] = v[a];
+    __syncthreads();
+    for (int w = EW / 2; w >= 1; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const double o = red[a][threadIdx.x + w], q = red[3 + a][threadIdx.x + w];
+                red[a][threadIdx.x] = o < red[a][threadIdx.x] ? o : red[a][threadIdx.x];
+                red[3 + a][threadIdx.x] = q > red[3 + a][threadIdx.x] ? q : red[3 + a][threadIdx.x];
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 6)
+        part[blockIdx.x * 6 + threadIdx.x] = red[threadIdx.x][0];
+}
+
+// box[0..2] = centre, box[3] = half-width of the root cube (a little larger
+// than the samples' extent, and never zero).
+__global__ void box_stage2(const double *part, int nblk, double *box)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0)
+        return;
+    double lo[3] = {DBL_MAX, DBL_MAX, DBL_MAX}, hi[3] = {-DBL_MAX, -DBL_MAX, -DBL_MAX};
+    for (int b = 0; b < nblk; ++b)
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = part[b * 6 + a] < lo[a] ? part[b * 6 + a] : lo[a];
+            hi[a] = part[b * 6 + 3 + a] > hi[a] ? part[b * 6 + 3 + a] : hi[a];
+        }
+    double R = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        box[a] = 0.5 * (lo[a] + hi[a]);
+        const double h = 0.5 * (hi[a] - lo[a]);
+        R = h > R ? h : R;
+    }
+    R = R * (1.0 + 0x1p-20) + 1e-30;
+    box[3] = R;
+}
+
+// Leaf coordinate along one axis, clamped to [0, N-1] (NaN goes to 0).
+__device__ inline int64_t leaf_coord(double x, double c, double R, int64_t N)
+{
+    double k = floor((x - (c - R)) / (2.0 * R / (double)N));
+    k = !(k >= 0.0) ? 0.0 : (k > (double)(N - 1) ? (double)(N - 1) : k);
+    return (int64_t)k;
+}
+
+template <typename T>
+__global__ __launch_bounds__(EW) void leaf_keys_kernel(const T *x, const T *y, const T *z, int64_t p,
+                                                       const double *box, int64_t N,
+                                                       uint32_t *key, uint32_t *val)
+{
+    const int64_t i = (int64_t)blockIdx.x * EW + threadIdx.x;
+    if (i >= p)
+        return;
+    const double R = box[3];
+    const int64_t ix = leaf_coord((double)x[i], box[0], R, N);
+    const int64_t iy = leaf_coord((double)y[i], box[1], R, N);
+    const int64_t iz = leaf_coord((double)z[i], box[2], R, N);
+    key[i] = (uint32_t)(ix + N * (iy + N * iz));
+    val[i] = (uint32_t)i;
+}
+
+template <typename T>
+__global__ __launch_bounds__(EW) void gather_kernel(const T *x, const T *y, const T *z,
+                                                    const uint32_t *order, int64_t p, T *xs, T *ys,
+                                                    T *zs)
+{
+    const int64_t j = (int64_t)blockIdx.x * EW + threadIdx.x;
+    if (j >= p)
+        return;
+    const uint32_t i = order[j];
+    xs[j] = x[i];
+    ys[j] = y[i];
+    zs[j] = z[i];
+}
+
+// start[k] = number of sorted keys below k, for k = 0..nleaves.
+__global__ __launch_bounds__(EW) void leaf_bounds_kernel(const uint32_t *ks, int64_t p,
+                                                         int64_t nleaves, int32_t *start)
+{
+    const int64_t k = (int64_t)blockIdx.x * EW + threadIdx.x;
+    if (k > nleaves)
+        return;
+    int64_t lo = 0, hi = p;   // first index with ks[index] >= k
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if ((int64_t)ks[mid] < k)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    start[k] = (int32_t)lo;
+}
+
+// chunks[k] = ceil(count_k / tpb) for k < nleaves, chunks[nleaves] = 0.
+__global__ __launch_bounds__(EW) void leaf_chunks_kernel(const int32_t *start, int64_t nleaves,
+                                                         int tpb, int32_t *chunks)
+{
+    const int64_t k = (int64_t)blockIdx.x * EW + threadIdx.x;
+    if (k > nleaves)
+        return;
+    chunks[k] = k < nleaves ? (start[k + 1] - start[k] + tpb - 1) / tpb : 0;
+}
+
+__global__ __launch_bounds__(EW) void fill_kernel(double *a, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * EW + threadIdx.x;
+    if (i < n)
+        a[i] = 0.0;
+}
+
+// ------------------------------------------------------------------ tree geometry
+struct Level {
+    int64_t side;   // cells per axis, 2^l
+    int64_t P;      // padded class side, side/2 + 4
+    double *W;      // [8][P^3][n^3]
+    double *L;      // [8][P^3][4 n^3]
+};
+
+__device__ inline int64_t class_of(int64_t ix, int64_t iy, int64_t iz)
+{
+    return (ix & 1) + 2 * ((iy & 1) + 2 * (iz & 1));
+}
+
+__device__ inline int64_t padded(int64_t ix, int64_t iy, int64_t iz, int64_t P)
+{
+    return ((ix >> 1) + 2) + P * (((iy >> 1) + 2) + P * ((iz >> 1) + 2));
+}
+
+__device__ inline int64_t slot(int64_t ix, int64_t iy, int64_t iz, int64_t P)
+{
+    return class_of(ix, iy, iz) * P * P * P + padded(ix, iy, iz, P);
+}
+
+// ------------------------------------------------------------------ P2M
+template <int N, typename T>
+__global__ __launch_bounds__(EW) void p2m_kernel(const T *xs, const T *ys, const T *zs,
+                                                 const int32_t *start, const double *box,
+                                                 int64_t side, Level lev, Cheb ch)
+{
+    constexpr int N3 = N * N * N;
+    const int64_t leaf = blockIdx.x;
+    const int32_t j0 = start[leaf], j1 = start[leaf + 1];
+    if (j0 == j1)
+        return;
+    const int64_t ix = leaf % side, iy = (leaf / side) % side, iz = leaf / (side * side);
+    const double R = box[3];
+    const double h = 2.0 * R / (double)side, hh = 0.5 * h;
+    const double cx = box[0] - R + ((double)ix + 0.5) * h;
+    const double cy = box[1] - R + ((double)iy + 0.5) * h;
+    const double cz = box[2] - R + ((double)iz + 0.5) * h;
+    double *w = lev.W + slot(ix, iy, iz, lev.P) * N3;
+    for (int m = threadIdx.x; m < N3; m += EW) {
+        const int mx = m % N, my = (m / N) % N, mz = m / (N * N);
+        double a = 0.0;
+        for (int32_t j = j0; j < j1; ++j) {
+            const double sx = cheb_s1<N>(ch, mx, ((double)xs[j] - cx) / hh);
+            const double sy = cheb_s1<N>(ch, my, ((double)ys[j] - cy) / hh);
+            const double sz = cheb_s1<N>(ch, mz, ((double)zs[j] - cz) / hh);
+            a += sx * sy * sz;
+        }
+        w[m] = a;
+    }
+}
+
+// T[pos][m][l] = prod_a S_{m_a}(u_a), u = child node l in the parent's frame.
+template <int N>
+__global__ __launch_bounds__(EW) void transfer_kernel(Cheb ch, double *Tm)
+{
+    constexpr int N3 = N * N * N;
+    const int64_t e = (int64_t)blockIdx.x * EW + threadIdx.x;
+    if (e >= 8 * N3 * N3)
+        return;
+    const int pos = (int)(e / (N3 * N3));
+    const int m = (int)((e / N3) % N3), l = (int)(e % N3);
+    const int mi[3] = {m % N, (m / N) % N, m / (N * N)};
+    const int li[3] = {l % N, (l / N) % N, l / (N * N)};
+    double v = 1.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const double u = (-0.5 + (double)((pos >> a) & 1)) + 0.5 * ch.tbar[li[a]];
+        v *= cheb_s1<N>(ch, mi[a], u);
+    }
+    Tm[e] = v;
+}
+
+// ------------------------------------------------------------------ M2M
+template <int N>
+__global__ __launch_bounds__(EW) void m2m_kernel(Level par, Level chd, const double *Tm)
+{
+    constexpr int N3 = N * N * N;
+    const int64_t side = par.side;
+    const int64_t cell = blockIdx.x;
+    const int64_t ix = cell % side, iy = (cell / side) % side, iz = cell / (side * side);
+    for (int m = threadIdx.x; m < N3; m += EW) {
+        double a = 0.0;
+        for (int pos = 0; pos < 8; ++pos) {
+            const int64_t cxi = 2 * ix + (pos & 1), cyi = 2 * iy + ((pos >> 1) & 1),
+                          czi = 2 * iz + ((pos >> 2) & 1);
+            const double *wc = chd.W + slot(cxi, cyi, czi, chd.P) * N3;
+            const double *t = Tm + ((int64_t)pos * N3 + m) * N3;
+            for (int l = 0; l < N3; ++l)
+                a += t[l] * wc[l];
+        }
+        par.W[slot(ix, iy, iz, par.P) * N3 + m] = a;
+    }
+}
+
+// ------------------------------------------------------------------ M2L tables
+// A[o][row][l], row = c*n^3 + m: K_c(x_m - y_l) with target nodes hl*tbar_m
+// (relative to the target centre) and source nodes o*h + hl*tbar_l.
+template <int N, int KERN>
+__global__ __launch_bounds__(EW) void m2l_table_kernel(const double *box, int level, double eps,
+                                                       Cheb ch, double *A)
+{
+    constexpr int N3 = N * N * N;
+    const int64_t e = (int64_t)blockIdx.x * EW + threadIdx.x;
+    if (e >= (int64_t)343 * 4 * N3 * N3)
+        return;
+    const int64_t o = e / (4 * N3 * N3);
+    const int row = (int)((e / N3) % (4 * N3)), l = (int)(e % N3);
+    const int c = row / N3, m = row % N3;
+    const int ov[3] = {(int)(o % 7) - 3, (int)((o / 7) % 7) - 3, (int)(o / 49) - 3};
+    const int mi[3] = {m % N, (m / N) % N, m / (N * N)};
+    const int li[3] = {l % N, (l / N) % N, l / (N * N)};
+    const double h = 2.0 * box[3] / (double)(int64_t(1) << level), hl = 0.5 * h;
+    double d[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+        d[a] = hl * ch.tbar[mi[a]] - ((double)ov[a] * h + hl * ch.tbar[li[a]]);
+    const double s = d[0] * d[0] + d[1] * d[1] + d[2] * d[2] + eps * eps;
+    double v;
+    if (KERN == kKernelLog)
+        v = c < 3 ? d[c] / s : 0.5 * log(s);
+    else
+        v = c < 3 ? (s > 0.0 ? d[c] / sqrt(s) : 0.0) : sqrt(s);
+    A[e] = v;
+}
+
+// Offset o (|o_a| <= 3, linear index o = (ox+3) + 7(oy+3) + 49(oz+3)) is in the
+// interaction list of target class ct when it is not a neighbour and the
+// source's parent is a neighbour of the target's parent.
+__device__ inline bool in_list(int o, int ct)
+{
+    const int ov[3] = {o % 7 - 3, (o / 7) % 7 - 3, o / 49 - 3};
+    bool near = true;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const int v = ov[a];
+        if (v < -1 || v > 1)
+            near = false;
+        const bool odd = (ct >> a) & 1;
+        if (!odd && (v < -2 || v > 3))
+            return false;
+        if (odd && (v < -3 || v > 2))
+            return false;
+    }
+    return !near;
+}
+
+// ------------------------------------------------------------------ M2L (GEMM)
+constexpr int GT = 64;    // C tile (rows x cols)
+constexpr int GK = 16;    // k step
+template <int N>
+__global__ __launch_bounds__(256) void m2l_kernel(Level lev, const double *A)
+{
+    constexpr int N3 = N * N * N, ROWS = 4 * N3;
+    __shared__ double As[GK][GT + 1];
+    __shared__ double Bs[GK][GT + 1];
+    const int64_t P = lev.P, P3 = P * P * P;
+    const int64_t span0 = 2 + 2 * P + 2 * P * P;
+    const int64_t ncol = P3 - 2 * span0;
+    const int ct = blockIdx.z;
+    const int row0 = blockIdx.x * GT;
+    const int64_t col0 = span0 + (int64_t)blockIdx.y * GT;
+    const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+    double acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            acc[i][j] = 0.0;
+    for (int o = 0; o < 343; ++o) {
+        if (!in_list(o, ct))
+            continue;
+        const int ov[3] = {o % 7 - 3, (o / 7) % 7 - 3, o / 49 - 3};
+        int cs = 0;
+        int64_t shift = 0, mul = 1;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const int ca = (ct >> a) & 1;
+            const int sa = (ca + ov[a]) & 1;
+            cs |= sa << a;
+            shift += (int64_t)((ca + ov[a] - sa) / 2) * mul;
+            mul *= P;
+        }
+        const double *Ao = A + (int64_t)o * ROWS * N3;
+        const double *Bc = lev.W + (int64_t)cs * P3 * N3;
+        for (int k0 = 0; k0 < N3; k0 += GK) {
+            // stage A[row0..+64][k0..+16] and B[col0+shift..+64][k0..+16]
+            for (int e = threadIdx.x; e < GT * GK; e += 256) {
+                const int r = e / GK, k = e % GK;
+                const int row = row0 + r, kk = k0 + k;
+                As[k][r] = (row < ROWS && kk < N3) ? Ao[(int64_t)row * N3 + kk] : 0.0;
+                const int64_t col = col0 + r;
+                Bs[k][r] = (col - span0 < ncol && kk < N3) ? Bc[(col + shift) * N3 + kk] : 0.0;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < GK; ++k) {
+                double a[4], b[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    a[i] = As[k][ty * 4 + i];
+                    b[i] = Bs[k][tx * 4 + i];
+                }
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        acc[i][j] = fma(a[i], b[j], acc[i][j]);
+            }
+            __syncthreads();
+        }
+    }
+    double *Cc = lev.L + (int64_t)ct * P3 * ROWS;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int64_t col = col0 + tx * 4 + j;
+        if (col - span0 >= ncol)
+            continue;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int row = row0 + ty * 4 + i;
+            if (row < ROWS)
+                Cc[col * ROWS + row] = acc[i][j];
+        }
+    }
+}
+
+// ------------------------------------------------------------------ L2L
+template <int N>
+__global__ __launch_bounds__(EW) void l2l_kernel(Level par, Level chd, const double *Tm)
+{
+    constexpr int N3 = N * N * N;
+    const int64_t side = chd.side;
+    const int64_t cell = blockIdx.x;
+    const int64_t ix = cell % side, iy = (cell / side) % side, iz = cell / (side * side);
+    const int pos = (int)((ix & 1) + 2 * (iy & 1) + 4 * (iz & 1));
+    const double *lp = par.L + slot(ix >> 1, iy >> 1, iz >> 1, par.P) * 4 * N3;
+    double *lc = chd.L + slot(ix, iy, iz, chd.P) * 4 * N3;
+    for (int e = threadIdx.x; e < 4 * N3; e += EW) {
+        const int c = e / N3, l = e % N3;
+        double a = 0.0;
+        for (int m = 0; m < N3; ++m)
+            a += lp[c * N3 + m] * Tm[((int64_t)pos * N3 + m) * N3 + l];
+        lc[e] += a;
+    }
+}
+
+// ------------------------------------------------------------------ L2P
+template <int N, typename T>
+__global__ __launch_bounds__(EW) void l2p_kernel(const T *xs, const T *ys, const T *zs,
+                                                 const uint32_t *ks, const uint32_t *order,
+                                                 int64_t p, const double *box, Level leaves,
+                                                 Cheb ch, int64_t t0, int64_t nt, bool energy,
+                                                 double *acc, int64_t ld)
+{
+    constexpr int N3 = N * N * N;
+    const int64_t j = (int64_t)blockIdx.x * EW + threadIdx.x;
+    if (j >= p)
+        return;
+    const int64_t i = (int64_t)order[j] - t0;
+    if (i < 0 || i >= nt)
+        return;
+    const int64_t side = leaves.side;
+    const int64_t leaf = ks[j];
+    const int64_t ix = leaf % side, iy = (leaf / side) % side, iz = leaf / (side * side);
+    const double R = box[3];
+    const double h = 2.0 * R / (double)side, hh = 0.5 * h;
+    double sx[N], sy[N], sz[N];
+    cheb_s<N>(ch, ((double)xs[j] - (box[0] - R + ((double)ix + 0.5) * h)) / hh, sx);
+    cheb_s<N>(ch, ((double)ys[j] - (box[1] - R + ((double)iy + 0.5) * h)) / hh, sy);
+    cheb_s<N>(ch, ((double)zs[j] - (box[2] - R + ((double)iz + 0.5) * h)) / hh, sz);
+    const double *lf = leaves.L + slot(ix, iy, iz, leaves.P) * 4 * N3;
+    double f[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int mz = 0; mz < N; ++mz)
+        for (int my = 0; my < N; ++my) {
+            const double syz = sy[my] * sz[mz];
+#pragma unroll
+            for (int mx = 0; mx < N; ++mx) {
+                const int m = mx + N * (my + N * mz);
+                const double s = sx[mx] * syz;
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+                    f[c] += lf[c * N3 + m] * s;
+            }
+        }
+    acc[i] += f[0];
+    acc[ld + i] += f[1];
+    acc[2 * ld + i] += f[2];
+    if (energy)
+        acc[3 * ld + i] += f[3];
+}
+
+template <int N>
+hipError_t run_order(const FmmLaunch &f, hipStream_t s);
+
+}  // namespace
+
+int64_t fmm_padded_side(int level) { return (int64_t(1) << level) / 2 + 4; }
+
+size_t fmm_level_cells(int level)
+{
+    const int64_t P = fmm_padded_side(level);
+    return (size_t)(8 * P * P * P);
+}
+
+size_t fmm_sort_temp_bytes(int64_t p, int depth)
+{
+    const int64_t nleaves = int64_t(1) << (3 * depth);
+    size_t a = 0, b = 0;
+    hipcub::DeviceRadixSort::SortPairs(nullptr, a, (const uint32_t *)nullptr, (uint32_t *)nullptr,
+                                       (const uint32_t *)nullptr, (uint32_t *)nullptr, (int)p, 0,
+                                       3 * depth);
+    hipcub::DeviceScan::ExclusiveSum(nullptr, b, (const int32_t *)nullptr, (int32_t *)nullptr,
+                                     (int)(nleaves + 1));
+    return a > b ? a : b;
+}
+
+namespace {
+
+Cheb make_cheb(int n)
+{
+    Cheb ch{};
+    ch.n = n;
+    for (int k = 0; k < n; ++k) {
+        const double th = (2.0 * k + 1.0) * 3.14159265358979323846 / (2.0 * n);
+        ch.tbar[k] = std::cos(th);
+        for (int i = 0; i < n; ++i)
+            ch.tb[i][k] = std::cos(i * th);
+    }
+    return ch;
+}
+
+template <int N, typename T>
+hipError_t run_typed(const FmmLaunch &f, hipStream_t s)
+{
+    constexpr int N3 = N * N * N;
+    const T *x = static_cast<const T *>(f.x), *y = static_cast<const T *>(f.y),
+            *z = static_cast<const T *>(f.z);
+    T *xs = static_cast<T *>(f.xs), *ys = static_cast<T *>(f.ys), *zs = static_cast<T *>(f.zs);
+    const int64_t p = f.p, side = int64_t(1) << f.depth, nleaves = side * side * side;
+    const Cheb ch = make_cheb(N);
+    hipError_t e;
+    // root box
+    const int nb = (int)std::min<int64_t>(kFmmBoxBlocks, (p + EW - 1) / EW);
+    hipLaunchKernelGGL(box_stage1<T>, dim3(nb), dim3(EW), 0, s, x, y, z, p, f.box_part);
+    hipLaunchKernelGGL(box_stage2, dim3(1), dim3(64), 0, s, f.box_part, nb, f.box);
+    // leaf keys, stable sort by leaf, sorted coordinates, leaf ranges and chunks
+    hipLaunchKernelGGL(leaf_keys_kernel<T>, dim3(ew_blocks(p)), dim3(EW), 0, s, x, y, z, p, f.box,
+                       side, f.keys_in, f.vals_in);
+    size_t tb = f.temp_bytes;
+    if ((e = hipcub::DeviceRadixSort::SortPairs(f.temp, tb, f.keys_in, f.keys_out, f.vals_in,
+                                                f.vals_out, (int)p, 0, 3 * f.depth, s)) !=
+        hipSuccess)
+        return e;
+    hipLaunchKernelGGL(gather_kernel<T>, dim3(ew_blocks(p)), dim3(EW), 0, s, x, y, z, f.vals_out,
+                       p, xs, ys, zs);
+    hipLaunchKernelGGL(leaf_bounds_kernel, dim3(ew_blocks(nleaves + 1)), dim3(EW), 0, s,
+                       f.keys_out, p, nleaves, f.start);
+    hipLaunchKernelGGL(leaf_chunks_kernel, dim3(ew_blocks(nleaves + 1)), dim3(EW), 0, s, f.start,
+                       nleaves, f.near_tpb, f.chunks);
+    tb = f.temp_bytes;
+    if ((e = hipcub::DeviceScan::ExclusiveSum(f.temp, tb, f.chunks, f.chunk_start,
+                                              (int)(nleaves + 1), s)) != hipSuccess)
+        return e;
+    // multipole weights: zero (padding included), leaves, then upward
+    Level lev[kFmmMaxDepth + 1];
+    for (int l = 2; l <= f.depth; ++l) {
+        lev[l].side = int64_t(1) << l;
+        lev[l].P = fmm_padded_side(l);
+        lev[l].W = f.W[l];
+        lev[l].L = f.L[l];
+        const int64_t nw = (int64_t)fmm_level_cells(l) * N3;
+        hipLaunchKernelGGL(fill_kernel, dim3(ew_blocks(nw)), dim3(EW), 0, s, lev[l].W, nw);
+    }
+    hipLaunchKernelGGL(transfer_kernel<N>, dim3(ew_blocks(8 * N3 * N3)), dim3(EW), 0, s, ch, f.Tm);
+    hipLaunchKernelGGL((p2m_kernel<N, T>), dim3((unsigned)nleaves), dim3(EW), 0, s, xs, ys, zs,
+                       f.start, f.box, side, lev[f.depth], ch);
+    for (int l = f.depth - 1; l >= 2; --l)
+        hipLaunchKernelGGL(m2m_kernel<N>, dim3((unsigned)(int64_t(1) << (3 * l))), dim3(EW), 0, s,
+                           lev[l], lev[l + 1], f.Tm);
+    // interactions and the downward pass
+    for (int l = 2; l <= f.depth; ++l) {
+        const int64_t ntab = (int64_t)343 * 4 * N3 * N3;
+        if (f.kernel == kKernelLog)
+            hipLaunchKernelGGL((m2l_table_kernel<N, kKernelLog>), dim3(ew_blocks(ntab)), dim3(EW),
+                               0, s, f.box, l, f.eps, ch, f.A);
+        else
+            hipLaunchKernelGGL((m2l_table_kernel<N, kKernelDistance>), dim3(ew_blocks(ntab)),
+                               dim3(EW), 0, s, f.box, l, f.eps, ch, f.A);
+        const int64_t P = lev[l].P;
+        const int64_t ncol = P * P * P - 2 * (2 + 2 * P + 2 * P * P);
+        dim3 grid((unsigned)((4 * N3 + GT - 1) / GT), (unsigned)((ncol + GT - 1) / GT), 8);
+        hipLaunchKernelGGL(m2l_kernel<N>, grid, dim3(256), 0, s, lev[l], f.A);
+        if (l >= 3)
+            hipLaunchKernelGGL(l2l_kernel<N>, dim3((unsigned)(int64_t(1) << (3 * l))), dim3(EW),
+                               0, s, lev[l - 1], lev[l], f.Tm);
+    }
+    if ((e = hipGetLastError()) != hipSuccess)
+        return e;
+    // near field (exact pair sums over the 27 leaves around each leaf), then far field
+    NearLaunch nl;
+    nl.precision = f.precision;
+    nl.kernel = f.kernel;
+    nl.energy = f.energy;
+    nl.xs = xs;
+    nl.ys = ys;
+    nl.zs = zs;
+    nl.order = f.vals_out;
+    nl.start = f.start;
+    nl.chunk_start = f.chunk_start;
+    nl.nleaves = nleaves;
+    nl.side = side;
+    nl.t0 = f.t0;
+    nl.nt = f.nt;
+    nl.eps = f.eps;
+    nl.acc = f.acc;
+    nl.ld = f.ld;
+    nl.max_blocks = (p + f.near_tpb - 1) / f.near_tpb + nleaves;
+    if ((e = launch_near(nl, s)) != hipSuccess)
+        return e;
+    hipLaunchKernelGGL((l2p_kernel<N, T>), dim3(ew_blocks(p)), dim3(EW), 0, s, xs, ys, zs,
+                       f.keys_out, f.vals_out, p, f.box, lev[f.depth], ch, f.t0, f.nt, f.energy,
+                       f.acc, f.ld);
+    return hipGetLastError();
+}
+
+template <int N>
+hipError_t run_order(const FmmLaunch &f, hipStream_t s)
+{
+    return f.precision == SPK_PLAIN_FP64 ? run_typed<N, double>(f, s) : run_typed<N, float>(f, s);
+}
+
+}  // namespace
+
+hipError_t launch_fmm_repulsion(const FmmLaunch &f, hipStream_t s)
+{
+    if (f.depth < 2 || f.depth > kFmmMaxDepth || f.p < 1)
+        return hipErrorInvalidValue;
+    switch (f.order) {
+    case 3: return run_order<3>(f, s);
+    case 4: return run_order<4>(f, s);
+    case 5: return run_order<5>(f, s);
+    case 6: return run_order<6>(f, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace spk

@@ -14,6 +14,44 @@ namespace spk {
 // Largest shot length the projection kernel supports.
 constexpr int64_t kMaxProjectSamples = 4096;
 
+// Far field of the repulsion (fmm.hip): a Chebyshev fast multipole method on a
+// uniform octree of `depth` levels below the root cube, interpolation order
+// `order` per axis, with the near field summed exactly (launch_near).  Writes
+// the four repulsion sums of targets [t0, t0 + nt) to acc[c*ld + i - t0].
+constexpr int kFmmMaxDepth = 7;
+constexpr int kFmmMinOrder = 3;
+constexpr int kFmmMaxOrder = 6;
+constexpr int kFmmBoxBlocks = 1024;
+struct FmmLaunch {
+    int precision = 0, kernel = kKernelDistance;
+    bool energy = false;
+    int depth = 0, order = 0;
+    const void *x = nullptr, *y = nullptr, *z = nullptr;
+    int64_t p = 0, t0 = 0, nt = 0;
+    double eps = 0.0;
+    double *acc = nullptr;
+    int64_t ld = 0;
+    int near_tpb = 0;                     // targets per near-field block
+    // workspace
+    double *box_part = nullptr;           // [kFmmBoxBlocks][6]
+    double *box = nullptr;                // centre[3], half-width
+    uint32_t *keys_in = nullptr, *keys_out = nullptr, *vals_in = nullptr, *vals_out = nullptr;
+    void *xs = nullptr, *ys = nullptr, *zs = nullptr;
+    int32_t *start = nullptr, *chunks = nullptr, *chunk_start = nullptr;   // [8^depth + 1]
+    void *temp = nullptr;
+    size_t temp_bytes = 0;
+    double *W[kFmmMaxDepth + 1] = {};     // level l: [8][P^3][order^3]
+    double *L[kFmmMaxDepth + 1] = {};     // level l: [8][P^3][4 order^3]
+    double *A = nullptr;                  // [343][4 order^3][order^3]
+    double *Tm = nullptr;                 // [8][order^3][order^3]
+};
+// Padded class side P and cell slots 8 P^3 of level l.
+int64_t fmm_padded_side(int level);
+size_t fmm_level_cells(int level);
+// Temporary bytes of the leaf sort (3 * depth key bits) and of the block-count scan.
+size_t fmm_sort_temp_bytes(int64_t p, int depth);
+hipError_t launch_fmm_repulsion(const FmmLaunch &f, hipStream_t s);
+
 // acc[c*ld + t] = (init ? 0 : acc[c*ld + t]) + part[0][c][t] + ... + part[n-1][c][t],
 // with part[y][c][t] at part[(y*4 + c)*part_ld + t].
 hipError_t launch_combine(double *acc, int64_t ld, const double *part, int64_t part_ld,

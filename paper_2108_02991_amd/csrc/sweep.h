@@ -80,4 +80,29 @@ struct SweepLaunch {
 hipError_t launch_sweep_samples(const SweepLaunch &l, hipStream_t s);
 hipError_t launch_sweep_cells(const SweepLaunch &l, hipStream_t s);
 
+// Near field of the far-field repulsion (plain FP64 and compensated FP32
+// forms): targets of each leaf against the samples of the 27 leaves around
+// it, from samples sorted by leaf.  Writes the four sums of every target in
+// [t0, t0 + nt) to acc[c*ld + i - t0].  Blocks of sweep_targets_per_block()
+// targets; chunk_start[k] is the first block of leaf k (an exclusive prefix
+// sum of the per-leaf block counts, nleaves + 1 entries); the grid has
+// max_blocks >= chunk_start[nleaves] blocks and the extra ones return.
+struct NearLaunch {
+    int precision = 0;
+    int kernel = kKernelDistance;
+    bool energy = false;
+    const void *xs = nullptr, *ys = nullptr, *zs = nullptr;   // leaf-sorted samples
+    const uint32_t *order = nullptr;   // sorted position -> sample index
+    const int32_t *start = nullptr;    // [nleaves + 1]: first sorted sample of each leaf
+    const int32_t *chunk_start = nullptr;
+    int64_t nleaves = 0, side = 0;     // leaves, and leaves per axis
+    int64_t t0 = 0, nt = 0;
+    double eps = 0.0;
+    double *acc = nullptr;
+    int64_t ld = 0;
+    int64_t max_blocks = 0;
+};
+
+hipError_t launch_near(const NearLaunch &l, hipStream_t s);
+
 }  // namespace spk

@@ -403,6 +403,117 @@ void sweep_cells_kernel(SweepLaunch l)
     }
 }
 
+// Near field of the far-field repulsion: every sample of a leaf against the
+// samples of the 27 leaves around it, which are nine contiguous runs of the
+// leaf-sorted samples (three consecutive leaves along x for each y, z
+// neighbour).  Block b takes chunk b - chunk_start[leaf] of the leaf with
+// chunk_start[leaf] <= b < chunk_start[leaf + 1]; the pair arithmetic and the
+// accumulation are those of the sample sweep, and the sums are written (not
+// added) to the rows of targets in [t0, t0 + nt).
+template <int MODE, int R, bool ENERGY, int KERN>
+__global__ __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(min_waves<MODE>())))
+void near_kernel(NearLaunch l)
+{
+    using T = typename ModeT<MODE>::T;
+    __shared__ P4<T> tile[kSampleTile];
+    const int64_t b = blockIdx.x;
+    if (b >= (int64_t)l.chunk_start[l.nleaves])
+        return;
+    int64_t lo = 0, hi = l.nleaves;          // chunk_start[lo] <= b < chunk_start[hi]
+    while (hi - lo > 1) {
+        const int64_t mid = (lo + hi) >> 1;
+        if ((int64_t)l.chunk_start[mid] <= b)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    const int64_t leaf = lo;
+    const int64_t side = l.side;
+    const int64_t ix = leaf % side, iy = (leaf / side) % side, iz = leaf / (side * side);
+    const int64_t first = (int64_t)l.start[leaf] + (b - l.chunk_start[leaf]) * (int64_t)(BLK * R);
+    const int64_t last = (int64_t)l.start[leaf + 1] - 1;
+    const T *xs = static_cast<const T *>(l.xs), *ys = static_cast<const T *>(l.ys),
+            *zs = static_cast<const T *>(l.zs);
+    T xi[R], yi[R], zi[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        int64_t j = first + threadIdx.x + r * BLK;
+        j = j < last ? j : last;
+        xi[r] = xs[j];
+        yi[r] = ys[j];
+        zi[r] = zs[j];
+    }
+    Acc<MODE> gx[R], gy[R], gz[R], ee[R];
+    const T guard = guard_value<T>(l.eps);
+    for (int oz = -1; oz <= 1; ++oz)
+        for (int oy = -1; oy <= 1; ++oy) {
+            const int64_t y = iy + oy, z = iz + oz;
+            if (y < 0 || y >= side || z < 0 || z >= side)
+                continue;
+            const int64_t x0 = ix > 0 ? ix - 1 : 0, x1 = ix + 1 < side ? ix + 1 : side - 1;
+            const int64_t row = side * (y + side * z);
+            const int64_t s0 = l.start[x0 + row], s1 = l.start[x1 + row + 1];
+            for (int64_t base = s0; base < s1; base += kSampleTile) {
+                const int n = (int)((s1 - base) < kSampleTile ? (s1 - base) : kSampleTile);
+                for (int j = threadIdx.x; j < n; j += BLK)
+                    tile[j] = P4<T>{xs[base + j], ys[base + j], zs[base + j], T(0)};
+                __syncthreads();
+                for (int j = 0; j < n; ++j) {
+                    const P4<T> sv = tile[j];
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        T dx = xi[r] - sv.x, dy = yi[r] - sv.y, dz = zi[r] - sv.z;
+                        T r2 = fmaT(dz, dz, fmaT(dy, dy, fmaT(dx, dx, guard)));
+                        T w = pair_weight<KERN>(r2);
+                        acc_fma(gx[r], w, dx);
+                        acc_fma(gy[r], w, dy);
+                        acc_fma(gz[r], w, dz);
+                        if constexpr (ENERGY) {
+                            if constexpr (KERN == kLog)
+                                acc_add(ee[r], lg2(r2));
+                            else
+                                acc_fma(ee[r], w, r2);
+                        }
+                    }
+                }
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    gx[r].end_tile();
+                    gy[r].end_tile();
+                    gz[r].end_tile();
+                    if constexpr (ENERGY)
+                        ee[r].end_tile();
+                }
+                __syncthreads();
+            }
+        }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t j = first + threadIdx.x + r * BLK;
+        if (j > last)
+            continue;
+        const int64_t i = (int64_t)l.order[j] - l.t0;
+        if (i < 0 || i >= l.nt)
+            continue;
+        l.acc[i] = gx[r].total();
+        l.acc[l.ld + i] = gy[r].total();
+        l.acc[2 * l.ld + i] = gz[r].total();
+        if constexpr (KERN == kLog)
+            l.acc[3 * l.ld + i] = ENERGY ? potential_scale<KERN>() * ee[r].total() : 0.0;
+        else
+            l.acc[3 * l.ld + i] = ENERGY ? ee[r].total() : 0.0;
+    }
+}
+
+template <int MODE, bool ENERGY, int KERN>
+hipError_t launch_near_mode(const NearLaunch &l, hipStream_t s)
+{
+    constexpr int R = lanes_targets<MODE>();
+    hipLaunchKernelGGL((near_kernel<MODE, R, ENERGY, KERN>), dim3((unsigned)l.max_blocks),
+                       dim3(BLK), 0, s, l);
+    return hipGetLastError();
+}
+
 template <int MODE, bool ENERGY, int KERN>
 hipError_t launch_samples_mode(const SweepLaunch &l, hipStream_t s)
 {
@@ -451,6 +562,29 @@ hipError_t launch_any(const SweepLaunch &l, hipStream_t s)
 }
 
 }  // namespace
+
+hipError_t launch_near(const NearLaunch &l, hipStream_t s)
+{
+    if (l.max_blocks <= 0)
+        return hipSuccess;
+    const bool e = l.energy;
+    if (l.kernel == kLog) {
+        if (l.precision == kPlain64)
+            return e ? launch_near_mode<kPlain64, true, kLog>(l, s)
+                     : launch_near_mode<kPlain64, false, kLog>(l, s);
+        if (l.precision == kComp)
+            return e ? launch_near_mode<kComp, true, kLog>(l, s)
+                     : launch_near_mode<kComp, false, kLog>(l, s);
+        return hipErrorInvalidValue;
+    }
+    if (l.precision == kPlain64)
+        return e ? launch_near_mode<kPlain64, true, kDist>(l, s)
+                 : launch_near_mode<kPlain64, false, kDist>(l, s);
+    if (l.precision == kComp)
+        return e ? launch_near_mode<kComp, true, kDist>(l, s)
+                 : launch_near_mode<kComp, false, kDist>(l, s);
+    return hipErrorInvalidValue;
+}
 
 int sweep_targets_per_block(int precision)
 {

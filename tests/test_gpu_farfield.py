@@ -1,0 +1,107 @@
+"""The far field of the repulsion (Chebyshev fast multipole method on a uniform
+octree, exact near field) against the oracle and the exact all-pairs sweep."""
+import numpy as np
+import pytest
+import torch
+
+from gpu_util import (ENERGY_TOL, GRAD_TOL, configs, device_problem, host64, inputs, oracle,
+                      params_for, rel_l2, say, spk)
+
+pytestmark = pytest.mark.gpu
+
+
+def grad_pair(dev, K, rho, G, precision, depth, order, eps=0.0, kernel="distance"):
+    Nc, Ns = 1, K.shape[1]
+    exact = spk.Params(Nc, Ns, G, precision=precision, eps=eps, kernel=kernel)
+    far = spk.Params(Nc, Ns, G, precision=precision, eps=eps, kernel=kernel,
+                     far_field_depth=depth, far_field_order=order)
+    Kd, rd = device_problem(K, rho, precision, dev)
+    g0, (pa0, pr0), e0 = spk.grad(Kd, rd, exact, potentials=True, with_energy=True)
+    g1, (pa1, pr1), e1 = spk.grad(Kd, rd, far, potentials=True, with_energy=True)
+    torch.cuda.synchronize()
+    return Kd, rd, far, (host64(g0), host64(pr0), e0), (host64(g1), host64(pr1), e1)
+
+
+def test_small_ragged_against_oracle(gpu):
+    K = inputs.radial_spokes(37, 113, 0.5, seed=41, jitter=0.05)
+    rho = inputs.radial_density(9, 0.5, 0.0625, 2.0)
+    for precision in ("plain_fp64", "fp32_comp"):
+        for depth, order in ((2, 4), (3, 6)):
+            say(f"  far field {precision} depth {depth} order {order}, p = {K.shape[1]}")
+            Kd, rd, prm, ex, ff = grad_pair(gpu, K, rho, 9, precision, depth, order)
+            ref = oracle.grad(host64(Kd), host64(rd), 9, 0.5)
+            e_far = rel_l2(ff[0], ref["dF"])
+            e_pot = rel_l2(ff[1], ref["ur"])
+            say(f"    grad rel L2 {e_far:.3e}, repulsion potential {e_pot:.3e}")
+            assert rel_l2(ex[0], ref["dF"]) <= GRAD_TOL[precision]
+            assert e_far <= (3e-3 if order == 4 else 3e-5)
+            assert e_pot <= (1e-4 if order == 4 else 1e-6)
+
+
+def test_rerun_and_chunks_bitwise(gpu):
+    w = configs.C4
+    K, rho = w.trajectory(), w.density()
+    prm = params_for(w, "fp32_comp", far_field_depth=4, far_field_order=5)
+    Kd, rd = device_problem(K, rho, "fp32_comp", gpu)
+    full = spk.grad(Kd, rd, prm)
+    assert torch.equal(full, spk.grad(Kd, rd, prm))
+    parts = [spk.grad(Kd, rd, prm, tgt=(b, min(b + 5000, prm.p))) for b in range(0, prm.p, 5000)]
+    assert torch.equal(torch.cat(parts, dim=1), full)
+
+
+def test_coincident_and_outside_the_box(gpu):
+    # every sample at one point: all pairs are near, the far field is empty
+    K = np.full((3, 700), 0.125)
+    Kd, rd, prm, ex, ff = grad_pair(gpu, K, inputs.uniform_density(4), 4, "plain_fp64", 3, 5)
+    assert np.array_equal(ff[0], ex[0])
+    # samples outside [-L, L]^3: the octree spans the samples' own bounding cube
+    K = inputs.uniform_points(3000, 0.5, seed=5) * np.array([[3.0], [0.7], [1.5]])
+    Kd, rd, prm, ex, ff = grad_pair(gpu, K, inputs.uniform_density(4), 4, "plain_fp64", 4, 6)
+    say(f"  outside the box: grad rel L2 vs exact {rel_l2(ff[0], ex[0]):.3e}")
+    assert rel_l2(ff[0], ex[0]) <= 3e-5
+
+
+def test_c2_against_exact_sweep(gpu):
+    """524,288 samples on 128^3: the far field against the exact all-pairs sweep."""
+    w = configs.C2
+    K, rho = w.trajectory(), w.density()
+    for precision, depth, order, tol in (("fp32_comp", 5, 5, 3e-4), ("fp32_comp", 5, 6, 5e-5),
+                                         ("plain_fp64", 5, 6, 5e-5)):
+        Kd, rd, prm, ex, ff = grad_pair(gpu, K, rho, w.grid, precision, depth, order)
+        eg, ep = rel_l2(ff[0], ex[0]), rel_l2(ff[1], ex[1])
+        eF = abs(ff[2][0] - ex[2][0]) / abs(ex[2][0])
+        say(f"  c2 {precision} depth {depth} order {order}: grad F rel L2 {eg:.3e}, "
+            f"repulsion potential {ep:.3e}, F {eF:.3e}")
+        assert eg <= tol and ep <= tol / 10 and eF <= tol / 10
+
+
+def test_log_kernel_far_field(gpu):
+    K = inputs.radial_spokes(64, 128, 0.5, seed=42, jitter=0.05)
+    rho = inputs.radial_density(16, 0.5, 0.0625, 2.0)
+    eps = 0.01
+    Kd, rd, prm, ex, ff = grad_pair(gpu, K, rho, 16, "plain_fp64", 4, 6, eps=eps, kernel="log")
+    say(f"  log kernel: grad rel L2 vs exact {rel_l2(ff[0], ex[0]):.3e}")
+    assert rel_l2(ff[0], ex[0]) <= 1e-4
+
+
+def test_c3_far_field_sampled_against_oracle(gpu):
+    """8.4M samples, depth 5, order 6: rows against the oracle, and the time of both methods."""
+    w = configs.C3
+    K, rho = w.trajectory(), w.density()
+    prm = params_for(w, "fp32_comp", far_field_depth=5, far_field_order=6)
+    Kd, rd = device_problem(K, rho, "fp32_comp", gpu)
+    spk.grad(Kd, rd, prm)                       # warm-up
+    torch.cuda.synchronize()
+    spk.timing_reset()
+    spk.timing_enable(True)
+    g = spk.grad(Kd, rd, prm)
+    torch.cuda.synchronize()
+    spk.timing_enable(False)
+    rep_ms = spk.timing_query(spk.KIND_REPULSION)[0]
+    att_ms = spk.timing_query(spk.KIND_ATTRACTION)[0]
+    t = inputs.sample_targets(prm.p, 256, seed=43)
+    say(f"  c3 far-field repulsion {rep_ms:.1f} ms, attraction {att_ms:.1f} ms; oracle on 256 targets")
+    ref = oracle.grad(host64(Kd), host64(rd), w.grid, 0.5, 0.0, t)
+    err = rel_l2(host64(g)[:, t], ref["dF"])
+    say(f"  c3 far field: grad rel L2 vs oracle {err:.3e}")
+    assert err <= 5e-5
