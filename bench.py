@@ -94,6 +94,9 @@ def main():
     ap.add_argument("--eta", choices=["fixed", "lipschitz"], default=None,
                     help="fixed step: the workload's (default, distance kernel) or 1/L from "
                          "the Lipschitz bound (default for the log kernel; needs eps > 0)")
+    ap.add_argument("--far-field", default=None, metavar="DEPTH,ORDER",
+                    help="repulsion by the Chebyshev fast multipole method (e.g. 5,6) instead "
+                         "of all p^2 pairs; value is then an equivalent rate and roofline null")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed region, run a plain 1 GiB device copy three times "
                          "(reference dispatches for HBM byte counters)")
@@ -117,9 +120,11 @@ def main():
     p_total = w.n_shots * w.n_samples
     eps = args.eps if args.eps is not None else (
         0.25 * 2 * w.half_width / p_total ** (1.0 / 3.0) if args.kernel == "log" else 0.0)
+    ff_depth, ff_order = (int(v) for v in args.far_field.split(",")) if args.far_field else (0, 5)
     prm = spk.Params(w.n_shots, w.n_samples, w.grid, precision=precision,
                      half_width=w.half_width, eps=eps, a_max=a, b_max=b, te_index=0,
-                     n_pit=w.n_pit, kernel=args.kernel)
+                     n_pit=w.n_pit, kernel=args.kernel, far_field_depth=ff_depth,
+                     far_field_order=ff_order)
     p, M = prm.p, w.n_voxels
 
     log(f"workload {w.name}: p={p} G={w.grid} precision={precision} kernel={args.kernel} "
@@ -208,7 +213,8 @@ def main():
         "config": {"workload": w.name, "n_shots": w.n_shots, "n_samples": w.n_samples, "p": p,
                    "grid": w.grid, "precision": precision, "n_pit": w.n_pit,
                    "kernel": args.kernel, "eps": eps, "eta": eta_rule,
-                   "attraction": args.attraction, "pairs_per_step": pairs_per_step},
+                   "attraction": args.attraction, "pairs_per_step": pairs_per_step,
+                   "far_field": ({"depth": ff_depth, "order": ff_order} if ff_depth else None)},
         "s_per_grad_eval": grad_ms / 1e3,
         "kernels": {
             "repulsion": {"ms_per_step": rep["ms"] / args.steps, "launches_per_step":
@@ -223,9 +229,10 @@ def main():
             "projection_ms_per_step": kern["projection"]["ms"] / args.steps,
             "other_ms_per_step": kern["other"]["ms"] / args.steps,
         },
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK_TFLOPS,
-                     "traffic": recorded_traffic(w.name, precision, args.kernel)},
+        "roofline": ({"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS,
+                      "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK_TFLOPS,
+                      "traffic": recorded_traffic(w.name, precision, args.kernel)}
+                     if not ff_depth else None),
         "last_step": {k: (v.tolist() if isinstance(v, np.ndarray) else v)
                       for k, v in infos[-1].items()},
     }
@@ -239,6 +246,9 @@ def main():
         result["copy_calibration_bytes"] = {"read": src.numel() * 4, "write": dst.numel() * 4}
         del src, dst
 
+    if ff_depth:
+        result["value_kind"] = ("equivalent: the all-pairs interactions a step stands for, per "
+                                "second; the far field approximates the repulsion")
     if args.fp64_fraction > 0 and precision != "plain_fp64" and args.attraction == "direct":
         result["fp64_plain"] = fp64_comparison(spk, torch, w, prm, K, rho, args.fp64_fraction, dev)
 

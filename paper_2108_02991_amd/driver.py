@@ -34,7 +34,8 @@ def fixed_step(prm: api.Params, rho_mass: float, rule: str, eta_fixed: float) ->
 
 def run(workload: configs.Workload, precision: str, iters: int, device="cuda:0",
         out=None, log_every: int = 1, rotation_variant: bool = False, kernel: str = "distance",
-        eps: float = 0.0, eta_rule: str = "fixed", graph: bool = False):
+        eps: float = 0.0, eta_rule: str = "fixed", graph: bool = False,
+        far_field: tuple = (0, 5)):
     """Runs `iters` projected gradient steps; returns the list of records.
 
     With graph=True the step runs as two captured HIP graphs (fixed-step and
@@ -45,7 +46,8 @@ def run(workload: configs.Workload, precision: str, iters: int, device="cuda:0",
                           workload.fov, workload.kmax, configs.GAMMA_BAR, workload.half_width)
     prm = api.Params(workload.n_shots, workload.n_samples, workload.grid, precision=precision,
                      half_width=workload.half_width, eps=eps, a_max=a, b_max=b, te_index=0,
-                     n_pit=workload.n_pit, rotation_variant=rotation_variant, kernel=kernel)
+                     n_pit=workload.n_pit, rotation_variant=rotation_variant, kernel=kernel,
+                     far_field_depth=far_field[0], far_field_order=far_field[1])
     rho_host = workload.density()
     K = torch.tensor(workload.trajectory(), dtype=prm.dtype, device=dev)
     rho = torch.tensor(rho_host, dtype=prm.dtype, device=dev)
@@ -121,6 +123,16 @@ def _run_graph(K, rho, prm, state, eta, iters, precision, viol0, out, log_every)
     return records, K
 
 
+def _level_depth(depth: int, d: int) -> int:
+    """Octree depth of the far field at decimation level d: 8^depth leaves for
+    p / 2^d samples keep about as many samples per leaf when the depth drops by
+    one every three halvings; below depth 2 the sum is exact."""
+    if depth == 0:
+        return 0
+    dd = depth - (d + 1) // 3
+    return dd if dd >= 2 else 0
+
+
 def multiresolution(K0: torch.Tensor, rho: torch.Tensor, prm_full: api.Params, levels: int,
                     n_git: int, final_level: bool = True, eta_scale: float = 0.25, out=None,
                     log_every: int = 0, eta_rule: str = "fixed"):
@@ -148,7 +160,9 @@ def multiresolution(K0: torch.Tensor, rho: torch.Tensor, prm_full: api.Params, l
                          a_max=prm_full.a_max * 2.0 ** d, b_max=prm_full.b_max * 2.0 ** d,
                          te_index=prm_full.te_index, n_pit=prm_full.n_pit,
                          rotation_variant=prm_full.rotation_variant, kernel=prm_full.kernel,
-                         attraction_field=prm_full.attraction_field)
+                         attraction_field=prm_full.attraction_field,
+                         far_field_depth=_level_depth(prm_full.far_field_depth, d),
+                         far_field_order=prm_full.far_field_order)
         if K.shape[1] != prm.p:
             raise ValueError(f"level {d}: K has {K.shape[1]} samples, expected {prm.p}")
         eta = fixed_step(prm, float(rho.sum().item()), eta_rule,
@@ -196,6 +210,8 @@ def main():
                     help="run the single-level loop as captured HIP graphs")
     ap.add_argument("--n-pit", type=int, default=None,
                     help="projection iterations (default: the workload's)")
+    ap.add_argument("--far-field", default=None, metavar="DEPTH,ORDER",
+                    help="repulsion by the Chebyshev fast multipole method (e.g. 5,6)")
     args = ap.parse_args()
     w = configs.WORKLOADS[args.workload]
     if args.n_pit is not None:
@@ -203,12 +219,13 @@ def main():
     precision = args.precision or w.precision
     iters = args.iters if args.iters is not None else w.n_iters
     api.load_library()
+    ffd, ffo = (int(v) for v in args.far_field.split(",")) if args.far_field else (0, 5)
     out = open(args.out, "a") if args.out else None
     try:
         if args.levels == 0 and not args.field:
             run(w, precision, iters, out=out, log_every=args.log_every,
                 rotation_variant=args.rotation_variant, kernel=args.kernel, eps=args.eps,
-                eta_rule=args.eta, graph=args.graph)
+                eta_rule=args.eta, graph=args.graph, far_field=(ffd, ffo))
         else:
             dev = torch.device("cuda:0")
             a, b = api.alpha_beta(configs.GMAX, configs.SMAX, configs.RASTER_DT,
@@ -217,7 +234,8 @@ def main():
             prm = api.Params(w.n_shots, w.n_samples, w.grid, precision=precision,
                              half_width=w.half_width, a_max=a, b_max=b, te_index=0,
                              n_pit=w.n_pit, rotation_variant=args.rotation_variant,
-                             kernel=args.kernel, eps=args.eps)
+                             kernel=args.kernel, eps=args.eps, far_field_depth=ffd,
+                             far_field_order=ffo)
             from . import inputs
             K0 = inputs.radial_spokes(w.n_shots, w.n_samples >> args.levels, w.half_width,
                                       w.seed, w.jitter)
