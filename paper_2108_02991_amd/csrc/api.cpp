@@ -233,7 +233,8 @@ struct Layout {
     size_t fmm_box_part = 0, fmm_box = 0, fmm_keys_in = 0, fmm_keys_out = 0, fmm_vals_in = 0,
            fmm_vals_out = 0, fmm_xs = 0, fmm_start = 0, fmm_chunks = 0, fmm_chunk_start = 0,
            fmm_temp = 0, fmm_temp_bytes = 0, fmm_A = 0, fmm_Tm = 0;
-    size_t fmm_W[kFmmMaxDepth + 1] = {}, fmm_L[kFmmMaxDepth + 1] = {};
+    size_t fmm_W[kFmmMaxDepth + 1] = {}, fmm_L[kFmmMaxDepth + 1] = {},
+           fmm_occ[kFmmMaxDepth + 1] = {};
     size_t total = 0;
     int64_t ld = 0;
     int64_t part_rows = 0;   // capacity of the slab partials, in rows of 4 doubles
@@ -303,6 +304,7 @@ Layout make_layout(const spk_params *prm)
         for (int l = 2; l <= D; ++l) {
             L.fmm_W[l] = take(sizeof(double) * fmm_level_cells(l) * n3);
             L.fmm_L[l] = take(sizeof(double) * fmm_level_cells(l) * 4 * n3);
+            L.fmm_occ[l] = take(sizeof(int32_t) * fmm_level_cells(l));
         }
         L.fmm_A = take(sizeof(double) * 343 * 4 * n3 * n3);
         L.fmm_Tm = take(sizeof(double) * 8 * n3 * n3);
@@ -446,6 +448,7 @@ int run_far_field(const spk_params *prm, const void *kx, const void *ky, const v
     for (int l = 2; l <= f.depth; ++l) {
         f.W[l] = w.at<double>(L.fmm_W[l]);
         f.L[l] = w.at<double>(L.fmm_L[l]);
+        f.occ[l] = w.at<int32_t>(L.fmm_occ[l]);
     }
     f.A = w.at<double>(L.fmm_A);
     f.Tm = w.at<double>(L.fmm_Tm);

@@ -24,9 +24,10 @@
 // sub-grid of side Q = 2^l / 2 padded by 2 zero cells on every side (side
 // P = Q + 4).  A target class and an offset of its interaction list then map
 // every target to its source by one constant shift of the padded linear
-// index, so M2L is a GEMM over padded columns: C[col][row] +=
+// index, so M2L is a GEMM over the class's cells: C[col][row] +=
 // A_o[row][k] B[col + shift][k], with rows (component, node) and k the source
-// nodes.  Every stage runs in double precision and in a fixed order.
+// nodes.  Empty cells (no samples) are skipped.  Every stage runs in double
+// precision and in a fixed order.
 
 #include <algorithm>
 #include <cfloat>
@@ -215,12 +216,20 @@ __global__ __launch_bounds__(EW) void fill_kernel(double *a, int64_t n)
         a[i] = 0.0;
 }
 
+__global__ __launch_bounds__(EW) void fill_int_kernel(int32_t *a, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * EW + threadIdx.x;
+    if (i < n)
+        a[i] = 0;
+}
+
 // ------------------------------------------------------------------ tree geometry
 struct Level {
     int64_t side;   // cells per axis, 2^l
     int64_t P;      // padded class side, side/2 + 4
     double *W;      // [8][P^3][n^3]
     double *L;      // [8][P^3][4 n^3]
+    int32_t *occ;   // [8][P^3]: 1 if the cell holds samples (padding 0)
 };
 
 __device__ inline int64_t class_of(int64_t ix, int64_t iy, int64_t iz)
@@ -256,6 +265,8 @@ __global__ __launch_bounds__(EW) void p2m_kernel(const T *xs, const T *ys, const
     const double cy = box[1] - R + ((double)iy + 0.5) * h;
     const double cz = box[2] - R + ((double)iz + 0.5) * h;
     double *w = lev.W + slot(ix, iy, iz, lev.P) * N3;
+    if (threadIdx.x == 0)
+        lev.occ[slot(ix, iy, iz, lev.P)] = 1;
     for (int m = threadIdx.x; m < N3; m += EW) {
         const int mx = m % N, my = (m / N) % N, mz = m / (N * N);
         double a = 0.0;
@@ -298,6 +309,14 @@ __global__ __launch_bounds__(EW) void m2m_kernel(Level par, Level chd, const dou
     const int64_t side = par.side;
     const int64_t cell = blockIdx.x;
     const int64_t ix = cell % side, iy = (cell / side) % side, iz = cell / (side * side);
+    int32_t any = 0;
+    for (int pos = 0; pos < 8; ++pos)
+        any |= chd.occ[slot(2 * ix + (pos & 1), 2 * iy + ((pos >> 1) & 1),
+                            2 * iz + ((pos >> 2) & 1), chd.P)];
+    if (!any)
+        return;                      // W stays zero
+    if (threadIdx.x == 0)
+        par.occ[slot(ix, iy, iz, par.P)] = 1;
     for (int m = threadIdx.x; m < N3; m += EW) {
         double a = 0.0;
         for (int pos = 0; pos < 8; ++pos) {
@@ -365,24 +384,43 @@ __device__ inline bool in_list(int o, int ct)
 }
 
 // ------------------------------------------------------------------ M2L (GEMM)
-constexpr int GT = 64;    // C tile (rows x cols)
-constexpr int GK = 16;    // k step
+// Block (row tile, column tile, class ct): rows are (component, node) pairs,
+// columns the class's cells (Q^3 of them, Q = side/2) in sub-grid order.  The
+// block adds, offset by offset in a fixed order, A_o[rows][k] W[source][k]
+// into registers (8 x 4 per thread) and writes the tile once.  Tiles without
+// an occupied target cell are skipped (nothing reads the local expansion of
+// an empty cell), and so are offsets whose 64 source cells are all empty
+// (their weights are exact zeros).
+constexpr int TM = 128, TN = 64, TK = 8;
 template <int N>
 __global__ __launch_bounds__(256) void m2l_kernel(Level lev, const double *A)
 {
     constexpr int N3 = N * N * N, ROWS = 4 * N3;
-    __shared__ double As[GK][GT + 1];
-    __shared__ double Bs[GK][GT + 1];
-    const int64_t P = lev.P, P3 = P * P * P;
-    const int64_t span0 = 2 + 2 * P + 2 * P * P;
-    const int64_t ncol = P3 - 2 * span0;
+    __shared__ double As[TK][TM];
+    __shared__ double Bs[TK][TN + 1];
+    __shared__ int64_t colpad[TN];
+    const int64_t P = lev.P, P3 = P * P * P, Q = lev.side / 2, Q3 = Q * Q * Q;
     const int ct = blockIdx.z;
-    const int row0 = blockIdx.x * GT;
-    const int64_t col0 = span0 + (int64_t)blockIdx.y * GT;
+    const int row0 = blockIdx.x * TM;
+    const int64_t c0 = (int64_t)blockIdx.y * TN;
     const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
-    double acc[4][4];
+    const int32_t *occ_t = lev.occ + (int64_t)ct * P3;
+    int mine = 0;
+    if (threadIdx.x < TN) {
+        const int64_t c = c0 + threadIdx.x;
+        int64_t pc = -1;
+        if (c < Q3) {
+            const int64_t ux = c % Q, uy = (c / Q) % Q, uz = c / (Q * Q);
+            pc = (ux + 2) + P * ((uy + 2) + P * (uz + 2));
+            mine = occ_t[pc];
+        }
+        colpad[threadIdx.x] = pc;
+    }
+    if (!__syncthreads_or(mine))
+        return;
+    double acc[8][4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < 8; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j)
             acc[i][j] = 0.0;
@@ -400,28 +438,37 @@ __global__ __launch_bounds__(256) void m2l_kernel(Level lev, const double *A)
             shift += (int64_t)((ca + ov[a] - sa) / 2) * mul;
             mul *= P;
         }
-        const double *Ao = A + (int64_t)o * ROWS * N3;
         const double *Bc = lev.W + (int64_t)cs * P3 * N3;
-        for (int k0 = 0; k0 < N3; k0 += GK) {
-            // stage A[row0..+64][k0..+16] and B[col0+shift..+64][k0..+16]
-            for (int e = threadIdx.x; e < GT * GK; e += 256) {
-                const int r = e / GK, k = e % GK;
+        int src = 0;
+        if (threadIdx.x < TN && colpad[threadIdx.x] >= 0)
+            src = lev.occ[(int64_t)cs * P3 + colpad[threadIdx.x] + shift];
+        if (!__syncthreads_or(src))
+            continue;
+        const double *Ao = A + (int64_t)o * ROWS * N3;
+        for (int k0 = 0; k0 < N3; k0 += TK) {
+            for (int e = threadIdx.x; e < TM * TK; e += 256) {
+                const int r = e / TK, k = e % TK;
                 const int row = row0 + r, kk = k0 + k;
                 As[k][r] = (row < ROWS && kk < N3) ? Ao[(int64_t)row * N3 + kk] : 0.0;
-                const int64_t col = col0 + r;
-                Bs[k][r] = (col - span0 < ncol && kk < N3) ? Bc[(col + shift) * N3 + kk] : 0.0;
+            }
+            for (int e = threadIdx.x; e < TN * TK; e += 256) {
+                const int cl = e / TK, k = e % TK;
+                const int64_t pc = colpad[cl];
+                const int kk = k0 + k;
+                Bs[k][cl] = (pc >= 0 && kk < N3) ? Bc[(pc + shift) * N3 + kk] : 0.0;
             }
             __syncthreads();
 #pragma unroll
-            for (int k = 0; k < GK; ++k) {
-                double a[4], b[4];
+            for (int k = 0; k < TK; ++k) {
+                double a[8], b[4];
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    a[i] = As[k][ty * 4 + i];
-                    b[i] = Bs[k][tx * 4 + i];
-                }
+                for (int i = 0; i < 8; ++i)
+                    a[i] = As[k][ty * 8 + i];
 #pragma unroll
-                for (int i = 0; i < 4; ++i)
+                for (int j = 0; j < 4; ++j)
+                    b[j] = Bs[k][tx * 4 + j];
+#pragma unroll
+                for (int i = 0; i < 8; ++i)
 #pragma unroll
                     for (int j = 0; j < 4; ++j)
                         acc[i][j] = fma(a[i], b[j], acc[i][j]);
@@ -432,14 +479,14 @@ __global__ __launch_bounds__(256) void m2l_kernel(Level lev, const double *A)
     double *Cc = lev.L + (int64_t)ct * P3 * ROWS;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-        const int64_t col = col0 + tx * 4 + j;
-        if (col - span0 >= ncol)
+        const int64_t pc = colpad[tx * 4 + j];
+        if (pc < 0)
             continue;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int row = row0 + ty * 4 + i;
+        for (int i = 0; i < 8; ++i) {
+            const int row = row0 + ty * 8 + i;
             if (row < ROWS)
-                Cc[col * ROWS + row] = acc[i][j];
+                Cc[pc * ROWS + row] = acc[i][j];
         }
     }
 }
@@ -452,6 +499,8 @@ __global__ __launch_bounds__(EW) void l2l_kernel(Level par, Level chd, const dou
     const int64_t side = chd.side;
     const int64_t cell = blockIdx.x;
     const int64_t ix = cell % side, iy = (cell / side) % side, iz = cell / (side * side);
+    if (!chd.occ[slot(ix, iy, iz, chd.P)])
+        return;                      // nothing reads an empty cell's expansion
     const int pos = (int)((ix & 1) + 2 * (iy & 1) + 4 * (iz & 1));
     const double *lp = par.L + slot(ix >> 1, iy >> 1, iz >> 1, par.P) * 4 * N3;
     double *lc = chd.L + slot(ix, iy, iz, chd.P) * 4 * N3;
@@ -588,8 +637,11 @@ hipError_t run_typed(const FmmLaunch &f, hipStream_t s)
         lev[l].P = fmm_padded_side(l);
         lev[l].W = f.W[l];
         lev[l].L = f.L[l];
+        lev[l].occ = f.occ[l];
         const int64_t nw = (int64_t)fmm_level_cells(l) * N3;
         hipLaunchKernelGGL(fill_kernel, dim3(ew_blocks(nw)), dim3(EW), 0, s, lev[l].W, nw);
+        const int64_t no = (int64_t)fmm_level_cells(l);
+        hipLaunchKernelGGL(fill_int_kernel, dim3(ew_blocks(no)), dim3(EW), 0, s, lev[l].occ, no);
     }
     hipLaunchKernelGGL(transfer_kernel<N>, dim3(ew_blocks(8 * N3 * N3)), dim3(EW), 0, s, ch, f.Tm);
     hipLaunchKernelGGL((p2m_kernel<N, T>), dim3((unsigned)nleaves), dim3(EW), 0, s, xs, ys, zs,
@@ -606,9 +658,8 @@ hipError_t run_typed(const FmmLaunch &f, hipStream_t s)
         else
             hipLaunchKernelGGL((m2l_table_kernel<N, kKernelDistance>), dim3(ew_blocks(ntab)),
                                dim3(EW), 0, s, f.box, l, f.eps, ch, f.A);
-        const int64_t P = lev[l].P;
-        const int64_t ncol = P * P * P - 2 * (2 + 2 * P + 2 * P * P);
-        dim3 grid((unsigned)((4 * N3 + GT - 1) / GT), (unsigned)((ncol + GT - 1) / GT), 8);
+        const int64_t Q = lev[l].side / 2, Q3 = Q * Q * Q;
+        dim3 grid((unsigned)((4 * N3 + TM - 1) / TM), (unsigned)((Q3 + TN - 1) / TN), 8);
         hipLaunchKernelGGL(m2l_kernel<N>, grid, dim3(256), 0, s, lev[l], f.A);
         if (l >= 3)
             hipLaunchKernelGGL(l2l_kernel<N>, dim3((unsigned)(int64_t(1) << (3 * l))), dim3(EW),

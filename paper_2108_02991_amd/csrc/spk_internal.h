@@ -41,6 +41,7 @@ struct FmmLaunch {
     void *temp = nullptr;
     size_t temp_bytes = 0;
     double *W[kFmmMaxDepth + 1] = {};     // level l: [8][P^3][order^3]
+    int32_t *occ[kFmmMaxDepth + 1] = {};  // level l: [8][P^3]
     double *L[kFmmMaxDepth + 1] = {};     // level l: [8][P^3][4 order^3]
     double *A = nullptr;                  // [343][4 order^3][order^3]
     double *Tm = nullptr;                 // [8][order^3][order^3]
