@@ -105,3 +105,21 @@ def test_c3_far_field_sampled_against_oracle(gpu):
     err = rel_l2(host64(g)[:, t], ref["dF"])
     say(f"  c3 far field: grad rel L2 vs oracle {err:.3e}")
     assert err <= 5e-5
+
+
+def test_step_with_far_field_tracks_the_exact_step(gpu):
+    """One projected step at 2048 x 1024 samples with the far field against the exact step."""
+    w = configs.C5
+    K, rho = w.trajectory(), w.density()
+    out = []
+    for depth in (0, 5):
+        prm = params_for(w, "fp32_comp", far_field_depth=depth, far_field_order=6)
+        Kd, rd = device_problem(K, rho, "fp32_comp", gpu)
+        spk.project_(Kd, prm)
+        info = spk.step_(Kd, rd, prm, spk.StepState(prm, gpu), 0, w.eta_fixed)
+        out.append((host64(Kd), info))
+    d = np.abs(out[0][0] - out[1][0]).max()
+    say(f"  c5 step, far field vs exact: max |dK| {d:.3e}, F {out[1][1]['F']:.12e} vs "
+        f"{out[0][1]['F']:.12e}")
+    assert d <= 1e-5
+    assert out[1][1]["F"] == pytest.approx(out[0][1]["F"], rel=1e-7)
