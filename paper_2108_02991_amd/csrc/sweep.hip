@@ -458,8 +458,7 @@ void near_kernel(NearLaunch l)
                 for (int j = threadIdx.x; j < n; j += BLK)
                     tile[j] = P4<T>{xs[base + j], ys[base + j], zs[base + j], T(0)};
                 __syncthreads();
-                for (int j = 0; j < n; ++j) {
-                    const P4<T> sv = tile[j];
+                auto pair = [&](const P4<T> sv) {
 #pragma unroll
                     for (int r = 0; r < R; ++r) {
                         T dx = xi[r] - sv.x, dy = yi[r] - sv.y, dz = zi[r] - sv.z;
@@ -475,6 +474,29 @@ void near_kernel(NearLaunch l)
                                 acc_fma(ee[r], w, r2);
                         }
                     }
+                };
+                if (n == kSampleTile) {
+                    // full tile: LDS reads one group of U sources ahead, as in the sweep
+                    constexpr int U = SPK_SOURCE_UNROLL;
+                    P4<T> cur[U], nxt[U];
+#pragma unroll
+                    for (int u = 0; u < U; ++u)
+                        cur[u] = tile[u];
+                    for (int j = 0; j < kSampleTile; j += U) {
+                        const int jn = (j + U) & (kSampleTile - 1);
+#pragma unroll
+                        for (int u = 0; u < U; ++u)
+                            nxt[u] = tile[jn + u];
+#pragma unroll
+                        for (int u = 0; u < U; ++u)
+                            pair(cur[u]);
+#pragma unroll
+                        for (int u = 0; u < U; ++u)
+                            cur[u] = nxt[u];
+                    }
+                } else {
+                    for (int j = 0; j < n; ++j)
+                        pair(tile[j]);
                 }
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
