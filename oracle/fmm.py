@@ -1,0 +1,160 @@
+"""Plain NumPy reference of the repulsion's far field by the Chebyshev fast
+multipole method -- TEST INFRASTRUCTURE ONLY (tests import it; the product
+never does).  It shares no code with the HIP path.
+
+The method ("Evaluating F^r and its gradient": the FMM for large p; the
+kernel-independent Chebyshev variant, with the interpolation order n per axis
+as its precision parameter), step by step in its textbook order:
+
+* root cube: centre of the samples' bounding box, half-width R = (largest
+  half-extent) * (1 + 2^-20) + 1e-30;
+* uniform octree of depth D; sample i sits in leaf floor((x - (c - R)) /
+  (2R / 2^D)) per axis, clamped to [0, 2^D - 1];
+* upward pass: leaf weights W[m] = sum_i S_m(t_i) at the tensor Chebyshev
+  nodes (t: coordinates scaled to the cell's [-1, 1]^3), then parents from
+  children by interpolation at the children's nodes;
+* interactions, levels 2..D: every cell receives from the cells of its
+  interaction list (children of its parent's neighbours that are not its own
+  neighbours) the kernel evaluated between node sets, applied to their
+  weights;
+* downward pass: children add their parent's expansion interpolated at their
+  nodes; every sample adds its leaf's expansion interpolated at itself;
+* near field: every sample sums the kernel exactly over the samples of the
+  27 leaves around its leaf (itself included).
+
+S_k(t) = 1/n + (2/n) sum_{i=1}^{n-1} T_i(tbar_k) T_i(t), tbar_k = cos((2k+1) pi
+/ 2n).  Parity unpinned except by the pins in the tests (exactness for
+polynomial kernels of degree below n, convergence to the exact sum).
+"""
+import itertools
+
+import numpy as np
+
+
+def cheb_nodes(n):
+    return np.cos((2 * np.arange(n) + 1) * np.pi / (2 * n))
+
+
+def cheb_S(n, t):
+    """S[k, j] = S_k(t_j)."""
+    t = np.atleast_1d(np.asarray(t, dtype=np.float64))
+    Tb = np.cos(np.outer(np.arange(n), np.arccos(cheb_nodes(n))))      # [i, k]
+    Tt = np.empty((n, t.size))
+    Tt[0] = 1.0
+    if n > 1:
+        Tt[1] = t
+    for i in range(2, n):
+        Tt[i] = 2 * t * Tt[i - 1] - Tt[i - 2]
+    w = np.full(n, 2.0 / n)
+    w[0] = 1.0 / n
+    return (Tb * w[:, None]).T @ Tt
+
+
+def distance_kernel(eps=0.0):
+    def k(d):
+        s = (d ** 2).sum(axis=-1) + eps * eps
+        r = np.sqrt(s)
+        with np.errstate(invalid="ignore", divide="ignore"):
+            g = np.where(r[..., None] > 0, d / np.where(r > 0, r, 1.0)[..., None], 0.0)
+        return r, g
+    return k
+
+
+def log_kernel(eps):
+    def k(d):
+        s = (d ** 2).sum(axis=-1) + eps * eps
+        return 0.5 * np.log(s), d / s[..., None]
+    return k
+
+
+def square_kernel():
+    """H(d) = |d|^2 (degree 2): interpolated exactly from order 3 on."""
+    def k(d):
+        return (d ** 2).sum(axis=-1), 2.0 * d
+    return k
+
+
+def exact(X, kernel):
+    """(g (p, 3), u (p,)): sum over all j of grad H(x_i - x_j) and H(x_i - x_j)."""
+    u, g = kernel(X[:, None, :] - X[None, :, :])
+    return g.sum(axis=1), u.sum(axis=1)
+
+
+def fmm(X, depth, n, kernel):
+    """Repulsion sums of every sample by the Chebyshev FMM; X is (p, 3)."""
+    X = np.asarray(X, dtype=np.float64)
+    p = X.shape[0]
+    lo, hi = X.min(axis=0), X.max(axis=0)
+    c0 = 0.5 * (lo + hi)
+    R = (0.5 * (hi - lo)).max() * (1.0 + 2.0 ** -20) + 1e-30
+    N = 2 ** depth
+    leaf = np.clip(np.floor((X - (c0 - R)) / (2 * R / N)).astype(np.int64), 0, N - 1)
+    tb = cheb_nodes(n)
+    n3 = n ** 3
+    m = np.arange(n3)
+    m3 = np.stack([m % n, (m // n) % n, m // (n * n)], axis=1)          # x fastest
+
+    def Sm(t):                                                           # (q, 3) -> (n^3, q)
+        return (cheb_S(n, t[:, 0])[m3[:, 0]] * cheb_S(n, t[:, 1])[m3[:, 1]]
+                * cheb_S(n, t[:, 2])[m3[:, 2]])
+
+    def centre(level, cell):
+        h = 2 * R / 2 ** level
+        return c0 - R + (np.asarray(cell) + 0.5) * h, 0.5 * h
+
+    # upward pass
+    W = {depth: np.zeros((N, N, N, n3))}
+    cc, hh = centre(depth, leaf)
+    np.add.at(W[depth], (leaf[:, 0], leaf[:, 1], leaf[:, 2]), Sm((X - cc) / hh).T)
+    T = np.zeros((8, n3, n3))                                            # [pos, parent m, child l]
+    for pos in range(8):
+        b = np.array([pos & 1, (pos >> 1) & 1, (pos >> 2) & 1])
+        T[pos] = Sm((-0.5 + b[None, :]) + 0.5 * tb[m3])
+    for lvl in range(depth - 1, 1, -1):
+        Nl = 2 ** lvl
+        W[lvl] = np.zeros((Nl, Nl, Nl, n3))
+        for pos in range(8):
+            b = [pos & 1, (pos >> 1) & 1, (pos >> 2) & 1]
+            W[lvl] += W[lvl + 1][b[0]::2, b[1]::2, b[2]::2] @ T[pos].T
+    # interactions
+    Lx = {lvl: np.zeros((2 ** lvl,) * 3 + (4, n3)) for lvl in range(2, depth + 1)}
+    for lvl in range(2, depth + 1):
+        Nl = 2 ** lvl
+        h = 2 * R / Nl
+        cells = np.stack(np.meshgrid(*(np.arange(Nl),) * 3, indexing="ij"), -1).reshape(-1, 3)
+        for o in itertools.product(range(-3, 4), repeat=3):
+            o = np.array(o)
+            if np.abs(o).max() <= 1:
+                continue                                  # a neighbour: near field
+            src = cells + o
+            inside = ((src >= 0) & (src < Nl)).all(axis=1)
+            parents_near = np.abs(src // 2 - cells // 2).max(axis=1) <= 1
+            ok = inside & parents_near                    # in the cell's interaction list
+            if not ok.any():
+                continue
+            d = 0.5 * h * tb[m3][:, None, :] - (o * h + 0.5 * h * tb[m3])[None, :, :]
+            u, g = kernel(d)
+            Kc = np.stack([g[..., 0], g[..., 1], g[..., 2], u])          # (4, m, l)
+            t, s_ = cells[ok], src[ok]
+            w = W[lvl][s_[:, 0], s_[:, 1], s_[:, 2]]                       # (k, l)
+            Lx[lvl][t[:, 0], t[:, 1], t[:, 2]] += np.einsum("cml,kl->kcm", Kc, w)
+    # downward pass
+    for lvl in range(2, depth):
+        for pos in range(8):
+            b = [pos & 1, (pos >> 1) & 1, (pos >> 2) & 1]
+            Lx[lvl + 1][b[0]::2, b[1]::2, b[2]::2] += Lx[lvl] @ T[pos]
+    far = np.einsum("pcm,mp->pc", Lx[depth][leaf[:, 0], leaf[:, 1], leaf[:, 2]],
+                    Sm((X - cc) / hh))
+    g = far[:, :3].copy()
+    u = far[:, 3].copy()
+    # near field
+    members = {}
+    for i, key in enumerate(map(tuple, leaf)):
+        members.setdefault(key, []).append(i)
+    for key, tgt in members.items():
+        src = [j for o in itertools.product((-1, 0, 1), repeat=3)
+               for j in members.get(tuple(np.array(key) + o), [])]
+        uu, gg = kernel(X[tgt][:, None, :] - X[src][None, :, :])
+        g[tgt] += gg.sum(axis=1)
+        u[tgt] += uu.sum(axis=1)
+    return g, u

@@ -123,3 +123,22 @@ def test_step_with_far_field_tracks_the_exact_step(gpu):
         f"{out[0][1]['F']:.12e}")
     assert d <= 1e-5
     assert out[1][1]["F"] == pytest.approx(out[0][1]["F"], rel=1e-7)
+
+
+@pytest.mark.parametrize("depth,order", [(2, 4), (3, 5)])
+def test_matches_the_reference_fmm(gpu, depth, order):
+    """Plain FP64 GPU far field against the NumPy reference of the same method:
+    equal up to summation order."""
+    from oracle import fmm
+    K = inputs.radial_spokes(20, 90, 0.5, seed=53, jitter=0.05)
+    prm = spk.Params(20, 90, 1, precision="plain_fp64", far_field_depth=depth,
+                     far_field_order=order)
+    Kd, rd = device_problem(K, [0.0], "plain_fp64", gpu)       # no attraction
+    g, (pa, pr) = spk.grad(Kd, rd, prm, potentials=True)
+    gr, ur = fmm.fmm(K.T, depth, order, fmm.distance_kernel())
+    p = K.shape[1]
+    got = -host64(g) * p * p                                     # grad F = -sum grad H / p^2
+    err = np.abs(got - gr.T).max() / np.abs(gr).max()
+    say(f"  GPU vs reference FMM, depth {depth} order {order}: {err:.3e}")
+    assert err <= 1e-13
+    assert np.abs(host64(pr) - ur).max() <= 1e-13 * np.abs(ur).max()

@@ -696,3 +696,35 @@ def test_upsample_single_sample_shots():
     K = RNG.uniform(-0.3, 0.3, (3, 4))
     f = oracle.upsample(K, 4, 1)
     assert np.array_equal(f[:, 0::2], K) and np.array_equal(f[:, 1::2], K)
+
+
+# --------------------------------------------------------------------------
+# Far field: the reference Chebyshev FMM (oracle/fmm.py)
+# --------------------------------------------------------------------------
+def test_fmm_reference_exact_for_polynomial_kernel():
+    """H = |d|^2 is interpolated exactly from order 3 on, so near plus far field must
+    equal the exact sum: every pair counted once, none dropped or doubled."""
+    from oracle import fmm
+    X = inputs.radial_spokes(12, 40, 0.5, seed=51, jitter=0.05).T.copy()
+    k = fmm.square_kernel()
+    ge, ue = fmm.exact(X, k)
+    for depth, n in ((2, 3), (3, 3)):
+        g, u = fmm.fmm(X, depth, n, k)
+        assert np.abs(g - ge).max() <= 1e-10 * np.abs(ge).max(), (depth, n)
+        assert np.abs(u - ue).max() <= 1e-10 * np.abs(ue).max(), (depth, n)
+
+
+def test_fmm_reference_converges_to_the_exact_sum():
+    from oracle import fmm
+    X = inputs.radial_spokes(16, 60, 0.5, seed=52, jitter=0.05).T.copy()
+    k = fmm.distance_kernel()
+    ge, ue = fmm.exact(X, k)
+    err = []
+    for n in (3, 4, 6):
+        g, u = fmm.fmm(X, 2, n, k)
+        err.append(np.linalg.norm(g - ge) / np.linalg.norm(ge))
+    assert err[0] > err[1] > err[2]
+    assert err[2] < 1e-5 and err[1] < 3e-4
+    # the oracle's exact sums are the same sums
+    ref = oracle.grad(X.T, [0.0], 1, 0.5)
+    np.testing.assert_allclose(ref["dFr"] * X.shape[0] ** 2, ge.T, rtol=1e-12, atol=1e-12)
