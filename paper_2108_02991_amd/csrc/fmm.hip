@@ -41,7 +41,7 @@ namespace spk {
 namespace {
 
 constexpr int EW = 256;
-constexpr int kMaxOrder = 6;
+constexpr int kMaxOrder = kFmmMaxOrder;
 inline unsigned ew_blocks(int64_t n) { return (unsigned)((n + EW - 1) / EW); }
 
 // Host-computed Chebyshev tables passed by value: tb[i][k] = T_i(tbar_k).

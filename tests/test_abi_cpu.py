@@ -123,6 +123,24 @@ def test_unknown_precision_and_flags(lib):
     assert lib.spk_workspace_size(None, ctypes.byref(n)) == EINVAL
 
 
+def test_far_field_validation_and_workspace(lib):
+    n = ctypes.c_size_t()
+    base = spk.workspace_size(good_params())
+    sizes = []
+    for depth, order in ((2, 3), (3, 4), (4, 6)):
+        c = good_params(far_field_depth=depth, far_field_order=order).c()
+        assert lib.spk_workspace_size(ctypes.byref(c), ctypes.byref(n)) == 0
+        sizes.append(n.value)
+    assert base < sizes[0] < sizes[1] < sizes[2]
+    for bad, code in [(dict(far_field_depth=1), EINVAL), (dict(far_field_depth=8), EINVAL),
+                      (dict(far_field_depth=3, far_field_order=2), EINVAL),
+                      (dict(far_field_depth=3, far_field_order=7), EINVAL),
+                      (dict(far_field_depth=3, precision="fp32_naive"), EUNSUPPORTED),
+                      (dict(far_field_depth=3, precision="fp32_acc64"), EUNSUPPORTED)]:
+        c = good_params(**bad).c()
+        assert lib.spk_workspace_size(ctypes.byref(c), ctypes.byref(n)) == code, bad
+
+
 def test_log_kernel_validation(lib):
     n = ctypes.c_size_t()
     ok = good_params(kernel="log", eps=0.01).c()
