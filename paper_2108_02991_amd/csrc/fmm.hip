@@ -332,18 +332,46 @@ __global__ __launch_bounds__(EW) void m2m_kernel(Level par, Level chd, const dou
 }
 
 // ------------------------------------------------------------------ M2L tables
-// A[o][row][l], row = c*n^3 + m: K_c(x_m - y_l) with target nodes hl*tbar_m
-// (relative to the target centre) and source nodes o*h + hl*tbar_l.
+// The M2L kernels run on the FP64 matrix cores.  The table of level l holds,
+// for every offset o, A_o^T: At[o][k][row] = K_c(x_m - y_k), row = c*n^3 + m,
+// with target nodes hl*tbar_m (relative to the target centre) and source nodes
+// o*h + hl*tbar_k; rows are padded with zeros to a multiple of the row tile and
+// k to a multiple of the k tile, so tile loads need no bounds tests.
+#ifndef SPK_M2L_TN
+#define SPK_M2L_TN 64
+#endif
+#ifndef SPK_M2L_TK
+#define SPK_M2L_TK 16
+#endif
+constexpr int TM = 128, TN = SPK_M2L_TN, TK = SPK_M2L_TK;
+constexpr int kM2lThreads = 256, kXcds = 8, kOffsets = 343, kMaxList = 189;
+static_assert(TN == 64 || TN == 128, "column tile");
+static_assert(TK % 4 == 0 && (TK * TM) % (2 * kM2lThreads) == 0 &&
+              (TK * TN) % kM2lThreads == 0, "k tile");
+
+template <int N>
+struct M2lShape {
+    static constexpr int N3 = N * N * N, ROWS = 4 * N3;
+    static constexpr int RP = (ROWS + TM - 1) / TM * TM;  // padded rows
+    static constexpr int KP = (N3 + TK - 1) / TK * TK;    // padded k
+    static constexpr int KT = KP / TK;                    // k tiles per offset
+};
+
 template <int N, int KERN>
 __global__ __launch_bounds__(EW) void m2l_table_kernel(const double *box, int level, double eps,
-                                                       Cheb ch, double *A)
+                                                       Cheb ch, double *At)
 {
-    constexpr int N3 = N * N * N;
+    using S = M2lShape<N>;
+    constexpr int N3 = S::N3;
     const int64_t e = (int64_t)blockIdx.x * EW + threadIdx.x;
-    if (e >= (int64_t)343 * 4 * N3 * N3)
+    if (e >= (int64_t)kOffsets * S::KP * S::RP)
         return;
-    const int64_t o = e / (4 * N3 * N3);
-    const int row = (int)((e / N3) % (4 * N3)), l = (int)(e % N3);
+    const int64_t o = e / ((int64_t)S::KP * S::RP);
+    const int l = (int)((e / S::RP) % S::KP), row = (int)(e % S::RP);
+    if (row >= S::ROWS || l >= N3) {
+        At[e] = 0.0;
+        return;
+    }
     const int c = row / N3, m = row % N3;
     const int ov[3] = {(int)(o % 7) - 3, (int)((o / 7) % 7) - 3, (int)(o / 49) - 3};
     const int mi[3] = {m % N, (m / N) % N, m / (N * N)};
@@ -359,7 +387,7 @@ __global__ __launch_bounds__(EW) void m2l_table_kernel(const double *box, int le
         v = c < 3 ? d[c] / s : 0.5 * log(s);
     else
         v = c < 3 ? (s > 0.0 ? d[c] / sqrt(s) : 0.0) : sqrt(s);
-    A[e] = v;
+    At[e] = v;
 }
 
 // Offset o (|o_a| <= 3, linear index o = (ox+3) + 7(oy+3) + 49(oz+3)) is in the
@@ -383,111 +411,214 @@ __device__ inline bool in_list(int o, int ct)
     return !near;
 }
 
+// Source class and padded-index shift of offset o seen from target class ct.
+__device__ inline void offset_shift(int o, int ct, int64_t P, int &cs, int64_t &shift)
+{
+    const int ov[3] = {o % 7 - 3, (o / 7) % 7 - 3, o / 49 - 3};
+    cs = 0;
+    shift = 0;
+    int64_t mul = 1;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const int ca = (ct >> a) & 1;
+        const int sa = (ca + ov[a]) & 1;
+        cs |= sa << a;
+        shift += (int64_t)((ca + ov[a] - sa) / 2) * mul;
+        mul *= P;
+    }
+}
+
 // ------------------------------------------------------------------ M2L (GEMM)
 // Block (row tile, column tile, class ct): rows are (component, node) pairs,
-// columns the class's cells (Q^3 of them, Q = side/2) in sub-grid order.  The
-// block adds, offset by offset in a fixed order, A_o[rows][k] W[source][k]
-// into registers (8 x 4 per thread) and writes the tile once.  Tiles without
-// an occupied target cell are skipped (nothing reads the local expansion of
-// an empty cell), and so are offsets whose 64 source cells are all empty
-// (their weights are exact zeros).
-constexpr int TM = 128, TN = 64, TK = 8;
+// columns the class's cells (Q^3 of them, Q = side/2) in sub-grid order.  For
+// every offset of the interaction list, in increasing order, the block adds
+// A_o[rows][k] W[source][k] with v_mfma_f64_16x16x4 into accumulators held
+// by its four waves (wave w: rows 64 (w & 1) .., columns (TN/2)(w >> 1) ..),
+// and writes the tile once.  Tiles of TK k-values go through two LDS buffers:
+// the next tile is read from global memory into registers while the matrix
+// cores work on the current one.  Tiles without an occupied target cell are
+// skipped (nothing reads the local expansion of an empty cell), and so are
+// offsets whose TN source cells are all empty (their weights are exact zeros).
+// Blocks are renumbered so that consecutive tiles run on the same XCD, which
+// then shares the column tile's weights in its L2.
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+typedef double dbl2 __attribute__((ext_vector_type(2)));
+
 template <int N>
-__global__ __launch_bounds__(256) void m2l_kernel(Level lev, const double *A)
+__global__ __launch_bounds__(kM2lThreads) void m2l_kernel(Level lev, const double *At, int ntiles_r,
+                                                          int64_t ntiles_c, int64_t nblocks)
 {
-    constexpr int N3 = N * N * N, ROWS = 4 * N3;
-    __shared__ double As[TK][TM];
-    __shared__ double Bs[TK][TN + 1];
+    using S = M2lShape<N>;
+    constexpr int N3 = S::N3, ROWS = S::ROWS, RP = S::RP, KP = S::KP, KT = S::KT;
+    constexpr int FM = 4, FN = TN / 32;  // 16 x 16 fragments per wave
+    constexpr int BPAD = TN + 1;         // padded LDS row of the weights tile
+    __shared__ __align__(16) double As[2][TK][TM];
+    __shared__ __align__(16) double Bs[2][TK][BPAD];
     __shared__ int64_t colpad[TN];
+    __shared__ int64_t list_shift[kMaxList];
+    __shared__ int16_t list_o[kMaxList];
+    __shared__ int8_t list_cs[kMaxList];
+    __shared__ int8_t flag[kOffsets];
+    __shared__ int nlist;
+
+    // XCD-aware renumbering: hardware block b runs on XCD b % 8; logical block
+    // ids are consecutive within an XCD.
+    const int64_t b = blockIdx.x, q = nblocks / kXcds;
+    const int64_t lb = b < q * kXcds ? (b % kXcds) * q + b / kXcds : b;
+    const int rt = (int)(lb % ntiles_r);
+    const int64_t cti = (lb / ntiles_r) % ntiles_c;
+    const int ct = (int)(lb / (ntiles_r * ntiles_c));
+
     const int64_t P = lev.P, P3 = P * P * P, Q = lev.side / 2, Q3 = Q * Q * Q;
-    const int ct = blockIdx.z;
-    const int row0 = blockIdx.x * TM;
-    const int64_t c0 = (int64_t)blockIdx.y * TN;
-    const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+    const int row0 = rt * TM;
+    const int64_t c0 = cti * TN;
+    const int t = threadIdx.x, lane = t % 64, wave = t / 64;
     const int32_t *occ_t = lev.occ + (int64_t)ct * P3;
     int mine = 0;
-    if (threadIdx.x < TN) {
-        const int64_t c = c0 + threadIdx.x;
+    if (t < TN) {
+        const int64_t c = c0 + t;
         int64_t pc = -1;
         if (c < Q3) {
             const int64_t ux = c % Q, uy = (c / Q) % Q, uz = c / (Q * Q);
             pc = (ux + 2) + P * ((uy + 2) + P * (uz + 2));
             mine = occ_t[pc];
         }
-        colpad[threadIdx.x] = pc;
+        colpad[t] = pc;
     }
     if (!__syncthreads_or(mine))
         return;
-    double acc[8][4];
-#pragma unroll
-    for (int i = 0; i < 8; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-            acc[i][j] = 0.0;
-    for (int o = 0; o < 343; ++o) {
-        if (!in_list(o, ct))
-            continue;
-        const int ov[3] = {o % 7 - 3, (o / 7) % 7 - 3, o / 49 - 3};
-        int cs = 0;
-        int64_t shift = 0, mul = 1;
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            const int ca = (ct >> a) & 1;
-            const int sa = (ca + ov[a]) & 1;
-            cs |= sa << a;
-            shift += (int64_t)((ca + ov[a] - sa) / 2) * mul;
-            mul *= P;
+
+    // interaction list of this tile: offsets with an occupied source cell
+    for (int o = wave; o < kOffsets; o += kM2lThreads / 64) {
+        int any = 0;
+        if (in_list(o, ct)) {
+            int cs;
+            int64_t shift;
+            offset_shift(o, ct, P, cs, shift);
+            const int32_t *occ_s = lev.occ + (int64_t)cs * P3 + shift;
+            int v = 0;
+            for (int c = lane; c < TN; c += 64)
+                if (colpad[c] >= 0 && occ_s[colpad[c]])
+                    v = 1;
+            any = __ballot(v) != 0;
         }
-        const double *Bc = lev.W + (int64_t)cs * P3 * N3;
-        int src = 0;
-        if (threadIdx.x < TN && colpad[threadIdx.x] >= 0)
-            src = lev.occ[(int64_t)cs * P3 + colpad[threadIdx.x] + shift];
-        if (!__syncthreads_or(src))
-            continue;
-        const double *Ao = A + (int64_t)o * ROWS * N3;
-        for (int k0 = 0; k0 < N3; k0 += TK) {
-            for (int e = threadIdx.x; e < TM * TK; e += 256) {
-                const int r = e / TK, k = e % TK;
-                const int row = row0 + r, kk = k0 + k;
-                As[k][r] = (row < ROWS && kk < N3) ? Ao[(int64_t)row * N3 + kk] : 0.0;
-            }
-            for (int e = threadIdx.x; e < TN * TK; e += 256) {
-                const int cl = e / TK, k = e % TK;
-                const int64_t pc = colpad[cl];
-                const int kk = k0 + k;
-                Bs[k][cl] = (pc >= 0 && kk < N3) ? Bc[(pc + shift) * N3 + kk] : 0.0;
-            }
-            __syncthreads();
-#pragma unroll
-            for (int k = 0; k < TK; ++k) {
-                double a[8], b[4];
-#pragma unroll
-                for (int i = 0; i < 8; ++i)
-                    a[i] = As[k][ty * 8 + i];
-#pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    b[j] = Bs[k][tx * 4 + j];
-#pragma unroll
-                for (int i = 0; i < 8; ++i)
-#pragma unroll
-                    for (int j = 0; j < 4; ++j)
-                        acc[i][j] = fma(a[i], b[j], acc[i][j]);
-            }
-            __syncthreads();
-        }
+        if (lane == 0)
+            flag[o] = (int8_t)any;
     }
+    __syncthreads();
+    if (wave == 0) {
+        int base = 0;
+        for (int o0 = 0; o0 < kOffsets; o0 += 64) {
+            const int o = o0 + lane;
+            const int f = o < kOffsets && flag[o];
+            const unsigned long long mask = __ballot(f);
+            if (f) {
+                const int pos = base + __popcll(mask & ((1ull << lane) - 1ull));
+                int cs;
+                int64_t shift;
+                offset_shift(o, ct, P, cs, shift);
+                list_o[pos] = (int16_t)o;
+                list_cs[pos] = (int8_t)cs;
+                list_shift[pos] = shift;
+            }
+            base += __popcll(mask);
+        }
+        if (lane == 0)
+            nlist = base;
+    }
+    __syncthreads();
+    const int nit = nlist * KT;  // 0: no source, the tile's expansions are zero
+
+    // per-thread share of a tile: A as TK rows of TM (two doubles a piece),
+    // W as TN cells of TK values (k fastest)
+    constexpr int LA = TK * TM / (2 * kM2lThreads), LB = TK * TN / kM2lThreads;
+    dbl2 ra[LA];
+    double rb[LB];
+    auto load = [&](int it) {
+        const int a = it / KT, kt = it % KT;
+        const double *Ao = At + ((int64_t)list_o[a] * KP + kt * TK) * RP + row0;
+#pragma unroll
+        for (int i = 0; i < LA; ++i) {
+            const int e = t + kM2lThreads * i, k = e / (TM / 2), r = 2 * (e % (TM / 2));
+            ra[i] = *reinterpret_cast<const dbl2 *>(Ao + (int64_t)k * RP + r);
+        }
+        const double *Bc = lev.W + ((int64_t)list_cs[a] * P3 + list_shift[a]) * N3;
+#pragma unroll
+        for (int i = 0; i < LB; ++i) {
+            const int e = t + kM2lThreads * i, k = e % TK, cl = e / TK;
+            const int kk = kt * TK + k;
+            const int64_t pc = colpad[cl];
+            rb[i] = (pc >= 0 && kk < N3) ? Bc[pc * N3 + kk] : 0.0;
+        }
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+        for (int i = 0; i < LA; ++i) {
+            const int e = t + kM2lThreads * i, k = e / (TM / 2), r = 2 * (e % (TM / 2));
+            *reinterpret_cast<dbl2 *>(&As[buf][k][r]) = ra[i];
+        }
+#pragma unroll
+        for (int i = 0; i < LB; ++i) {
+            const int e = t + kM2lThreads * i, k = e % TK, cl = e / TK;
+            Bs[buf][k][cl] = rb[i];
+        }
+    };
+
+    dbl4 acc[FM][FN];
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+            acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
+    const int wr = (wave & 1) * 64, wc = (wave >> 1) * (TN / 2);
+    const int fr = lane % 16, fk = lane / 16;
+
+    if (nit > 0) {
+        load(0);
+        store(0);
+    }
+    __syncthreads();
+    for (int it = 0; it < nit; ++it) {
+        const int buf = it & 1;
+        if (it + 1 < nit)
+            load(it + 1);
+#pragma unroll
+        for (int k0 = 0; k0 < TK; k0 += 4) {
+            double a[FM], bb[FN];
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+                a[i] = As[buf][k0 + fk][wr + 16 * i + fr];
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+                bb[j] = Bs[buf][k0 + fk][wc + 16 * j + fr];
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+#pragma unroll
+                for (int j = 0; j < FN; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], bb[j], acc[i][j], 0,
+                                                                     0, 0);
+        }
+        if (it + 1 < nit)
+            store(buf ^ 1);
+        __syncthreads();
+    }
+
+    // accumulator layout of v_mfma_f64_16x16x4: register r of a lane holds row
+    // lane/16 + 4r of column lane % 16
     double *Cc = lev.L + (int64_t)ct * P3 * ROWS;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const int64_t pc = colpad[tx * 4 + j];
+    for (int j = 0; j < FN; ++j) {
+        const int64_t pc = colpad[wc + 16 * j + fr];
         if (pc < 0)
             continue;
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            const int row = row0 + ty * 8 + i;
-            if (row < ROWS)
-                Cc[pc * ROWS + row] = acc[i][j];
-        }
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = row0 + wr + 16 * i + fk + 4 * r;
+                if (row < ROWS)
+                    Cc[pc * ROWS + row] = acc[i][j][r];
+            }
     }
 }
 
@@ -571,6 +702,17 @@ size_t fmm_level_cells(int level)
     return (size_t)(8 * P * P * P);
 }
 
+size_t fmm_table_doubles(int order)
+{
+    switch (order) {
+    case 3: return (size_t)kOffsets * M2lShape<3>::KP * M2lShape<3>::RP;
+    case 4: return (size_t)kOffsets * M2lShape<4>::KP * M2lShape<4>::RP;
+    case 5: return (size_t)kOffsets * M2lShape<5>::KP * M2lShape<5>::RP;
+    case 6: return (size_t)kOffsets * M2lShape<6>::KP * M2lShape<6>::RP;
+    default: return 0;
+    }
+}
+
 size_t fmm_sort_temp_bytes(int64_t p, int depth)
 {
     const int64_t nleaves = int64_t(1) << (3 * depth);
@@ -651,7 +793,7 @@ hipError_t run_typed(const FmmLaunch &f, hipStream_t s)
                            lev[l], lev[l + 1], f.Tm);
     // interactions and the downward pass
     for (int l = 2; l <= f.depth; ++l) {
-        const int64_t ntab = (int64_t)343 * 4 * N3 * N3;
+        const int64_t ntab = (int64_t)kOffsets * M2lShape<N>::KP * M2lShape<N>::RP;
         if (f.kernel == kKernelLog)
             hipLaunchKernelGGL((m2l_table_kernel<N, kKernelLog>), dim3(ew_blocks(ntab)), dim3(EW),
                                0, s, f.box, l, f.eps, ch, f.A);
@@ -659,8 +801,10 @@ hipError_t run_typed(const FmmLaunch &f, hipStream_t s)
             hipLaunchKernelGGL((m2l_table_kernel<N, kKernelDistance>), dim3(ew_blocks(ntab)),
                                dim3(EW), 0, s, f.box, l, f.eps, ch, f.A);
         const int64_t Q = lev[l].side / 2, Q3 = Q * Q * Q;
-        dim3 grid((unsigned)((4 * N3 + TM - 1) / TM), (unsigned)((Q3 + TN - 1) / TN), 8);
-        hipLaunchKernelGGL(m2l_kernel<N>, grid, dim3(256), 0, s, lev[l], f.A);
+        const int ntr = M2lShape<N>::RP / TM;
+        const int64_t ntc = (Q3 + TN - 1) / TN, nbl = 8 * ntr * ntc;
+        hipLaunchKernelGGL(m2l_kernel<N>, dim3((unsigned)nbl), dim3(kM2lThreads), 0, s, lev[l],
+                           f.A, ntr, ntc, nbl);
         if (l >= 3)
             hipLaunchKernelGGL(l2l_kernel<N>, dim3((unsigned)(int64_t(1) << (3 * l))), dim3(EW),
                                0, s, lev[l - 1], lev[l], f.Tm);

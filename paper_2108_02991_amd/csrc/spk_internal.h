@@ -43,13 +43,14 @@ struct FmmLaunch {
     double *W[kFmmMaxDepth + 1] = {};     // level l: [8][P^3][order^3]
     int32_t *occ[kFmmMaxDepth + 1] = {};  // level l: [8][P^3]
     double *L[kFmmMaxDepth + 1] = {};     // level l: [8][P^3][4 order^3]
-    double *A = nullptr;                  // [343][4 order^3][order^3]
+    double *A = nullptr;                  // [343][k padded][rows padded]
     double *Tm = nullptr;                 // [8][order^3][order^3]
 };
 // Padded class side P and cell slots 8 P^3 of level l.
 int64_t fmm_padded_side(int level);
 size_t fmm_level_cells(int level);
 // Temporary bytes of the leaf sort (3 * depth key bits) and of the block-count scan.
+size_t fmm_table_doubles(int order);  // M2L table of one level, padded
 size_t fmm_sort_temp_bytes(int64_t p, int depth);
 hipError_t launch_fmm_repulsion(const FmmLaunch &f, hipStream_t s);
 
