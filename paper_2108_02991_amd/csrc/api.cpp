@@ -306,7 +306,7 @@ Layout make_layout(const spk_params *prm)
             L.fmm_L[l] = take(sizeof(double) * fmm_level_cells(l) * 4 * n3);
             L.fmm_occ[l] = take(sizeof(int32_t) * fmm_level_cells(l));
         }
-        L.fmm_A = take(sizeof(double) * fmm_table_doubles(prm->far_field_order));
+        L.fmm_A = take(sizeof(double) * fmm_table_doubles(prm->far_field_order) * (D - 1));
         L.fmm_Tm = take(sizeof(double) * 8 * n3 * n3);
     }
     L.total = off + 256;   // slack for aligning the caller's base pointer

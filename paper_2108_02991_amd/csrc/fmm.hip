@@ -248,12 +248,18 @@ __device__ inline int64_t slot(int64_t ix, int64_t iy, int64_t iz, int64_t P)
 }
 
 // ------------------------------------------------------------------ P2M
+// One block per leaf.  Batches of EW samples first evaluate their 3 N
+// one-dimensional interpolation polynomials (one sample per thread, into LDS);
+// then thread m adds S_mx(x_j) S_my(y_j) S_mz(z_j) over the batch, so each
+// node's weight is summed over the leaf's samples in sorted order.
 template <int N, typename T>
 __global__ __launch_bounds__(EW) void p2m_kernel(const T *xs, const T *ys, const T *zs,
                                                  const int32_t *start, const double *box,
                                                  int64_t side, Level lev, Cheb ch)
 {
     constexpr int N3 = N * N * N;
+    static_assert(N3 <= EW, "one thread per node");
+    __shared__ double S[EW][3 * N];
     const int64_t leaf = blockIdx.x;
     const int32_t j0 = start[leaf], j1 = start[leaf + 1];
     if (j0 == j1)
@@ -267,17 +273,35 @@ __global__ __launch_bounds__(EW) void p2m_kernel(const T *xs, const T *ys, const
     double *w = lev.W + slot(ix, iy, iz, lev.P) * N3;
     if (threadIdx.x == 0)
         lev.occ[slot(ix, iy, iz, lev.P)] = 1;
-    for (int m = threadIdx.x; m < N3; m += EW) {
-        const int mx = m % N, my = (m / N) % N, mz = m / (N * N);
-        double a = 0.0;
-        for (int32_t j = j0; j < j1; ++j) {
-            const double sx = cheb_s1<N>(ch, mx, ((double)xs[j] - cx) / hh);
-            const double sy = cheb_s1<N>(ch, my, ((double)ys[j] - cy) / hh);
-            const double sz = cheb_s1<N>(ch, mz, ((double)zs[j] - cz) / hh);
-            a += sx * sy * sz;
+    const int m = threadIdx.x;
+    const int mx = m % N, my = (m / N) % N, mz = m / (N * N);
+    double a = 0.0;
+    for (int32_t b = j0; b < j1; b += EW) {
+        const int32_t j = b + (int32_t)threadIdx.x;
+        if (j < j1) {
+            double sv[N];
+            cheb_s<N>(ch, ((double)xs[j] - cx) / hh, sv);
+#pragma unroll
+            for (int k = 0; k < N; ++k)
+                S[threadIdx.x][k] = sv[k];
+            cheb_s<N>(ch, ((double)ys[j] - cy) / hh, sv);
+#pragma unroll
+            for (int k = 0; k < N; ++k)
+                S[threadIdx.x][N + k] = sv[k];
+            cheb_s<N>(ch, ((double)zs[j] - cz) / hh, sv);
+#pragma unroll
+            for (int k = 0; k < N; ++k)
+                S[threadIdx.x][2 * N + k] = sv[k];
         }
-        w[m] = a;
+        __syncthreads();
+        const int cnt = j1 - b < EW ? (int)(j1 - b) : EW;
+        if (m < N3)
+            for (int q = 0; q < cnt; ++q)
+                a += S[q][mx] * S[q][N + my] * S[q][2 * N + mz];
+        __syncthreads();
     }
+    if (m < N3)
+        w[m] = a;
 }
 
 // T[pos][m][l] = prod_a S_{m_a}(u_a), u = child node l in the parent's frame.
@@ -439,14 +463,26 @@ __device__ inline void offset_shift(int o, int ct, int64_t P, int &cs, int64_t &
 // cores work on the current one.  Tiles without an occupied target cell are
 // skipped (nothing reads the local expansion of an empty cell), and so are
 // offsets whose TN source cells are all empty (their weights are exact zeros).
-// Blocks are renumbered so that consecutive tiles run on the same XCD, which
-// then shares the column tile's weights in its L2.
+// One launch covers every level (level 2's blocks first): the levels' M2L
+// steps are independent, and the few blocks of the coarse levels then run
+// beside the many of the finest.  Blocks are renumbered so that consecutive
+// tiles run on the same XCD, which then shares the column tile's weights in
+// its L2.
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 typedef double dbl2 __attribute__((ext_vector_type(2)));
 
+constexpr int kMaxLevels = kFmmMaxDepth - 1;  // levels 2..depth
+struct M2lPlan {
+    Level lev[kMaxLevels];
+    const double *At[kMaxLevels];  // table of each level
+    int64_t ntc[kMaxLevels];       // column tiles of each level
+    int64_t first[kMaxLevels];     // first block of each level
+    int nlev, ntr;
+    int64_t nblocks;
+};
+
 template <int N>
-__global__ __launch_bounds__(kM2lThreads) void m2l_kernel(Level lev, const double *At, int ntiles_r,
-                                                          int64_t ntiles_c, int64_t nblocks)
+__global__ __launch_bounds__(kM2lThreads) void m2l_kernel(M2lPlan plan)
 {
     using S = M2lShape<N>;
     constexpr int N3 = S::N3, ROWS = S::ROWS, RP = S::RP, KP = S::KP, KT = S::KT;
@@ -463,8 +499,22 @@ __global__ __launch_bounds__(kM2lThreads) void m2l_kernel(Level lev, const doubl
 
     // XCD-aware renumbering: hardware block b runs on XCD b % 8; logical block
     // ids are consecutive within an XCD.
-    const int64_t b = blockIdx.x, q = nblocks / kXcds;
-    const int64_t lb = b < q * kXcds ? (b % kXcds) * q + b / kXcds : b;
+    const int64_t b = blockIdx.x, q = plan.nblocks / kXcds;
+    int64_t lb = b < q * kXcds ? (b % kXcds) * q + b / kXcds : b;
+    // the block's level (a select, not an index, keeps the plan in SGPRs)
+    Level lev = plan.lev[0];
+    const double *At = plan.At[0];
+    int64_t ntiles_c = plan.ntc[0], lfirst = 0;
+#pragma unroll
+    for (int i = 1; i < kMaxLevels; ++i)
+        if (i < plan.nlev && lb >= plan.first[i]) {
+            lev = plan.lev[i];
+            At = plan.At[i];
+            ntiles_c = plan.ntc[i];
+            lfirst = plan.first[i];
+        }
+    lb -= lfirst;
+    const int ntiles_r = plan.ntr;
     const int rt = (int)(lb % ntiles_r);
     const int64_t cti = (lb / ntiles_r) % ntiles_c;
     const int ct = (int)(lb / (ntiles_r * ntiles_c));
@@ -791,24 +841,32 @@ hipError_t run_typed(const FmmLaunch &f, hipStream_t s)
     for (int l = f.depth - 1; l >= 2; --l)
         hipLaunchKernelGGL(m2m_kernel<N>, dim3((unsigned)(int64_t(1) << (3 * l))), dim3(EW), 0, s,
                            lev[l], lev[l + 1], f.Tm);
-    // interactions and the downward pass
+    // interactions (every level in one launch), then the downward pass
+    const int64_t ntab = (int64_t)kOffsets * M2lShape<N>::KP * M2lShape<N>::RP;
+    M2lPlan plan{};
+    plan.nlev = f.depth - 1;
+    plan.ntr = M2lShape<N>::RP / TM;
+    plan.nblocks = 0;
     for (int l = 2; l <= f.depth; ++l) {
-        const int64_t ntab = (int64_t)kOffsets * M2lShape<N>::KP * M2lShape<N>::RP;
+        double *At = f.A + (l - 2) * ntab;
         if (f.kernel == kKernelLog)
             hipLaunchKernelGGL((m2l_table_kernel<N, kKernelLog>), dim3(ew_blocks(ntab)), dim3(EW),
-                               0, s, f.box, l, f.eps, ch, f.A);
+                               0, s, f.box, l, f.eps, ch, At);
         else
             hipLaunchKernelGGL((m2l_table_kernel<N, kKernelDistance>), dim3(ew_blocks(ntab)),
-                               dim3(EW), 0, s, f.box, l, f.eps, ch, f.A);
+                               dim3(EW), 0, s, f.box, l, f.eps, ch, At);
         const int64_t Q = lev[l].side / 2, Q3 = Q * Q * Q;
-        const int ntr = M2lShape<N>::RP / TM;
-        const int64_t ntc = (Q3 + TN - 1) / TN, nbl = 8 * ntr * ntc;
-        hipLaunchKernelGGL(m2l_kernel<N>, dim3((unsigned)nbl), dim3(kM2lThreads), 0, s, lev[l],
-                           f.A, ntr, ntc, nbl);
-        if (l >= 3)
-            hipLaunchKernelGGL(l2l_kernel<N>, dim3((unsigned)(int64_t(1) << (3 * l))), dim3(EW),
-                               0, s, lev[l - 1], lev[l], f.Tm);
+        const int i = l - 2;
+        plan.lev[i] = lev[l];
+        plan.At[i] = At;
+        plan.ntc[i] = (Q3 + TN - 1) / TN;
+        plan.first[i] = plan.nblocks;
+        plan.nblocks += 8 * plan.ntr * plan.ntc[i];
     }
+    hipLaunchKernelGGL(m2l_kernel<N>, dim3((unsigned)plan.nblocks), dim3(kM2lThreads), 0, s, plan);
+    for (int l = 3; l <= f.depth; ++l)
+        hipLaunchKernelGGL(l2l_kernel<N>, dim3((unsigned)(int64_t(1) << (3 * l))), dim3(EW), 0, s,
+                           lev[l - 1], lev[l], f.Tm);
     if ((e = hipGetLastError()) != hipSuccess)
         return e;
     // near field (exact pair sums over the 27 leaves around each leaf), then far field

@@ -43,7 +43,7 @@ struct FmmLaunch {
     double *W[kFmmMaxDepth + 1] = {};     // level l: [8][P^3][order^3]
     int32_t *occ[kFmmMaxDepth + 1] = {};  // level l: [8][P^3]
     double *L[kFmmMaxDepth + 1] = {};     // level l: [8][P^3][4 order^3]
-    double *A = nullptr;                  // [343][k padded][rows padded]
+    double *A = nullptr;                  // [depth-1][343][k padded][rows padded]
     double *Tm = nullptr;                 // [8][order^3][order^3]
 };
 // Padded class side P and cell slots 8 P^3 of level l.
