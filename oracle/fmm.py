@@ -20,7 +20,10 @@ as its precision parameter), step by step in its textbook order:
 * downward pass: children add their parent's expansion interpolated at their
   nodes; every sample adds its leaf's expansion interpolated at itself;
 * near field: every sample sums the kernel exactly over the samples of the
-  27 leaves around its leaf (itself included).
+  27 leaves around its leaf (itself included);
+* adaptive tree (optional): leaves whose near field is dense enough
+  (refined_leaves) take their targets one level deeper, where the same steps
+  apply to them.
 
 S_k(t) = 1/n + (2/n) sum_{i=1}^{n-1} T_i(tbar_k) T_i(t), tbar_k = cos((2k+1) pi
 / 2n).  Parity unpinned except by the pins in the tests (exactness for
@@ -75,20 +78,64 @@ def square_kernel():
 
 
 def exact(X, kernel):
-    """(g (p, 3), u (p,)): sum over all j of grad H(x_i - x_j) and H(x_i - x_j)."""
-    u, g = kernel(X[:, None, :] - X[None, :, :])
-    return g.sum(axis=1), u.sum(axis=1)
+    """(g (p, 3), u (p,)): sum over all j of grad H(x_i - x_j) and H(x_i - x_j)
+    (rows in blocks, to bound the memory of the pair arrays)."""
+    g = np.empty((X.shape[0], 3))
+    u = np.empty(X.shape[0])
+    for a in range(0, X.shape[0], 1024):
+        uu, gg = kernel(X[a:a + 1024, None, :] - X[None, :, :])
+        g[a:a + 1024] = gg.sum(axis=1)
+        u[a:a + 1024] = uu.sum(axis=1)
+    return g, u
 
 
-def fmm(X, depth, n, kernel):
-    """Repulsion sums of every sample by the Chebyshev FMM; X is (p, 3)."""
+def refine_threshold(n):
+    """Price of refining one leaf, in direct pairs: 8 children x 189
+    interactions x 4 components x n^6 multiply-adds at 1/7 of a pair each."""
+    return 8 * 189 * 4 * n ** 6 // 7
+
+
+def _around(counts):
+    """Sum of counts over the (existing) 27 cells around every cell."""
+    N = counts.shape[0]
+    pad = np.zeros((N + 2,) * 3, dtype=np.int64)
+    pad[1:-1, 1:-1, 1:-1] = counts
+    out = np.zeros_like(counts)
+    for o in itertools.product((0, 1, 2), repeat=3):
+        out += pad[o[0]:o[0] + N, o[1]:o[1] + N, o[2]:o[2] + N]
+    return out
+
+
+def refined_leaves(leaf, fine, depth, n):
+    """Adaptive tree: leaves (depth `depth`) whose targets take their near
+    field one level deeper.  A leaf is refined when the direct pairs this saves,
+    n_L * (samples around L) - sum over children c of n_c * (samples around c),
+    exceed refine_threshold(n); exact integers."""
+    N = 2 ** depth
+    cL = np.zeros((N, N, N), dtype=np.int64)
+    np.add.at(cL, (leaf[:, 0], leaf[:, 1], leaf[:, 2]), 1)
+    cF = np.zeros((2 * N,) * 3, dtype=np.int64)
+    np.add.at(cF, (fine[:, 0], fine[:, 1], fine[:, 2]), 1)
+    coarse = cL * _around(cL)
+    fine_pairs = (cF * _around(cF)).reshape(N, 2, N, 2, N, 2).sum(axis=(1, 3, 5))
+    return (cL > 0) & (coarse - fine_pairs > refine_threshold(n))
+
+
+def fmm(X, depth, n, kernel, adaptive=False, info=None):
+    """Repulsion sums of every sample by the Chebyshev FMM; X is (p, 3).
+
+    adaptive: the tree goes one level deeper (depth + 1) for the targets of
+    refined leaves (refined_leaves): their local expansion comes from that
+    level (its interactions included) and their near field from the 27 cells
+    of that level around them.  Every other target is treated as in the
+    uniform tree of the given depth.  info (a dict) receives the refine flags.
+    """
     X = np.asarray(X, dtype=np.float64)
     p = X.shape[0]
     lo, hi = X.min(axis=0), X.max(axis=0)
     c0 = 0.5 * (lo + hi)
     R = (0.5 * (hi - lo)).max() * (1.0 + 2.0 ** -20) + 1e-30
-    N = 2 ** depth
-    leaf = np.clip(np.floor((X - (c0 - R)) / (2 * R / N)).astype(np.int64), 0, N - 1)
+    F = depth + 1 if adaptive else depth                 # deepest level
     tb = cheb_nodes(n)
     n3 = n ** 3
     m = np.arange(n3)
@@ -102,23 +149,39 @@ def fmm(X, depth, n, kernel):
         h = 2 * R / 2 ** level
         return c0 - R + (np.asarray(cell) + 0.5) * h, 0.5 * h
 
-    # upward pass
-    W = {depth: np.zeros((N, N, N, n3))}
-    cc, hh = centre(depth, leaf)
-    np.add.at(W[depth], (leaf[:, 0], leaf[:, 1], leaf[:, 2]), Sm((X - cc) / hh).T)
+    def cell_of(level):
+        Nl = 2 ** level
+        return np.clip(np.floor((X - (c0 - R)) / (2 * R / Nl)).astype(np.int64), 0, Nl - 1)
+
+    leaf = cell_of(depth)
+    fine = cell_of(F)
+    ref = np.zeros(p, dtype=bool)
+    if adaptive:
+        rl = refined_leaves(leaf, fine, depth, n)
+        ref = rl[leaf[:, 0], leaf[:, 1], leaf[:, 2]]
+        if info is not None:
+            info["refined_leaves"] = rl
+    if info is not None:
+        info["refined_targets"] = ref
+
+    # upward pass from the deepest level
+    NF = 2 ** F
+    W = {F: np.zeros((NF, NF, NF, n3))}
+    cc, hh = centre(F, fine)
+    np.add.at(W[F], (fine[:, 0], fine[:, 1], fine[:, 2]), Sm((X - cc) / hh).T)
     T = np.zeros((8, n3, n3))                                            # [pos, parent m, child l]
     for pos in range(8):
         b = np.array([pos & 1, (pos >> 1) & 1, (pos >> 2) & 1])
         T[pos] = Sm((-0.5 + b[None, :]) + 0.5 * tb[m3])
-    for lvl in range(depth - 1, 1, -1):
+    for lvl in range(F - 1, 1, -1):
         Nl = 2 ** lvl
         W[lvl] = np.zeros((Nl, Nl, Nl, n3))
         for pos in range(8):
             b = [pos & 1, (pos >> 1) & 1, (pos >> 2) & 1]
             W[lvl] += W[lvl + 1][b[0]::2, b[1]::2, b[2]::2] @ T[pos].T
     # interactions
-    Lx = {lvl: np.zeros((2 ** lvl,) * 3 + (4, n3)) for lvl in range(2, depth + 1)}
-    for lvl in range(2, depth + 1):
+    Lx = {lvl: np.zeros((2 ** lvl,) * 3 + (4, n3)) for lvl in range(2, F + 1)}
+    for lvl in range(2, F + 1):
         Nl = 2 ** lvl
         h = 2 * R / Nl
         cells = np.stack(np.meshgrid(*(np.arange(Nl),) * 3, indexing="ij"), -1).reshape(-1, 3)
@@ -139,22 +202,33 @@ def fmm(X, depth, n, kernel):
             w = W[lvl][s_[:, 0], s_[:, 1], s_[:, 2]]                       # (k, l)
             Lx[lvl][t[:, 0], t[:, 1], t[:, 2]] += np.einsum("cml,kl->kcm", Kc, w)
     # downward pass
-    for lvl in range(2, depth):
+    for lvl in range(2, F):
         for pos in range(8):
             b = [pos & 1, (pos >> 1) & 1, (pos >> 2) & 1]
             Lx[lvl + 1][b[0]::2, b[1]::2, b[2]::2] += Lx[lvl] @ T[pos]
-    far = np.einsum("pcm,mp->pc", Lx[depth][leaf[:, 0], leaf[:, 1], leaf[:, 2]],
-                    Sm((X - cc) / hh))
+    far = np.zeros((p, 4))
+    for level, cellv, sel in ((depth, leaf, ~ref), (F, fine, ref)):
+        if not sel.any():
+            continue
+        cs, hs = centre(level, cellv[sel])
+        far[sel] = np.einsum("pcm,mp->pc",
+                             Lx[level][cellv[sel, 0], cellv[sel, 1], cellv[sel, 2]],
+                             Sm((X[sel] - cs) / hs))
     g = far[:, :3].copy()
     u = far[:, 3].copy()
-    # near field
-    members = {}
-    for i, key in enumerate(map(tuple, leaf)):
-        members.setdefault(key, []).append(i)
-    for key, tgt in members.items():
-        src = [j for o in itertools.product((-1, 0, 1), repeat=3)
-               for j in members.get(tuple(np.array(key) + o), [])]
-        uu, gg = kernel(X[tgt][:, None, :] - X[src][None, :, :])
-        g[tgt] += gg.sum(axis=1)
-        u[tgt] += uu.sum(axis=1)
+    # near field: the 27 leaves around each target's leaf, or, for the targets
+    # of refined leaves, the 27 cells one level deeper around their cell
+    for cellv, sel in ((leaf, ~ref), (fine, ref)):
+        members = {}
+        for i, key in enumerate(map(tuple, cellv)):
+            members.setdefault(key, []).append(i)
+        targets = {}
+        for i in np.flatnonzero(sel):
+            targets.setdefault(tuple(cellv[i]), []).append(i)
+        for key, tgt in targets.items():
+            src = [j for o in itertools.product((-1, 0, 1), repeat=3)
+                   for j in members.get(tuple(np.array(key) + o), [])]
+            uu, gg = kernel(X[tgt][:, None, :] - X[src][None, :, :])
+            g[tgt] += gg.sum(axis=1)
+            u[tgt] += uu.sum(axis=1)
     return g, u

@@ -32,7 +32,8 @@ class SpkParams(ctypes.Structure):
     _fields_ = [("n_shots", _i64), ("n_samples", _i64), ("grid", _i64), ("precision", _i32),
                 ("te_index", _i32), ("half_width", _dbl), ("eps", _dbl), ("a_max", _dbl),
                 ("b_max", _dbl), ("n_pit", _i32), ("flags", _i32), ("attraction_field", _vp),
-                ("far_field_depth", _i32), ("far_field_order", _i32)]
+                ("far_field_depth", _i32), ("far_field_order", _i32),
+                ("far_field_adaptive", _i32)]
 
 
 class SpkStepInfo(ctypes.Structure):
@@ -112,6 +113,7 @@ class Params:
     attraction_field: "torch.Tensor | None" = None   # from attraction_field(); None = direct sum
     far_field_depth: int = 0                         # 0: exact repulsion; 2..7: octree depth
     far_field_order: int = 5                         # Chebyshev nodes per axis (3..6)
+    far_field_adaptive: bool = False                 # refine dense leaves once more
     _c: SpkParams = field(default=None, repr=False, compare=False)
 
     @property
@@ -135,7 +137,8 @@ class Params:
                          | (FLAG_ROTATION_VARIANT if self.rotation_variant else 0)
                          | KERNELS[self.kernel],
                          _vp(f.data_ptr()) if f is not None else None,
-                         self.far_field_depth, self.far_field_order if self.far_field_depth else 0)
+                         self.far_field_depth, self.far_field_order if self.far_field_depth else 0,
+                         int(bool(self.far_field_adaptive)))
 
 
 def lipschitz_bound(p: int, eps: float, rho_mass: float = 1.0, kernel: str = "distance") -> float:

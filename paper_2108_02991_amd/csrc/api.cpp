@@ -155,6 +155,13 @@ int check_params(const spk_params *prm, bool need_projection)
         if (prm->precision != SPK_PLAIN_FP64 && prm->precision != SPK_FP32_COMP)
             return fail(SPK_EUNSUPPORTED, "the far field runs in the plain_fp64 and fp32_comp "
                                           "forms only");
+        if (prm->far_field_adaptive != 0 && prm->far_field_adaptive != 1)
+            return fail(SPK_EINVAL, "far_field_adaptive must be 0 or 1");
+        if (prm->far_field_adaptive && prm->far_field_depth > kFmmMaxDepth - 1)
+            return fail(SPK_EINVAL, "an adaptive far field needs far_field_depth <= %d",
+                        kFmmMaxDepth - 1);
+    } else if (prm->far_field_adaptive != 0) {
+        return fail(SPK_EINVAL, "far_field_adaptive needs far_field_depth > 0");
     }
     if (prm->attraction_field &&
         reinterpret_cast<uintptr_t>(prm->attraction_field) % (4 * elt_size(prm->precision)))
@@ -232,7 +239,9 @@ struct Layout {
     // far field (only with far_field_depth > 0)
     size_t fmm_box_part = 0, fmm_box = 0, fmm_keys_in = 0, fmm_keys_out = 0, fmm_vals_in = 0,
            fmm_vals_out = 0, fmm_xs = 0, fmm_start = 0, fmm_chunks = 0, fmm_chunk_start = 0,
-           fmm_temp = 0, fmm_temp_bytes = 0, fmm_A = 0, fmm_Tm = 0;
+           fmm_temp = 0, fmm_temp_bytes = 0, fmm_A = 0, fmm_Tm = 0, fmm_chunks_fine = 0,
+           fmm_chunk_start_fine = 0, fmm_refined = 0, fmm_tmask_fine = 0, fmm_tflag = 0,
+           fmm_tscan = 0, fmm_tlist = 0;
     size_t fmm_W[kFmmMaxDepth + 1] = {}, fmm_L[kFmmMaxDepth + 1] = {},
            fmm_occ[kFmmMaxDepth + 1] = {};
     size_t total = 0;
@@ -287,8 +296,9 @@ Layout make_layout(const spk_params *prm)
     L.chunk_sums = take(sizeof(double) * ((M + kGridTargetChunk - 1) / kGridTargetChunk));
     if (prm->far_field_depth > 0) {
         const int D = prm->far_field_depth, n = prm->far_field_order;
+        const int F = prm->far_field_adaptive ? D + 1 : D;   // deepest level
         const size_t n3 = (size_t)n * n * n;
-        const int64_t nleaves = int64_t(1) << (3 * D);
+        const int64_t nleaves = int64_t(1) << (3 * D), ncells = int64_t(1) << (3 * F);
         L.fmm_box_part = take(sizeof(double) * 6 * kFmmBoxBlocks);
         L.fmm_box = take(sizeof(double) * 4);
         L.fmm_keys_in = take(sizeof(uint32_t) * p);
@@ -296,17 +306,26 @@ Layout make_layout(const spk_params *prm)
         L.fmm_vals_in = take(sizeof(uint32_t) * p);
         L.fmm_vals_out = take(sizeof(uint32_t) * p);
         L.fmm_xs = take(elt_size(prm->precision) * 3 * p);
-        L.fmm_start = take(sizeof(int32_t) * (nleaves + 1));
+        L.fmm_start = take(sizeof(int32_t) * (ncells + 1));
         L.fmm_chunks = take(sizeof(int32_t) * (nleaves + 1));
         L.fmm_chunk_start = take(sizeof(int32_t) * (nleaves + 1));
-        L.fmm_temp_bytes = fmm_sort_temp_bytes(p, D);
+        if (F > D) {
+            L.fmm_chunks_fine = take(sizeof(int32_t) * (ncells + 1));
+            L.fmm_chunk_start_fine = take(sizeof(int32_t) * (ncells + 1));
+            L.fmm_refined = take(sizeof(int32_t) * nleaves);
+            L.fmm_tmask_fine = take(sizeof(int32_t) * fmm_level_cells(F));
+            L.fmm_tflag = take(sizeof(int32_t) * (ncells + 1));
+            L.fmm_tscan = take(sizeof(int32_t) * (ncells + 1));
+            L.fmm_tlist = take(sizeof(int32_t) * ncells);
+        }
+        L.fmm_temp_bytes = fmm_sort_temp_bytes(p, F);
         L.fmm_temp = take(L.fmm_temp_bytes);
-        for (int l = 2; l <= D; ++l) {
+        for (int l = 2; l <= F; ++l) {
             L.fmm_W[l] = take(sizeof(double) * fmm_level_cells(l) * n3);
             L.fmm_L[l] = take(sizeof(double) * fmm_level_cells(l) * 4 * n3);
             L.fmm_occ[l] = take(sizeof(int32_t) * fmm_level_cells(l));
         }
-        L.fmm_A = take(sizeof(double) * fmm_table_doubles(prm->far_field_order) * (D - 1));
+        L.fmm_A = take(sizeof(double) * fmm_table_doubles(prm->far_field_order) * (F - 1));
         L.fmm_Tm = take(sizeof(double) * 8 * n3 * n3);
     }
     L.total = off + 256;   // slack for aligning the caller's base pointer
@@ -419,6 +438,7 @@ int run_far_field(const spk_params *prm, const void *kx, const void *ky, const v
     f.energy = energy;
     f.depth = prm->far_field_depth;
     f.order = prm->far_field_order;
+    f.adaptive = prm->far_field_adaptive != 0;
     f.x = kx;
     f.y = ky;
     f.z = kz;
@@ -443,9 +463,18 @@ int run_far_field(const spk_params *prm, const void *kx, const void *ky, const v
     f.start = w.at<int32_t>(L.fmm_start);
     f.chunks = w.at<int32_t>(L.fmm_chunks);
     f.chunk_start = w.at<int32_t>(L.fmm_chunk_start);
+    if (f.adaptive) {
+        f.chunks_fine = w.at<int32_t>(L.fmm_chunks_fine);
+        f.chunk_start_fine = w.at<int32_t>(L.fmm_chunk_start_fine);
+        f.refined = w.at<int32_t>(L.fmm_refined);
+        f.tmask_fine = w.at<int32_t>(L.fmm_tmask_fine);
+        f.tflag = w.at<int32_t>(L.fmm_tflag);
+        f.tscan = w.at<int32_t>(L.fmm_tscan);
+        f.tlist = w.at<int32_t>(L.fmm_tlist);
+    }
     f.temp = w.at<char>(L.fmm_temp);
     f.temp_bytes = L.fmm_temp_bytes;
-    for (int l = 2; l <= f.depth; ++l) {
+    for (int l = 2; l <= f.depth + (f.adaptive ? 1 : 0); ++l) {
         f.W[l] = w.at<double>(L.fmm_W[l]);
         f.L[l] = w.at<double>(L.fmm_L[l]);
         f.occ[l] = w.at<int32_t>(L.fmm_occ[l]);

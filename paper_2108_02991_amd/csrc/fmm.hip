@@ -151,9 +151,36 @@ __device__ inline int64_t leaf_coord(double x, double c, double R, int64_t N)
     return (int64_t)k;
 }
 
+// Cell numbering at the deepest level (N cells per axis): x fastest, or, with
+// fine set, (parent, child) = 8 (x-fastest parent index) + (cx + 2 cy + 4 cz),
+// which keeps every parent's samples contiguous.
+__device__ inline int64_t cell_key(int64_t ix, int64_t iy, int64_t iz, int64_t N, bool fine)
+{
+    if (!fine)
+        return ix + N * (iy + N * iz);
+    const int64_t ps = N >> 1;
+    return ((ix >> 1) + ps * ((iy >> 1) + ps * (iz >> 1))) * 8 +
+           ((ix & 1) | ((iy & 1) << 1) | ((iz & 1) << 2));
+}
+
+__device__ inline void cell_coords(int64_t k, int64_t N, bool fine, int64_t &ix, int64_t &iy,
+                                   int64_t &iz)
+{
+    if (!fine) {
+        ix = k % N;
+        iy = (k / N) % N;
+        iz = k / (N * N);
+        return;
+    }
+    const int64_t ps = N >> 1, par = k >> 3, ch = k & 7;
+    ix = 2 * (par % ps) + (ch & 1);
+    iy = 2 * ((par / ps) % ps) + ((ch >> 1) & 1);
+    iz = 2 * (par / (ps * ps)) + (ch >> 2);
+}
+
 template <typename T>
 __global__ __launch_bounds__(EW) void leaf_keys_kernel(const T *x, const T *y, const T *z, int64_t p,
-                                                       const double *box, int64_t N,
+                                                       const double *box, int64_t N, bool fine,
                                                        uint32_t *key, uint32_t *val)
 {
     const int64_t i = (int64_t)blockIdx.x * EW + threadIdx.x;
@@ -163,7 +190,7 @@ __global__ __launch_bounds__(EW) void leaf_keys_kernel(const T *x, const T *y, c
     const int64_t ix = leaf_coord((double)x[i], box[0], R, N);
     const int64_t iy = leaf_coord((double)y[i], box[1], R, N);
     const int64_t iz = leaf_coord((double)z[i], box[2], R, N);
-    key[i] = (uint32_t)(ix + N * (iy + N * iz));
+    key[i] = (uint32_t)cell_key(ix, iy, iz, N, fine);
     val[i] = (uint32_t)i;
 }
 
@@ -199,14 +226,71 @@ __global__ __launch_bounds__(EW) void leaf_bounds_kernel(const uint32_t *ks, int
     start[k] = (int32_t)lo;
 }
 
-// chunks[k] = ceil(count_k / tpb) for k < nleaves, chunks[nleaves] = 0.
-__global__ __launch_bounds__(EW) void leaf_chunks_kernel(const int32_t *start, int64_t nleaves,
-                                                         int tpb, int32_t *chunks)
+// Near-field target chunks: chunks[k] = ceil(count_k / tpb) for the cells k <
+// ncells whose samples are targets of this near field, else 0; chunks[ncells]
+// = 0.  Cell k owns [start[stride k], start[stride (k+1)]).  With a refine
+// flag array, cell k is a target cell when refined[k >> shift] equals want.
+__global__ __launch_bounds__(EW) void leaf_chunks_kernel(const int32_t *start, int64_t ncells,
+                                                         int64_t stride, int tpb,
+                                                         const int32_t *refined, int shift,
+                                                         bool want, int32_t *chunks)
 {
     const int64_t k = (int64_t)blockIdx.x * EW + threadIdx.x;
-    if (k > nleaves)
+    if (k > ncells)
         return;
-    chunks[k] = k < nleaves ? (start[k + 1] - start[k] + tpb - 1) / tpb : 0;
+    int32_t c = 0;
+    if (k < ncells && (!refined || (refined[k >> shift] != 0) == want))
+        c = (start[stride * (k + 1)] - start[stride * k] + tpb - 1) / tpb;
+    chunks[k] = c;
+}
+
+// Refinement of the base leaves (adaptive tree; samples sorted by (leaf,
+// child)).  A leaf is refined when the direct pairs its targets save by taking
+// their near field over the 27 children-level cells around each child instead
+// of the 27 leaves around the leaf exceed the threshold, a price for the
+// children-level interactions in units of pairs.  Counts are exact integers.
+__global__ __launch_bounds__(EW) void refine_kernel(const int32_t *start, int64_t side,
+                                                    int64_t threshold, int32_t *refined)
+{
+    const int64_t leaf = (int64_t)blockIdx.x * EW + threadIdx.x;
+    if (leaf >= side * side * side)
+        return;
+    const int64_t ix = leaf % side, iy = (leaf / side) % side, iz = leaf / (side * side);
+    const int64_t n = (int64_t)start[8 * (leaf + 1)] - start[8 * leaf];
+    int32_t r = 0;
+    if (n > 0) {
+        int64_t around = 0;
+        for (int64_t z = iz - 1; z <= iz + 1; ++z)
+            for (int64_t y = iy - 1; y <= iy + 1; ++y) {
+                if (y < 0 || y >= side || z < 0 || z >= side)
+                    continue;
+                const int64_t x0 = ix > 0 ? ix - 1 : 0, x1 = ix + 1 < side ? ix + 1 : side - 1;
+                const int64_t row = side * (y + side * z);
+                around += (int64_t)start[8 * (x1 + row + 1)] - start[8 * (x0 + row)];
+            }
+        const int64_t N = 2 * side;
+        int64_t fine_pairs = 0;
+        for (int ch = 0; ch < 8; ++ch) {
+            const int64_t cx = 2 * ix + (ch & 1), cy = 2 * iy + ((ch >> 1) & 1),
+                          cz = 2 * iz + (ch >> 2);
+            const int64_t k = leaf * 8 + ch;
+            const int64_t nc = (int64_t)start[k + 1] - start[k];
+            if (nc == 0)
+                continue;
+            int64_t a = 0;
+            for (int64_t z = cz - 1; z <= cz + 1; ++z)
+                for (int64_t y = cy - 1; y <= cy + 1; ++y)
+                    for (int64_t x = cx - 1; x <= cx + 1; ++x) {
+                        if (x < 0 || x >= N || y < 0 || y >= N || z < 0 || z >= N)
+                            continue;
+                        const int64_t kk = cell_key(x, y, z, N, true);
+                        a += (int64_t)start[kk + 1] - start[kk];
+                    }
+            fine_pairs += nc * a;
+        }
+        r = n * around - fine_pairs > threshold ? 1 : 0;
+    }
+    refined[leaf] = r;
 }
 
 __global__ __launch_bounds__(EW) void fill_kernel(double *a, int64_t n)
@@ -230,6 +314,12 @@ struct Level {
     double *W;      // [8][P^3][n^3]
     double *L;      // [8][P^3][4 n^3]
     int32_t *occ;   // [8][P^3]: 1 if the cell holds samples (padding 0)
+    int32_t *tmask; // [8][P^3]: 1 if the cell's local expansion is used (occ, or
+                    // at the refined level, occ and a refined parent)
+    // Refined level only (else null): the tmask cells of each class as a list
+    // of padded indices, class ct's at [tscan[ct Q^3], tscan[(ct+1) Q^3]).
+    const int32_t *tlist;
+    const int32_t *tscan;
 };
 
 __device__ inline int64_t class_of(int64_t ix, int64_t iy, int64_t iz)
@@ -255,7 +345,7 @@ __device__ inline int64_t slot(int64_t ix, int64_t iy, int64_t iz, int64_t P)
 template <int N, typename T>
 __global__ __launch_bounds__(EW) void p2m_kernel(const T *xs, const T *ys, const T *zs,
                                                  const int32_t *start, const double *box,
-                                                 int64_t side, Level lev, Cheb ch)
+                                                 int64_t side, bool fine, Level lev, Cheb ch)
 {
     constexpr int N3 = N * N * N;
     static_assert(N3 <= EW, "one thread per node");
@@ -264,7 +354,8 @@ __global__ __launch_bounds__(EW) void p2m_kernel(const T *xs, const T *ys, const
     const int32_t j0 = start[leaf], j1 = start[leaf + 1];
     if (j0 == j1)
         return;
-    const int64_t ix = leaf % side, iy = (leaf / side) % side, iz = leaf / (side * side);
+    int64_t ix, iy, iz;
+    cell_coords(leaf, side, fine, ix, iy, iz);
     const double R = box[3];
     const double h = 2.0 * R / (double)side, hh = 0.5 * h;
     const double cx = box[0] - R + ((double)ix + 0.5) * h;
@@ -302,6 +393,41 @@ __global__ __launch_bounds__(EW) void p2m_kernel(const T *xs, const T *ys, const
     }
     if (m < N3)
         w[m] = a;
+}
+
+// Target mask of the refined level: occupied cells whose parent leaf is refined.
+__global__ __launch_bounds__(EW) void tmask_kernel(Level lev, const int32_t *refined)
+{
+    const int64_t side = lev.side, k = (int64_t)blockIdx.x * EW + threadIdx.x;
+    if (k >= side * side * side)
+        return;
+    const int64_t ix = k % side, iy = (k / side) % side, iz = k / (side * side);
+    const int64_t ps = side >> 1, sl = slot(ix, iy, iz, lev.P);
+    const int64_t par = (ix >> 1) + ps * ((iy >> 1) + ps * (iz >> 1));
+    lev.tmask[sl] = lev.occ[sl] && refined[par] ? 1 : 0;
+}
+
+// flag[ct Q^3 + c] = tmask of class ct's cell c (sub-grid order, x fastest).
+__global__ __launch_bounds__(EW) void tflag_kernel(Level lev, int32_t *flag)
+{
+    const int64_t Q = lev.side / 2, Q3 = Q * Q * Q, e = (int64_t)blockIdx.x * EW + threadIdx.x;
+    if (e >= 8 * Q3)
+        return;
+    const int64_t ct = e / Q3, c = e % Q3, P = lev.P;
+    const int64_t ux = c % Q, uy = (c / Q) % Q, uz = c / (Q * Q);
+    flag[e] = lev.tmask[ct * P * P * P + (ux + 2) + P * ((uy + 2) + P * (uz + 2))];
+}
+
+// list[scan[e]] = padded index of cell e for every flagged cell.
+__global__ __launch_bounds__(EW) void tlist_kernel(Level lev, const int32_t *flag,
+                                                   const int32_t *scan, int32_t *list)
+{
+    const int64_t Q = lev.side / 2, Q3 = Q * Q * Q, e = (int64_t)blockIdx.x * EW + threadIdx.x;
+    if (e >= 8 * Q3 || !flag[e])
+        return;
+    const int64_t c = e % Q3, P = lev.P;
+    const int64_t ux = c % Q, uy = (c / Q) % Q, uz = c / (Q * Q);
+    list[scan[e]] = (int32_t)((ux + 2) + P * ((uy + 2) + P * (uz + 2)));
 }
 
 // T[pos][m][l] = prod_a S_{m_a}(u_a), u = child node l in the parent's frame.
@@ -463,11 +589,13 @@ __device__ inline void offset_shift(int o, int ct, int64_t P, int &cs, int64_t &
 // cores work on the current one.  Tiles without an occupied target cell are
 // skipped (nothing reads the local expansion of an empty cell), and so are
 // offsets whose TN source cells are all empty (their weights are exact zeros).
-// One launch covers every level (level 2's blocks first): the levels' M2L
+// One launch covers every level (level 2's tiles first): the levels' M2L
 // steps are independent, and the few blocks of the coarse levels then run
-// beside the many of the finest.  Blocks are renumbered so that consecutive
-// tiles run on the same XCD, which then shares the column tile's weights in
-// its L2.
+// beside the many of the finest.  Hardware block b runs on XCD b % 8; block
+// b = 8k + x takes column tile T = 8 floor(k / row_tiles) + x and row tile
+// k % row_tiles, so the row tiles of one column tile share an XCD (and its L2
+// copy of the column tile's weights) while consecutive column tiles, which
+// hold the work when it is concentrated, spread over all XCDs.
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 typedef double dbl2 __attribute__((ext_vector_type(2)));
 
@@ -475,10 +603,10 @@ constexpr int kMaxLevels = kFmmMaxDepth - 1;  // levels 2..depth
 struct M2lPlan {
     Level lev[kMaxLevels];
     const double *At[kMaxLevels];  // table of each level
-    int64_t ntc[kMaxLevels];       // column tiles of each level
-    int64_t first[kMaxLevels];     // first block of each level
-    int nlev, ntr;
-    int64_t nblocks;
+    int64_t ntc[kMaxLevels];       // column tiles per class of each level
+    int64_t first[kMaxLevels];     // first column tile (all classes) of each level
+    int nlev, ntr;                 // levels, row tiles
+    int64_t ntiles;                // column tiles of all levels and classes
 };
 
 template <int N>
@@ -497,41 +625,49 @@ __global__ __launch_bounds__(kM2lThreads) void m2l_kernel(M2lPlan plan)
     __shared__ int8_t flag[kOffsets];
     __shared__ int nlist;
 
-    // XCD-aware renumbering: hardware block b runs on XCD b % 8; logical block
-    // ids are consecutive within an XCD.
-    const int64_t b = blockIdx.x, q = plan.nblocks / kXcds;
-    int64_t lb = b < q * kXcds ? (b % kXcds) * q + b / kXcds : b;
-    // the block's level (a select, not an index, keeps the plan in SGPRs)
+    const int ntiles_r = plan.ntr;
+    const int64_t b = blockIdx.x, kb = b / kXcds;
+    int64_t tile = kXcds * (kb / ntiles_r) + b % kXcds;
+    const int rt = (int)(kb % ntiles_r);
+    if (tile >= plan.ntiles)
+        return;
+    // the tile's level (a select, not an index, keeps the plan in SGPRs)
     Level lev = plan.lev[0];
     const double *At = plan.At[0];
     int64_t ntiles_c = plan.ntc[0], lfirst = 0;
 #pragma unroll
     for (int i = 1; i < kMaxLevels; ++i)
-        if (i < plan.nlev && lb >= plan.first[i]) {
+        if (i < plan.nlev && tile >= plan.first[i]) {
             lev = plan.lev[i];
             At = plan.At[i];
             ntiles_c = plan.ntc[i];
             lfirst = plan.first[i];
         }
-    lb -= lfirst;
-    const int ntiles_r = plan.ntr;
-    const int rt = (int)(lb % ntiles_r);
-    const int64_t cti = (lb / ntiles_r) % ntiles_c;
-    const int ct = (int)(lb / (ntiles_r * ntiles_c));
+    tile -= lfirst;
+    const int64_t cti = tile % ntiles_c;
+    const int ct = (int)(tile / ntiles_c);
 
     const int64_t P = lev.P, P3 = P * P * P, Q = lev.side / 2, Q3 = Q * Q * Q;
     const int row0 = rt * TM;
     const int64_t c0 = cti * TN;
     const int t = threadIdx.x, lane = t % 64, wave = t / 64;
-    const int32_t *occ_t = lev.occ + (int64_t)ct * P3;
+    const int32_t *occ_t = lev.tmask + (int64_t)ct * P3;
     int mine = 0;
     if (t < TN) {
-        const int64_t c = c0 + t;
         int64_t pc = -1;
-        if (c < Q3) {
-            const int64_t ux = c % Q, uy = (c / Q) % Q, uz = c / (Q * Q);
-            pc = (ux + 2) + P * ((uy + 2) + P * (uz + 2));
-            mine = occ_t[pc];
+        if (lev.tlist) {          // columns from the class's list of target cells
+            const int64_t c = lev.tscan[ct * Q3] + c0 + t;
+            if (c < lev.tscan[(ct + 1) * Q3]) {
+                pc = lev.tlist[c];
+                mine = 1;
+            }
+        } else {
+            const int64_t c = c0 + t;
+            if (c < Q3) {
+                const int64_t ux = c % Q, uy = (c / Q) % Q, uz = c / (Q * Q);
+                pc = (ux + 2) + P * ((uy + 2) + P * (uz + 2));
+                mine = occ_t[pc];
+            }
         }
         colpad[t] = pc;
     }
@@ -680,8 +816,8 @@ __global__ __launch_bounds__(EW) void l2l_kernel(Level par, Level chd, const dou
     const int64_t side = chd.side;
     const int64_t cell = blockIdx.x;
     const int64_t ix = cell % side, iy = (cell / side) % side, iz = cell / (side * side);
-    if (!chd.occ[slot(ix, iy, iz, chd.P)])
-        return;                      // nothing reads an empty cell's expansion
+    if (!chd.tmask[slot(ix, iy, iz, chd.P)])
+        return;                      // nothing reads this cell's expansion
     const int pos = (int)((ix & 1) + 2 * (iy & 1) + 4 * (iz & 1));
     const double *lp = par.L + slot(ix >> 1, iy >> 1, iz >> 1, par.P) * 4 * N3;
     double *lc = chd.L + slot(ix, iy, iz, chd.P) * 4 * N3;
@@ -695,11 +831,14 @@ __global__ __launch_bounds__(EW) void l2l_kernel(Level par, Level chd, const dou
 }
 
 // ------------------------------------------------------------------ L2P
+// Sample j (sorted) evaluates the local expansion of its leaf, or, in the
+// adaptive tree when its leaf is refined, of its cell one level deeper.
 template <int N, typename T>
 __global__ __launch_bounds__(EW) void l2p_kernel(const T *xs, const T *ys, const T *zs,
                                                  const uint32_t *ks, const uint32_t *order,
                                                  int64_t p, const double *box, Level leaves,
-                                                 Cheb ch, int64_t t0, int64_t nt, bool energy,
+                                                 Level fine, const int32_t *refined, Cheb ch,
+                                                 int64_t t0, int64_t nt, bool energy,
                                                  double *acc, int64_t ld)
 {
     constexpr int N3 = N * N * N;
@@ -709,16 +848,29 @@ __global__ __launch_bounds__(EW) void l2p_kernel(const T *xs, const T *ys, const
     const int64_t i = (int64_t)order[j] - t0;
     if (i < 0 || i >= nt)
         return;
-    const int64_t side = leaves.side;
-    const int64_t leaf = ks[j];
-    const int64_t ix = leaf % side, iy = (leaf / side) % side, iz = leaf / (side * side);
+    const int64_t key = ks[j];
+    int64_t ix, iy, iz, side;
+    const Level *lv = &leaves;
+    if (refined) {                           // keys are (leaf, child)
+        if (refined[key >> 3]) {
+            lv = &fine;
+            side = fine.side;
+            cell_coords(key, side, true, ix, iy, iz);
+        } else {
+            side = leaves.side;
+            cell_coords(key >> 3, side, false, ix, iy, iz);
+        }
+    } else {
+        side = leaves.side;
+        cell_coords(key, side, false, ix, iy, iz);
+    }
     const double R = box[3];
     const double h = 2.0 * R / (double)side, hh = 0.5 * h;
     double sx[N], sy[N], sz[N];
     cheb_s<N>(ch, ((double)xs[j] - (box[0] - R + ((double)ix + 0.5) * h)) / hh, sx);
     cheb_s<N>(ch, ((double)ys[j] - (box[1] - R + ((double)iy + 0.5) * h)) / hh, sy);
     cheb_s<N>(ch, ((double)zs[j] - (box[2] - R + ((double)iz + 0.5) * h)) / hh, sz);
-    const double *lf = leaves.L + slot(ix, iy, iz, leaves.P) * 4 * N3;
+    const double *lf = lv->L + slot(ix, iy, iz, lv->P) * 4 * N3;
     double f[4] = {0.0, 0.0, 0.0, 0.0};
     for (int mz = 0; mz < N; ++mz)
         for (int my = 0; my < N; ++my) {
@@ -763,6 +915,16 @@ size_t fmm_table_doubles(int order)
     }
 }
 
+int64_t fmm_refine_threshold(int order)
+{
+    // 8 children x 189 interactions x 4 components x n^6 multiply-adds, at
+    // about 1/7 of a direct pair each (FP64 matrix-core rate over pair rate)
+    int64_t n6 = 1;
+    for (int i = 0; i < 6; ++i)
+        n6 *= order;
+    return 8 * 189 * 4 * n6 / 7;
+}
+
 size_t fmm_sort_temp_bytes(int64_t p, int depth)
 {
     const int64_t nleaves = int64_t(1) << (3 * depth);
@@ -797,57 +959,96 @@ hipError_t run_typed(const FmmLaunch &f, hipStream_t s)
     const T *x = static_cast<const T *>(f.x), *y = static_cast<const T *>(f.y),
             *z = static_cast<const T *>(f.z);
     T *xs = static_cast<T *>(f.xs), *ys = static_cast<T *>(f.ys), *zs = static_cast<T *>(f.zs);
-    const int64_t p = f.p, side = int64_t(1) << f.depth, nleaves = side * side * side;
+    const int D = f.depth, F = f.adaptive ? D + 1 : D;
+    const int64_t p = f.p, side = int64_t(1) << D, nleaves = side * side * side;
+    const int64_t sideF = int64_t(1) << F, ncellsF = sideF * sideF * sideF;
     const Cheb ch = make_cheb(N);
     hipError_t e;
     // root box
     const int nb = (int)std::min<int64_t>(kFmmBoxBlocks, (p + EW - 1) / EW);
     hipLaunchKernelGGL(box_stage1<T>, dim3(nb), dim3(EW), 0, s, x, y, z, p, f.box_part);
     hipLaunchKernelGGL(box_stage2, dim3(1), dim3(64), 0, s, f.box_part, nb, f.box);
-    // leaf keys, stable sort by leaf, sorted coordinates, leaf ranges and chunks
+    // cell keys at the deepest level, stable sort, sorted coordinates, cell ranges
     hipLaunchKernelGGL(leaf_keys_kernel<T>, dim3(ew_blocks(p)), dim3(EW), 0, s, x, y, z, p, f.box,
-                       side, f.keys_in, f.vals_in);
+                       sideF, f.adaptive, f.keys_in, f.vals_in);
     size_t tb = f.temp_bytes;
     if ((e = hipcub::DeviceRadixSort::SortPairs(f.temp, tb, f.keys_in, f.keys_out, f.vals_in,
-                                                f.vals_out, (int)p, 0, 3 * f.depth, s)) !=
-        hipSuccess)
+                                                f.vals_out, (int)p, 0, 3 * F, s)) != hipSuccess)
         return e;
     hipLaunchKernelGGL(gather_kernel<T>, dim3(ew_blocks(p)), dim3(EW), 0, s, x, y, z, f.vals_out,
                        p, xs, ys, zs);
-    hipLaunchKernelGGL(leaf_bounds_kernel, dim3(ew_blocks(nleaves + 1)), dim3(EW), 0, s,
-                       f.keys_out, p, nleaves, f.start);
+    hipLaunchKernelGGL(leaf_bounds_kernel, dim3(ew_blocks(ncellsF + 1)), dim3(EW), 0, s,
+                       f.keys_out, p, ncellsF, f.start);
+    // refinement and near-field target chunks
+    const int64_t stride = f.adaptive ? 8 : 1;
+    if (f.adaptive)
+        hipLaunchKernelGGL(refine_kernel, dim3(ew_blocks(nleaves)), dim3(EW), 0, s, f.start, side,
+                           fmm_refine_threshold(N), f.refined);
     hipLaunchKernelGGL(leaf_chunks_kernel, dim3(ew_blocks(nleaves + 1)), dim3(EW), 0, s, f.start,
-                       nleaves, f.near_tpb, f.chunks);
+                       nleaves, stride, f.near_tpb, f.adaptive ? f.refined : nullptr, 0, false,
+                       f.chunks);
     tb = f.temp_bytes;
     if ((e = hipcub::DeviceScan::ExclusiveSum(f.temp, tb, f.chunks, f.chunk_start,
                                               (int)(nleaves + 1), s)) != hipSuccess)
         return e;
-    // multipole weights: zero (padding included), leaves, then upward
+    if (f.adaptive) {
+        hipLaunchKernelGGL(leaf_chunks_kernel, dim3(ew_blocks(ncellsF + 1)), dim3(EW), 0, s,
+                           f.start, ncellsF, (int64_t)1, f.near_tpb, f.refined, 3, true,
+                           f.chunks_fine);
+        tb = f.temp_bytes;
+        if ((e = hipcub::DeviceScan::ExclusiveSum(f.temp, tb, f.chunks_fine, f.chunk_start_fine,
+                                                  (int)(ncellsF + 1), s)) != hipSuccess)
+            return e;
+    }
+    // multipole weights: zero (padding included), the deepest level, then upward
     Level lev[kFmmMaxDepth + 1];
-    for (int l = 2; l <= f.depth; ++l) {
+    for (int l = 2; l <= F; ++l) {
         lev[l].side = int64_t(1) << l;
         lev[l].P = fmm_padded_side(l);
         lev[l].W = f.W[l];
         lev[l].L = f.L[l];
         lev[l].occ = f.occ[l];
+        lev[l].tmask = (f.adaptive && l == F) ? f.tmask_fine : f.occ[l];
+        lev[l].tlist = nullptr;
+        lev[l].tscan = nullptr;
         const int64_t nw = (int64_t)fmm_level_cells(l) * N3;
         hipLaunchKernelGGL(fill_kernel, dim3(ew_blocks(nw)), dim3(EW), 0, s, lev[l].W, nw);
         const int64_t no = (int64_t)fmm_level_cells(l);
         hipLaunchKernelGGL(fill_int_kernel, dim3(ew_blocks(no)), dim3(EW), 0, s, lev[l].occ, no);
+        if (lev[l].tmask != lev[l].occ)
+            hipLaunchKernelGGL(fill_int_kernel, dim3(ew_blocks(no)), dim3(EW), 0, s,
+                               lev[l].tmask, no);
     }
     hipLaunchKernelGGL(transfer_kernel<N>, dim3(ew_blocks(8 * N3 * N3)), dim3(EW), 0, s, ch, f.Tm);
-    hipLaunchKernelGGL((p2m_kernel<N, T>), dim3((unsigned)nleaves), dim3(EW), 0, s, xs, ys, zs,
-                       f.start, f.box, side, lev[f.depth], ch);
-    for (int l = f.depth - 1; l >= 2; --l)
+    hipLaunchKernelGGL((p2m_kernel<N, T>), dim3((unsigned)ncellsF), dim3(EW), 0, s, xs, ys, zs,
+                       f.start, f.box, sideF, f.adaptive, lev[F], ch);
+    for (int l = F - 1; l >= 2; --l)
         hipLaunchKernelGGL(m2m_kernel<N>, dim3((unsigned)(int64_t(1) << (3 * l))), dim3(EW), 0, s,
                            lev[l], lev[l + 1], f.Tm);
+    if (f.adaptive) {
+        // the refined level's target cells, listed per class in sub-grid order
+        hipLaunchKernelGGL(tmask_kernel, dim3(ew_blocks(ncellsF)), dim3(EW), 0, s, lev[F],
+                           f.refined);
+        hipLaunchKernelGGL(tflag_kernel, dim3(ew_blocks(ncellsF)), dim3(EW), 0, s, lev[F],
+                           f.tflag);
+        hipLaunchKernelGGL(fill_int_kernel, dim3(1), dim3(EW), 0, s, f.tflag + ncellsF,
+                           (int64_t)1);
+        tb = f.temp_bytes;
+        if ((e = hipcub::DeviceScan::ExclusiveSum(f.temp, tb, f.tflag, f.tscan,
+                                                  (int)(ncellsF + 1), s)) != hipSuccess)
+            return e;
+        hipLaunchKernelGGL(tlist_kernel, dim3(ew_blocks(ncellsF)), dim3(EW), 0, s, lev[F],
+                           f.tflag, f.tscan, f.tlist);
+        lev[F].tlist = f.tlist;
+        lev[F].tscan = f.tscan;
+    }
     // interactions (every level in one launch), then the downward pass
     const int64_t ntab = (int64_t)kOffsets * M2lShape<N>::KP * M2lShape<N>::RP;
     M2lPlan plan{};
-    plan.nlev = f.depth - 1;
+    plan.nlev = F - 1;
     plan.ntr = M2lShape<N>::RP / TM;
-    plan.nblocks = 0;
-    for (int l = 2; l <= f.depth; ++l) {
+    plan.ntiles = 0;
+    for (int l = 2; l <= F; ++l) {
         double *At = f.A + (l - 2) * ntab;
         if (f.kernel == kKernelLog)
             hipLaunchKernelGGL((m2l_table_kernel<N, kKernelLog>), dim3(ew_blocks(ntab)), dim3(EW),
@@ -860,16 +1061,18 @@ hipError_t run_typed(const FmmLaunch &f, hipStream_t s)
         plan.lev[i] = lev[l];
         plan.At[i] = At;
         plan.ntc[i] = (Q3 + TN - 1) / TN;
-        plan.first[i] = plan.nblocks;
-        plan.nblocks += 8 * plan.ntr * plan.ntc[i];
+        plan.first[i] = plan.ntiles;
+        plan.ntiles += 8 * plan.ntc[i];
     }
-    hipLaunchKernelGGL(m2l_kernel<N>, dim3((unsigned)plan.nblocks), dim3(kM2lThreads), 0, s, plan);
-    for (int l = 3; l <= f.depth; ++l)
+    const int64_t nblocks = (plan.ntiles + kXcds - 1) / kXcds * kXcds * plan.ntr;
+    hipLaunchKernelGGL(m2l_kernel<N>, dim3((unsigned)nblocks), dim3(kM2lThreads), 0, s, plan);
+    for (int l = 3; l <= F; ++l)
         hipLaunchKernelGGL(l2l_kernel<N>, dim3((unsigned)(int64_t(1) << (3 * l))), dim3(EW), 0, s,
                            lev[l - 1], lev[l], f.Tm);
     if ((e = hipGetLastError()) != hipSuccess)
         return e;
-    // near field (exact pair sums over the 27 leaves around each leaf), then far field
+    // near field (exact pair sums over the 27 cells around each target's cell),
+    // then the far field
     NearLaunch nl;
     nl.precision = f.precision;
     nl.kernel = f.kernel;
@@ -879,8 +1082,9 @@ hipError_t run_typed(const FmmLaunch &f, hipStream_t s)
     nl.zs = zs;
     nl.order = f.vals_out;
     nl.start = f.start;
+    nl.stride = stride;
     nl.chunk_start = f.chunk_start;
-    nl.nleaves = nleaves;
+    nl.ncells = nleaves;
     nl.side = side;
     nl.t0 = f.t0;
     nl.nt = f.nt;
@@ -890,9 +1094,19 @@ hipError_t run_typed(const FmmLaunch &f, hipStream_t s)
     nl.max_blocks = (p + f.near_tpb - 1) / f.near_tpb + nleaves;
     if ((e = launch_near(nl, s)) != hipSuccess)
         return e;
+    if (f.adaptive) {
+        nl.fine = true;
+        nl.stride = 1;
+        nl.chunk_start = f.chunk_start_fine;
+        nl.ncells = ncellsF;
+        nl.side = sideF;
+        nl.max_blocks = (p + f.near_tpb - 1) / f.near_tpb + ncellsF;
+        if ((e = launch_near(nl, s)) != hipSuccess)
+            return e;
+    }
     hipLaunchKernelGGL((l2p_kernel<N, T>), dim3(ew_blocks(p)), dim3(EW), 0, s, xs, ys, zs,
-                       f.keys_out, f.vals_out, p, f.box, lev[f.depth], ch, f.t0, f.nt, f.energy,
-                       f.acc, f.ld);
+                       f.keys_out, f.vals_out, p, f.box, lev[D], lev[F],
+                       f.adaptive ? f.refined : nullptr, ch, f.t0, f.nt, f.energy, f.acc, f.ld);
     return hipGetLastError();
 }
 
@@ -906,7 +1120,7 @@ hipError_t run_order(const FmmLaunch &f, hipStream_t s)
 
 hipError_t launch_fmm_repulsion(const FmmLaunch &f, hipStream_t s)
 {
-    if (f.depth < 2 || f.depth > kFmmMaxDepth || f.p < 1)
+    if (f.depth < 2 || f.depth + (f.adaptive ? 1 : 0) > kFmmMaxDepth || f.p < 1)
         return hipErrorInvalidValue;
     switch (f.order) {
     case 3: return run_order<3>(f, s);

@@ -25,7 +25,8 @@ constexpr int kFmmBoxBlocks = 1024;
 struct FmmLaunch {
     int precision = 0, kernel = kKernelDistance;
     bool energy = false;
-    int depth = 0, order = 0;
+    int depth = 0, order = 0;             // base depth D, interpolation order
+    bool adaptive = false;                // refine dense leaves to depth D + 1
     const void *x = nullptr, *y = nullptr, *z = nullptr;
     int64_t p = 0, t0 = 0, nt = 0;
     double eps = 0.0;
@@ -37,21 +38,29 @@ struct FmmLaunch {
     double *box = nullptr;                // centre[3], half-width
     uint32_t *keys_in = nullptr, *keys_out = nullptr, *vals_in = nullptr, *vals_out = nullptr;
     void *xs = nullptr, *ys = nullptr, *zs = nullptr;
-    int32_t *start = nullptr, *chunks = nullptr, *chunk_start = nullptr;   // [8^depth + 1]
+    // [8^F + 1] with F = D (+1 if adaptive): cell starts, near-field chunks of
+    // the leaves and, when adaptive, of the refined level
+    int32_t *start = nullptr, *chunks = nullptr, *chunk_start = nullptr;
+    int32_t *chunks_fine = nullptr, *chunk_start_fine = nullptr;
+    int32_t *refined = nullptr;           // [8^D] when adaptive
+    int32_t *tmask_fine = nullptr;        // [8][P^3] of level D + 1 when adaptive
+    int32_t *tflag = nullptr, *tscan = nullptr, *tlist = nullptr;   // [8^F + 1] when adaptive
     void *temp = nullptr;
     size_t temp_bytes = 0;
     double *W[kFmmMaxDepth + 1] = {};     // level l: [8][P^3][order^3]
     int32_t *occ[kFmmMaxDepth + 1] = {};  // level l: [8][P^3]
     double *L[kFmmMaxDepth + 1] = {};     // level l: [8][P^3][4 order^3]
-    double *A = nullptr;                  // [depth-1][343][k padded][rows padded]
+    double *A = nullptr;                  // [F-1][343][k padded][rows padded]
     double *Tm = nullptr;                 // [8][order^3][order^3]
 };
 // Padded class side P and cell slots 8 P^3 of level l.
 int64_t fmm_padded_side(int level);
 size_t fmm_level_cells(int level);
-// Temporary bytes of the leaf sort (3 * depth key bits) and of the block-count scan.
 size_t fmm_table_doubles(int order);  // M2L table of one level, padded
+// Temporary bytes of the cell sort (3 * depth key bits) and of the chunk scans.
 size_t fmm_sort_temp_bytes(int64_t p, int depth);
+// Price of refining one leaf, in direct pairs (adaptive tree).
+int64_t fmm_refine_threshold(int order);
 hipError_t launch_fmm_repulsion(const FmmLaunch &f, hipStream_t s);
 
 // acc[c*ld + t] = (init ? 0 : acc[c*ld + t]) + part[0][c][t] + ... + part[n-1][c][t],

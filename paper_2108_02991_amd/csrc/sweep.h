@@ -87,15 +87,22 @@ hipError_t launch_sweep_cells(const SweepLaunch &l, hipStream_t s);
 // targets; chunk_start[k] is the first block of leaf k (an exclusive prefix
 // sum of the per-leaf block counts, nleaves + 1 entries); the grid has
 // max_blocks >= chunk_start[nleaves] blocks and the extra ones return.
+// Cells are numbered in one of two ways.  Plain: x fastest at the cells'
+// level, cell k owns sorted samples [start[stride k], start[stride (k+1)])
+// (stride 8 when the samples are sorted one level deeper).  Fine: the index
+// is (parent, child) = 8 (x-fastest parent index) + (cx + 2 cy + 4 cz) and
+// cell k owns [start[k], start[k+1]).
 struct NearLaunch {
     int precision = 0;
     int kernel = kKernelDistance;
     bool energy = false;
-    const void *xs = nullptr, *ys = nullptr, *zs = nullptr;   // leaf-sorted samples
+    bool fine = false;                 // cell numbering (see above)
+    const void *xs = nullptr, *ys = nullptr, *zs = nullptr;   // cell-sorted samples
     const uint32_t *order = nullptr;   // sorted position -> sample index
-    const int32_t *start = nullptr;    // [nleaves + 1]: first sorted sample of each leaf
-    const int32_t *chunk_start = nullptr;
-    int64_t nleaves = 0, side = 0;     // leaves, and leaves per axis
+    const int32_t *start = nullptr;    // first sorted sample of each cell
+    int64_t stride = 1;                // plain numbering: start index of cell k is stride k
+    const int32_t *chunk_start = nullptr;  // [ncells + 1] target chunks before each cell
+    int64_t ncells = 0, side = 0;      // cells, and cells per axis
     int64_t t0 = 0, nt = 0;
     double eps = 0.0;
     double *acc = nullptr;

@@ -403,23 +403,33 @@ void sweep_cells_kernel(SweepLaunch l)
     }
 }
 
-// Near field of the far-field repulsion: every sample of a leaf against the
-// samples of the 27 leaves around it, which are nine contiguous runs of the
-// leaf-sorted samples (three consecutive leaves along x for each y, z
-// neighbour).  Block b takes chunk b - chunk_start[leaf] of the leaf with
-// chunk_start[leaf] <= b < chunk_start[leaf + 1]; the pair arithmetic and the
-// accumulation are those of the sample sweep, and the sums are written (not
-// added) to the rows of targets in [t0, t0 + nt).
+// Near field of the far-field repulsion: every sample of a cell against the
+// samples of the 27 cells around it (itself included).  Those are runs of the
+// cell-sorted samples: nine runs of three cells along x in plain numbering,
+// 27 single cells in fine numbering.  The block streams the runs as one
+// sequence, in run order, through LDS tiles of kSampleTile sources, so tiles
+// fill across run boundaries.  Block b takes chunk b - chunk_start[cell] of
+// the cell with chunk_start[cell] <= b < chunk_start[cell + 1]; the pair
+// arithmetic and the accumulation are those of the sample sweep, and the sums
+// are written (not added) to the rows of targets in [t0, t0 + nt).
+__device__ inline int64_t fine_index(int64_t x, int64_t y, int64_t z, int64_t side)
+{
+    const int64_t ps = side >> 1;
+    return ((x >> 1) + ps * ((y >> 1) + ps * (z >> 1))) * 8 +
+           ((x & 1) | ((y & 1) << 1) | ((z & 1) << 2));
+}
+
 template <int MODE, int R, bool ENERGY, int KERN>
 __global__ __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(min_waves<MODE>())))
 void near_kernel(NearLaunch l)
 {
     using T = typename ModeT<MODE>::T;
     __shared__ P4<T> tile[kSampleTile];
+    __shared__ int64_t run_lo[27], run_pre[28];
     const int64_t b = blockIdx.x;
-    if (b >= (int64_t)l.chunk_start[l.nleaves])
+    if (b >= (int64_t)l.chunk_start[l.ncells])
         return;
-    int64_t lo = 0, hi = l.nleaves;          // chunk_start[lo] <= b < chunk_start[hi]
+    int64_t lo = 0, hi = l.ncells;           // chunk_start[lo] <= b < chunk_start[hi]
     while (hi - lo > 1) {
         const int64_t mid = (lo + hi) >> 1;
         if ((int64_t)l.chunk_start[mid] <= b)
@@ -427,11 +437,53 @@ void near_kernel(NearLaunch l)
         else
             hi = mid;
     }
-    const int64_t leaf = lo;
-    const int64_t side = l.side;
-    const int64_t ix = leaf % side, iy = (leaf / side) % side, iz = leaf / (side * side);
-    const int64_t first = (int64_t)l.start[leaf] + (b - l.chunk_start[leaf]) * (int64_t)(BLK * R);
-    const int64_t last = (int64_t)l.start[leaf + 1] - 1;
+    const int64_t cell = lo, side = l.side;
+    int64_t ix, iy, iz, t_lo, t_hi;
+    if (l.fine) {
+        const int64_t ps = side >> 1, par = cell >> 3, ch = cell & 7;
+        ix = 2 * (par % ps) + (ch & 1);
+        iy = 2 * ((par / ps) % ps) + ((ch >> 1) & 1);
+        iz = 2 * (par / (ps * ps)) + (ch >> 2);
+        t_lo = l.start[cell];
+        t_hi = l.start[cell + 1];
+    } else {
+        ix = cell % side;
+        iy = (cell / side) % side;
+        iz = cell / (side * side);
+        t_lo = l.start[l.stride * cell];
+        t_hi = l.start[l.stride * (cell + 1)];
+    }
+    // the source runs, in a fixed order (z, y, then x)
+    if (threadIdx.x < 27) {
+        const int o = (int)threadIdx.x;
+        const int64_t x = ix + o % 3 - 1, y = iy + (o / 3) % 3 - 1, z = iz + o / 9 - 1;
+        int64_t s0 = 0, s1 = 0;
+        const bool in_y = y >= 0 && y < side && z >= 0 && z < side;
+        if (l.fine) {
+            if (in_y && x >= 0 && x < side) {
+                const int64_t k = fine_index(x, y, z, side);
+                s0 = l.start[k];
+                s1 = l.start[k + 1];
+            }
+        } else if (in_y && o % 3 == 0) {     // one run of up to three cells along x
+            const int64_t x0 = ix > 0 ? ix - 1 : 0, x1 = ix + 1 < side ? ix + 1 : side - 1;
+            const int64_t row = side * (y + side * z);
+            s0 = l.start[l.stride * (x0 + row)];
+            s1 = l.start[l.stride * (x1 + row + 1)];
+        }
+        run_lo[o] = s0;
+        run_pre[o + 1] = s1 - s0;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        run_pre[0] = 0;
+        for (int o = 0; o < 27; ++o)
+            run_pre[o + 1] += run_pre[o];
+    }
+    __syncthreads();
+    const int64_t total = run_pre[27];
+    const int64_t first = t_lo + (b - l.chunk_start[cell]) * (int64_t)(BLK * R);
+    const int64_t last = t_hi - 1;
     const T *xs = static_cast<const T *>(l.xs), *ys = static_cast<const T *>(l.ys),
             *zs = static_cast<const T *>(l.zs);
     T xi[R], yi[R], zi[R];
@@ -445,70 +497,67 @@ void near_kernel(NearLaunch l)
     }
     Acc<MODE> gx[R], gy[R], gz[R], ee[R];
     const T guard = guard_value<T>(l.eps);
-    for (int oz = -1; oz <= 1; ++oz)
-        for (int oy = -1; oy <= 1; ++oy) {
-            const int64_t y = iy + oy, z = iz + oz;
-            if (y < 0 || y >= side || z < 0 || z >= side)
-                continue;
-            const int64_t x0 = ix > 0 ? ix - 1 : 0, x1 = ix + 1 < side ? ix + 1 : side - 1;
-            const int64_t row = side * (y + side * z);
-            const int64_t s0 = l.start[x0 + row], s1 = l.start[x1 + row + 1];
-            for (int64_t base = s0; base < s1; base += kSampleTile) {
-                const int n = (int)((s1 - base) < kSampleTile ? (s1 - base) : kSampleTile);
-                for (int j = threadIdx.x; j < n; j += BLK)
-                    tile[j] = P4<T>{xs[base + j], ys[base + j], zs[base + j], T(0)};
-                __syncthreads();
-                auto pair = [&](const P4<T> sv) {
-#pragma unroll
-                    for (int r = 0; r < R; ++r) {
-                        T dx = xi[r] - sv.x, dy = yi[r] - sv.y, dz = zi[r] - sv.z;
-                        T r2 = fmaT(dz, dz, fmaT(dy, dy, fmaT(dx, dx, guard)));
-                        T w = pair_weight<KERN>(r2);
-                        acc_fma(gx[r], w, dx);
-                        acc_fma(gy[r], w, dy);
-                        acc_fma(gz[r], w, dz);
-                        if constexpr (ENERGY) {
-                            if constexpr (KERN == kLog)
-                                acc_add(ee[r], lg2(r2));
-                            else
-                                acc_fma(ee[r], w, r2);
-                        }
-                    }
-                };
-                if (n == kSampleTile) {
-                    // full tile: LDS reads one group of U sources ahead, as in the sweep
-                    constexpr int U = SPK_SOURCE_UNROLL;
-                    P4<T> cur[U], nxt[U];
-#pragma unroll
-                    for (int u = 0; u < U; ++u)
-                        cur[u] = tile[u];
-                    for (int j = 0; j < kSampleTile; j += U) {
-                        const int jn = (j + U) & (kSampleTile - 1);
-#pragma unroll
-                        for (int u = 0; u < U; ++u)
-                            nxt[u] = tile[jn + u];
-#pragma unroll
-                        for (int u = 0; u < U; ++u)
-                            pair(cur[u]);
-#pragma unroll
-                        for (int u = 0; u < U; ++u)
-                            cur[u] = nxt[u];
-                    }
-                } else {
-                    for (int j = 0; j < n; ++j)
-                        pair(tile[j]);
-                }
-#pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    gx[r].end_tile();
-                    gy[r].end_tile();
-                    gz[r].end_tile();
-                    if constexpr (ENERGY)
-                        ee[r].end_tile();
-                }
-                __syncthreads();
-            }
+    int run = 0;  // run of this thread's next source (sources are read in increasing order)
+    for (int64_t base = 0; base < total; base += kSampleTile) {
+        const int n = (int)((total - base) < kSampleTile ? (total - base) : kSampleTile);
+        for (int j = threadIdx.x; j < n; j += BLK) {
+            const int64_t v = base + j;
+            while (run_pre[run + 1] <= v)
+                ++run;
+            const int64_t src = run_lo[run] + (v - run_pre[run]);
+            tile[j] = P4<T>{xs[src], ys[src], zs[src], T(0)};
         }
+        __syncthreads();
+        auto pair = [&](const P4<T> sv) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                T dx = xi[r] - sv.x, dy = yi[r] - sv.y, dz = zi[r] - sv.z;
+                T r2 = fmaT(dz, dz, fmaT(dy, dy, fmaT(dx, dx, guard)));
+                T w = pair_weight<KERN>(r2);
+                acc_fma(gx[r], w, dx);
+                acc_fma(gy[r], w, dy);
+                acc_fma(gz[r], w, dz);
+                if constexpr (ENERGY) {
+                    if constexpr (KERN == kLog)
+                        acc_add(ee[r], lg2(r2));
+                    else
+                        acc_fma(ee[r], w, r2);
+                }
+            }
+        };
+        if (n == kSampleTile) {
+            // full tile: LDS reads one group of U sources ahead, as in the sweep
+            constexpr int U = SPK_SOURCE_UNROLL;
+            P4<T> cur[U], nxt[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                cur[u] = tile[u];
+            for (int j = 0; j < kSampleTile; j += U) {
+                const int jn = (j + U) & (kSampleTile - 1);
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    nxt[u] = tile[jn + u];
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    pair(cur[u]);
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    cur[u] = nxt[u];
+            }
+        } else {
+            for (int j = 0; j < n; ++j)
+                pair(tile[j]);
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            gx[r].end_tile();
+            gy[r].end_tile();
+            gz[r].end_tile();
+            if constexpr (ENERGY)
+                ee[r].end_tile();
+        }
+        __syncthreads();
+    }
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int64_t j = first + threadIdx.x + r * BLK;

@@ -88,6 +88,16 @@ def uniform_points(p: int, L: float, seed: int) -> np.ndarray:
     return rng.uniform(-L, L, size=(3, p))
 
 
+def two_density_points(p_dense: int, p_sparse: int, L: float, seed: int) -> np.ndarray:
+    """(3, p_dense + p_sparse) points uniform in [-L, L]^3: the first p_dense in
+    the half x < 0, the rest in the half x >= 0 (a dense and a sparse region)."""
+    rng = np.random.default_rng(seed)
+    K = rng.uniform(-L, L, (3, p_dense + p_sparse))
+    K[0, :p_dense] = -np.abs(K[0, :p_dense])
+    K[0, p_dense:] = np.abs(K[0, p_dense:])
+    return K
+
+
 def rademacher(shape, seed: int) -> np.ndarray:
     rng = np.random.default_rng(seed)
     return rng.integers(0, 2, size=shape).astype(np.float64) * 2.0 - 1.0

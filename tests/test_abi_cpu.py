@@ -141,6 +141,23 @@ def test_far_field_validation_and_workspace(lib):
         assert lib.spk_workspace_size(ctypes.byref(c), ctypes.byref(n)) == code, bad
 
 
+def test_adaptive_far_field_validation(lib):
+    n = ctypes.c_size_t()
+    c = good_params(far_field_depth=4, far_field_order=5).c()
+    assert lib.spk_workspace_size(ctypes.byref(c), ctypes.byref(n)) == 0
+    uniform = n.value
+    c = good_params(far_field_depth=4, far_field_order=5, far_field_adaptive=True).c()
+    assert lib.spk_workspace_size(ctypes.byref(c), ctypes.byref(n)) == 0
+    assert n.value > uniform
+    for bad in [dict(far_field_depth=7, far_field_adaptive=True),
+                dict(far_field_depth=0, far_field_adaptive=True)]:
+        c = good_params(**bad).c()
+        assert lib.spk_workspace_size(ctypes.byref(c), ctypes.byref(n)) == EINVAL, bad
+    c = good_params(far_field_depth=3).c()
+    c.far_field_adaptive = 2
+    assert lib.spk_workspace_size(ctypes.byref(c), ctypes.byref(n)) == EINVAL
+
+
 def test_log_kernel_validation(lib):
     n = ctypes.c_size_t()
     ok = good_params(kernel="log", eps=0.01).c()

@@ -728,3 +728,63 @@ def test_fmm_reference_converges_to_the_exact_sum():
     # the oracle's exact sums are the same sums
     ref = oracle.grad(X.T, [0.0], 1, 0.5)
     np.testing.assert_allclose(ref["dFr"] * X.shape[0] ** 2, ge.T, rtol=1e-12, atol=1e-12)
+
+
+def _pairs_around_brute(cells, N):
+    """sum over samples i of the number of samples in the 27 cells around i's cell."""
+    tot = np.zeros((N, N, N), dtype=np.int64)
+    for a in range(cells.shape[0]):
+        near = np.abs(cells - cells[a]).max(axis=1) <= 1
+        tot[tuple(cells[a])] += int(near.sum())
+    return tot
+
+
+def test_fmm_reference_refine_rule_by_brute_force():
+    """The refine flags against pair counts taken sample by sample."""
+    from oracle import fmm
+    X = inputs.two_density_points(7000, 500, 0.5, seed=54).T.copy()
+    lo, hi = X.min(axis=0), X.max(axis=0)
+    c0 = 0.5 * (lo + hi)
+    R = (0.5 * (hi - lo)).max() * (1.0 + 2.0 ** -20) + 1e-30
+    cell = lambda N: np.clip(np.floor((X - (c0 - R)) / (2 * R / N)).astype(np.int64), 0, N - 1)
+    leaf, fine = cell(4), cell(8)
+    coarse = _pairs_around_brute(leaf, 4)
+    fine_pairs = _pairs_around_brute(fine, 8).reshape(4, 2, 4, 2, 4, 2).sum(axis=(1, 3, 5))
+    for n, thr in ((3, 629856), (4, 3538944)):
+        assert fmm.refine_threshold(n) == thr
+        want = (coarse - fine_pairs) > thr
+        assert np.array_equal(fmm.refined_leaves(leaf, fine, 2, n), want)
+    # the input refines some leaves (the dense half) and not others
+    flags = fmm.refined_leaves(leaf, fine, 2, 3)
+    assert 0 < flags.sum() < 32
+
+
+def test_fmm_reference_adaptive_is_the_uniform_tree_per_target():
+    """M2M is exact, so a refined target's sums are those of the uniform tree one
+    level deeper, and any other target's those of the uniform tree."""
+    from oracle import fmm
+    X = inputs.two_density_points(12000, 1000, 0.5, seed=55).T.copy()
+    k = fmm.distance_kernel()
+    info = {}
+    ga, ua = fmm.fmm(X, 2, 3, k, adaptive=True, info=info)
+    ref = info["refined_targets"]
+    assert 0 < ref.sum() < X.shape[0]
+    g2, u2 = fmm.fmm(X, 2, 3, k)
+    g3, u3 = fmm.fmm(X, 3, 3, k)
+    scale = np.abs(g2).max()
+    assert np.abs(ga[~ref] - g2[~ref]).max() <= 1e-12 * scale
+    assert np.abs(ga[ref] - g3[ref]).max() <= 1e-12 * scale
+    assert np.abs(ua[~ref] - u2[~ref]).max() <= 1e-12 * np.abs(u2).max()
+    assert np.abs(ua[ref] - u3[ref]).max() <= 1e-12 * np.abs(u3).max()
+
+
+def test_fmm_reference_adaptive_exact_for_polynomial_kernel():
+    from oracle import fmm
+    X = inputs.two_density_points(12000, 1000, 0.5, seed=56).T.copy()
+    k = fmm.square_kernel()
+    ge, ue = fmm.exact(X, k)
+    info = {}
+    g, u = fmm.fmm(X, 2, 3, k, adaptive=True, info=info)
+    assert 0 < info["refined_targets"].sum() < X.shape[0]
+    assert np.abs(g - ge).max() <= 1e-10 * np.abs(ge).max()
+    assert np.abs(u - ue).max() <= 1e-10 * np.abs(ue).max()
