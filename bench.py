@@ -94,9 +94,10 @@ def main():
     ap.add_argument("--eta", choices=["fixed", "lipschitz"], default=None,
                     help="fixed step: the workload's (default, distance kernel) or 1/L from "
                          "the Lipschitz bound (default for the log kernel; needs eps > 0)")
-    ap.add_argument("--far-field", default=None, metavar="DEPTH,ORDER",
-                    help="repulsion by the Chebyshev fast multipole method (e.g. 5,6) instead "
-                         "of all p^2 pairs; value is then an equivalent rate and roofline null")
+    ap.add_argument("--far-field", default=None, metavar="DEPTH,ORDER[,adaptive]",
+                    help="repulsion by the Chebyshev fast multipole method (e.g. 5,6 or "
+                         "5,6,adaptive) instead of all p^2 pairs; value is then an equivalent "
+                         "rate and roofline null")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed region, run a plain 1 GiB device copy three times "
                          "(reference dispatches for HBM byte counters)")
@@ -109,7 +110,7 @@ def main():
 
     import torch
     import paper_2108_02991_amd as spk
-    from paper_2108_02991_amd import configs
+    from paper_2108_02991_amd import configs, driver
 
     w = configs.WORKLOADS[args.workload]
     precision = args.precision or w.precision
@@ -120,11 +121,11 @@ def main():
     p_total = w.n_shots * w.n_samples
     eps = args.eps if args.eps is not None else (
         0.25 * 2 * w.half_width / p_total ** (1.0 / 3.0) if args.kernel == "log" else 0.0)
-    ff_depth, ff_order = (int(v) for v in args.far_field.split(",")) if args.far_field else (0, 5)
+    ff_depth, ff_order, ff_adaptive = driver.parse_far_field(args.far_field)
     prm = spk.Params(w.n_shots, w.n_samples, w.grid, precision=precision,
                      half_width=w.half_width, eps=eps, a_max=a, b_max=b, te_index=0,
                      n_pit=w.n_pit, kernel=args.kernel, far_field_depth=ff_depth,
-                     far_field_order=ff_order)
+                     far_field_order=ff_order, far_field_adaptive=ff_adaptive)
     p, M = prm.p, w.n_voxels
 
     log(f"workload {w.name}: p={p} G={w.grid} precision={precision} kernel={args.kernel} "
@@ -214,7 +215,8 @@ def main():
                    "grid": w.grid, "precision": precision, "n_pit": w.n_pit,
                    "kernel": args.kernel, "eps": eps, "eta": eta_rule,
                    "attraction": args.attraction, "pairs_per_step": pairs_per_step,
-                   "far_field": ({"depth": ff_depth, "order": ff_order} if ff_depth else None)},
+                   "far_field": ({"depth": ff_depth, "order": ff_order, "adaptive": ff_adaptive}
+                                 if ff_depth else None)},
         "s_per_grad_eval": grad_ms / 1e3,
         "kernels": {
             "repulsion": {"ms_per_step": rep["ms"] / args.steps, "launches_per_step":

@@ -35,7 +35,7 @@ def fixed_step(prm: api.Params, rho_mass: float, rule: str, eta_fixed: float) ->
 def run(workload: configs.Workload, precision: str, iters: int, device="cuda:0",
         out=None, log_every: int = 1, rotation_variant: bool = False, kernel: str = "distance",
         eps: float = 0.0, eta_rule: str = "fixed", graph: bool = False,
-        far_field: tuple = (0, 5)):
+        far_field: tuple = (0, 5, False)):
     """Runs `iters` projected gradient steps; returns the list of records.
 
     With graph=True the step runs as two captured HIP graphs (fixed-step and
@@ -47,7 +47,8 @@ def run(workload: configs.Workload, precision: str, iters: int, device="cuda:0",
     prm = api.Params(workload.n_shots, workload.n_samples, workload.grid, precision=precision,
                      half_width=workload.half_width, eps=eps, a_max=a, b_max=b, te_index=0,
                      n_pit=workload.n_pit, rotation_variant=rotation_variant, kernel=kernel,
-                     far_field_depth=far_field[0], far_field_order=far_field[1])
+                     far_field_depth=far_field[0], far_field_order=far_field[1],
+                     far_field_adaptive=bool(far_field[2:3] and far_field[2]))
     rho_host = workload.density()
     K = torch.tensor(workload.trajectory(), dtype=prm.dtype, device=dev)
     rho = torch.tensor(rho_host, dtype=prm.dtype, device=dev)
@@ -123,6 +124,16 @@ def _run_graph(K, rho, prm, state, eta, iters, precision, viol0, out, log_every)
     return records, K
 
 
+def parse_far_field(spec):
+    """'DEPTH,ORDER' or 'DEPTH,ORDER,adaptive' -> (depth, order, adaptive); None -> off."""
+    if not spec:
+        return 0, 5, False
+    f = spec.split(",")
+    if len(f) not in (2, 3) or (len(f) == 3 and f[2] != "adaptive"):
+        raise ValueError(f"far field spec {spec!r}: expected DEPTH,ORDER[,adaptive]")
+    return int(f[0]), int(f[1]), len(f) == 3
+
+
 def _level_depth(depth: int, d: int) -> int:
     """Octree depth of the far field at decimation level d: 8^depth leaves for
     p / 2^d samples keep about as many samples per leaf when the depth drops by
@@ -162,7 +173,9 @@ def multiresolution(K0: torch.Tensor, rho: torch.Tensor, prm_full: api.Params, l
                          rotation_variant=prm_full.rotation_variant, kernel=prm_full.kernel,
                          attraction_field=prm_full.attraction_field,
                          far_field_depth=_level_depth(prm_full.far_field_depth, d),
-                         far_field_order=prm_full.far_field_order)
+                         far_field_order=prm_full.far_field_order,
+                         far_field_adaptive=(prm_full.far_field_adaptive and
+                                             _level_depth(prm_full.far_field_depth, d) > 0))
         if K.shape[1] != prm.p:
             raise ValueError(f"level {d}: K has {K.shape[1]} samples, expected {prm.p}")
         eta = fixed_step(prm, float(rho.sum().item()), eta_rule,
@@ -210,8 +223,9 @@ def main():
                     help="run the single-level loop as captured HIP graphs")
     ap.add_argument("--n-pit", type=int, default=None,
                     help="projection iterations (default: the workload's)")
-    ap.add_argument("--far-field", default=None, metavar="DEPTH,ORDER",
-                    help="repulsion by the Chebyshev fast multipole method (e.g. 5,6)")
+    ap.add_argument("--far-field", default=None, metavar="DEPTH,ORDER[,adaptive]",
+                    help="repulsion by the Chebyshev fast multipole method (e.g. 5,6 or "
+                         "5,6,adaptive)")
     args = ap.parse_args()
     w = configs.WORKLOADS[args.workload]
     if args.n_pit is not None:
@@ -219,13 +233,13 @@ def main():
     precision = args.precision or w.precision
     iters = args.iters if args.iters is not None else w.n_iters
     api.load_library()
-    ffd, ffo = (int(v) for v in args.far_field.split(",")) if args.far_field else (0, 5)
+    ffd, ffo, ffa = parse_far_field(args.far_field)
     out = open(args.out, "a") if args.out else None
     try:
         if args.levels == 0 and not args.field:
             run(w, precision, iters, out=out, log_every=args.log_every,
                 rotation_variant=args.rotation_variant, kernel=args.kernel, eps=args.eps,
-                eta_rule=args.eta, graph=args.graph, far_field=(ffd, ffo))
+                eta_rule=args.eta, graph=args.graph, far_field=(ffd, ffo, ffa))
         else:
             dev = torch.device("cuda:0")
             a, b = api.alpha_beta(configs.GMAX, configs.SMAX, configs.RASTER_DT,
@@ -235,7 +249,7 @@ def main():
                              half_width=w.half_width, a_max=a, b_max=b, te_index=0,
                              n_pit=w.n_pit, rotation_variant=args.rotation_variant,
                              kernel=args.kernel, eps=args.eps, far_field_depth=ffd,
-                             far_field_order=ffo)
+                             far_field_order=ffo, far_field_adaptive=ffa)
             from . import inputs
             K0 = inputs.radial_spokes(w.n_shots, w.n_samples >> args.levels, w.half_width,
                                       w.seed, w.jitter)
