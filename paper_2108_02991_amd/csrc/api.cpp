@@ -448,7 +448,7 @@ int run_far_field(const spk_params *prm, const void *kx, const void *ky, const v
     f.eps = prm->eps;
     f.acc = w.acc_r();
     f.ld = L.ld;
-    f.near_tpb = sweep_targets_per_block(prm->precision);
+    f.near_tpb = near_targets_per_block(prm->precision);
     f.box_part = w.at<double>(L.fmm_box_part);
     f.box = w.at<double>(L.fmm_box);
     f.keys_in = w.at<uint32_t>(L.fmm_keys_in);

@@ -50,6 +50,10 @@ constexpr int64_t kMaxGrid = 1024;
 
 // Targets handled by one block of a sweep (blockDim * targets per lane).
 int sweep_targets_per_block(int precision);
+// The near-field kernel runs one wave per block, so that cells with few
+// targets leave few lanes idle; near_targets_per_block() targets per block.
+constexpr int kNearBlock = 64;
+int near_targets_per_block(int precision);
 
 // Pair kernels H of the sweeps.
 constexpr int kKernelDistance = 0;   // sqrt(|d|^2 + eps^2)

@@ -408,7 +408,8 @@ void sweep_cells_kernel(SweepLaunch l)
 // cell-sorted samples: nine runs of three cells along x in plain numbering,
 // 27 single cells in fine numbering.  The block streams the runs as one
 // sequence, in run order, through LDS tiles of kSampleTile sources, so tiles
-// fill across run boundaries.  Block b takes chunk b - chunk_start[cell] of
+// fill across run boundaries.  Blocks are one wave (kNearBlock threads), each
+// with kNearBlock * R targets.  Block b takes chunk b - chunk_start[cell] of
 // the cell with chunk_start[cell] <= b < chunk_start[cell + 1]; the pair
 // arithmetic and the accumulation are those of the sample sweep, and the sums
 // are written (not added) to the rows of targets in [t0, t0 + nt).
@@ -420,7 +421,7 @@ __device__ inline int64_t fine_index(int64_t x, int64_t y, int64_t z, int64_t si
 }
 
 template <int MODE, int R, bool ENERGY, int KERN>
-__global__ __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(min_waves<MODE>())))
+__global__ __launch_bounds__(kNearBlock) __attribute__((amdgpu_waves_per_eu(min_waves<MODE>())))
 void near_kernel(NearLaunch l)
 {
     using T = typename ModeT<MODE>::T;
@@ -482,14 +483,14 @@ void near_kernel(NearLaunch l)
     }
     __syncthreads();
     const int64_t total = run_pre[27];
-    const int64_t first = t_lo + (b - l.chunk_start[cell]) * (int64_t)(BLK * R);
+    const int64_t first = t_lo + (b - l.chunk_start[cell]) * (int64_t)(kNearBlock * R);
     const int64_t last = t_hi - 1;
     const T *xs = static_cast<const T *>(l.xs), *ys = static_cast<const T *>(l.ys),
             *zs = static_cast<const T *>(l.zs);
     T xi[R], yi[R], zi[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        int64_t j = first + threadIdx.x + r * BLK;
+        int64_t j = first + threadIdx.x + r * kNearBlock;
         j = j < last ? j : last;
         xi[r] = xs[j];
         yi[r] = ys[j];
@@ -500,7 +501,7 @@ void near_kernel(NearLaunch l)
     int run = 0;  // run of this thread's next source (sources are read in increasing order)
     for (int64_t base = 0; base < total; base += kSampleTile) {
         const int n = (int)((total - base) < kSampleTile ? (total - base) : kSampleTile);
-        for (int j = threadIdx.x; j < n; j += BLK) {
+        for (int j = threadIdx.x; j < n; j += kNearBlock) {
             const int64_t v = base + j;
             while (run_pre[run + 1] <= v)
                 ++run;
@@ -560,7 +561,7 @@ void near_kernel(NearLaunch l)
     }
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        const int64_t j = first + threadIdx.x + r * BLK;
+        const int64_t j = first + threadIdx.x + r * kNearBlock;
         if (j > last)
             continue;
         const int64_t i = (int64_t)l.order[j] - l.t0;
@@ -581,7 +582,7 @@ hipError_t launch_near_mode(const NearLaunch &l, hipStream_t s)
 {
     constexpr int R = lanes_targets<MODE>();
     hipLaunchKernelGGL((near_kernel<MODE, R, ENERGY, KERN>), dim3((unsigned)l.max_blocks),
-                       dim3(BLK), 0, s, l);
+                       dim3(kNearBlock), 0, s, l);
     return hipGetLastError();
 }
 
@@ -660,6 +661,12 @@ hipError_t launch_near(const NearLaunch &l, hipStream_t s)
 int sweep_targets_per_block(int precision)
 {
     return BLK * (precision == kPlain64 ? lanes_targets<kPlain64>() : lanes_targets<kComp>());
+}
+
+int near_targets_per_block(int precision)
+{
+    return kNearBlock *
+           (precision == kPlain64 ? lanes_targets<kPlain64>() : lanes_targets<kComp>());
 }
 
 hipError_t launch_sweep_samples(const SweepLaunch &l, hipStream_t s)
