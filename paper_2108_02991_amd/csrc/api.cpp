@@ -241,7 +241,7 @@ struct Layout {
            fmm_vals_out = 0, fmm_xs = 0, fmm_start = 0, fmm_chunks = 0, fmm_chunk_start = 0,
            fmm_temp = 0, fmm_temp_bytes = 0, fmm_A = 0, fmm_Tm = 0, fmm_chunks_fine = 0,
            fmm_chunk_start_fine = 0, fmm_refined = 0, fmm_tmask_fine = 0, fmm_tflag = 0,
-           fmm_tscan = 0, fmm_tlist = 0;
+           fmm_tscan = 0, fmm_tlist = 0, fmm_Tu = 0, fmm_Td = 0;
     size_t fmm_W[kFmmMaxDepth + 1] = {}, fmm_L[kFmmMaxDepth + 1] = {},
            fmm_occ[kFmmMaxDepth + 1] = {};
     size_t total = 0;
@@ -327,6 +327,8 @@ Layout make_layout(const spk_params *prm)
         }
         L.fmm_A = take(sizeof(double) * fmm_table_doubles(prm->far_field_order) * (F - 1));
         L.fmm_Tm = take(sizeof(double) * 8 * n3 * n3);
+        L.fmm_Tu = take(sizeof(double) * fmm_trans_doubles(n));
+        L.fmm_Td = take(sizeof(double) * fmm_trans_doubles(n));
     }
     L.total = off + 256;   // slack for aligning the caller's base pointer
     return L;
@@ -481,6 +483,8 @@ int run_far_field(const spk_params *prm, const void *kx, const void *ky, const v
     }
     f.A = w.at<double>(L.fmm_A);
     f.Tm = w.at<double>(L.fmm_Tm);
+    f.Tu = w.at<double>(L.fmm_Tu);
+    f.Td = w.at<double>(L.fmm_Td);
     Timed tm(SPK_KIND_REPULSION, 0.0, s);
     SPK_HIP(launch_fmm_repulsion(f, s), "far-field repulsion");
     return SPK_OK;

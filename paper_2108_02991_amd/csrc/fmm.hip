@@ -451,36 +451,6 @@ __global__ __launch_bounds__(EW) void transfer_kernel(Cheb ch, double *Tm)
     Tm[e] = v;
 }
 
-// ------------------------------------------------------------------ M2M
-template <int N>
-__global__ __launch_bounds__(EW) void m2m_kernel(Level par, Level chd, const double *Tm)
-{
-    constexpr int N3 = N * N * N;
-    const int64_t side = par.side;
-    const int64_t cell = blockIdx.x;
-    const int64_t ix = cell % side, iy = (cell / side) % side, iz = cell / (side * side);
-    int32_t any = 0;
-    for (int pos = 0; pos < 8; ++pos)
-        any |= chd.occ[slot(2 * ix + (pos & 1), 2 * iy + ((pos >> 1) & 1),
-                            2 * iz + ((pos >> 2) & 1), chd.P)];
-    if (!any)
-        return;                      // W stays zero
-    if (threadIdx.x == 0)
-        par.occ[slot(ix, iy, iz, par.P)] = 1;
-    for (int m = threadIdx.x; m < N3; m += EW) {
-        double a = 0.0;
-        for (int pos = 0; pos < 8; ++pos) {
-            const int64_t cxi = 2 * ix + (pos & 1), cyi = 2 * iy + ((pos >> 1) & 1),
-                          czi = 2 * iz + ((pos >> 2) & 1);
-            const double *wc = chd.W + slot(cxi, cyi, czi, chd.P) * N3;
-            const double *t = Tm + ((int64_t)pos * N3 + m) * N3;
-            for (int l = 0; l < N3; ++l)
-                a += t[l] * wc[l];
-        }
-        par.W[slot(ix, iy, iz, par.P) * N3 + m] = a;
-    }
-}
-
 // ------------------------------------------------------------------ M2L tables
 // The M2L kernels run on the FP64 matrix cores.  The table of level l holds,
 // for every offset o, A_o^T: At[o][k][row] = K_c(x_m - y_k), row = c*n^3 + m,
@@ -609,26 +579,148 @@ struct M2lPlan {
     int64_t ntiles;                // column tiles of all levels and classes
 };
 
+// The matrix-core loop shared by M2L, M2M and L2L: acc += sum over the nlist
+// entries a and the k tiles of A_a[rows][k] B_a[k][columns].  A_a is stored
+// k-major with row stride RP and padded with zeros to KP values of k;
+// abase(a) points at its row row0 for k = 0.  Column cl of B_a holds
+// bbase(a)[colsrc[cl] + k] for k < KV (colsrc < 0: a zero column).  Tiles of
+// TK k-values go through two LDS buffers; the next tile is read into
+// registers while the matrix cores work on the current one.  Wave w holds
+// rows 64 (w & 1) .. and columns (TN/2)(w >> 1) .. of the block's tile.
+template <int RP, int KP, int KV, typename AFn, typename BFn>
+__device__ inline void mfma_gemm(int nlist, AFn abase, BFn bbase, const int64_t *colsrc,
+                                 double (*As)[TK][TM], double (*Bs)[TK][TN + 1],
+                                 dbl4 (&acc)[4][TN / 32])
+{
+    constexpr int KT = KP / TK, FM = 4, FN = TN / 32;
+    constexpr int LA = TK * TM / (2 * kM2lThreads), LB = TK * TN / kM2lThreads;
+    const int t = threadIdx.x, lane = t % 64, wave = t / 64;
+    const int nit = nlist * KT;
+    dbl2 ra[LA];
+    double rb[LB];
+    auto load = [&](int it) {
+        const int a = it / KT, kt = it % KT;
+        const double *Ao = abase(a) + (int64_t)kt * TK * RP;
+#pragma unroll
+        for (int i = 0; i < LA; ++i) {
+            const int e = t + kM2lThreads * i, k = e / (TM / 2), r = 2 * (e % (TM / 2));
+            ra[i] = *reinterpret_cast<const dbl2 *>(Ao + (int64_t)k * RP + r);
+        }
+        const double *Bc = bbase(a);
+#pragma unroll
+        for (int i = 0; i < LB; ++i) {
+            const int e = t + kM2lThreads * i, k = e % TK, cl = e / TK;
+            const int kk = kt * TK + k;
+            const int64_t cs = colsrc[cl];
+            rb[i] = (cs >= 0 && kk < KV) ? Bc[cs + kk] : 0.0;
+        }
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+        for (int i = 0; i < LA; ++i) {
+            const int e = t + kM2lThreads * i, k = e / (TM / 2), r = 2 * (e % (TM / 2));
+            *reinterpret_cast<dbl2 *>(&As[buf][k][r]) = ra[i];
+        }
+#pragma unroll
+        for (int i = 0; i < LB; ++i) {
+            const int e = t + kM2lThreads * i, k = e % TK, cl = e / TK;
+            Bs[buf][k][cl] = rb[i];
+        }
+    };
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+            acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
+    const int wr = (wave & 1) * 64, wc = (wave >> 1) * (TN / 2);
+    const int fr = lane % 16, fk = lane / 16;
+    if (nit > 0) {
+        load(0);
+        store(0);
+    }
+    __syncthreads();
+    for (int it = 0; it < nit; ++it) {
+        const int buf = it & 1;
+        if (it + 1 < nit)
+            load(it + 1);
+#pragma unroll
+        for (int k0 = 0; k0 < TK; k0 += 4) {
+            double a[FM], bb[FN];
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+                a[i] = As[buf][k0 + fk][wr + 16 * i + fr];
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+                bb[j] = Bs[buf][k0 + fk][wc + 16 * j + fr];
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+#pragma unroll
+                for (int j = 0; j < FN; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], bb[j], acc[i][j], 0,
+                                                                     0, 0);
+        }
+        if (it + 1 < nit)
+            store(buf ^ 1);
+        __syncthreads();
+    }
+}
+
+// Writes the accumulators: out[outidx[column] + row] (= or +=) for rows below
+// nrows and columns with outidx >= 0.  Register r of a lane of
+// v_mfma_f64_16x16x4 holds row lane/16 + 4r of column lane % 16.
+template <bool ADD>
+__device__ inline void mfma_store(const dbl4 (&acc)[4][TN / 32], const int64_t *outidx, int row0,
+                                  int nrows, double *out)
+{
+    constexpr int FM = 4, FN = TN / 32;
+    const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+    const int wr = (wave & 1) * 64, wc = (wave >> 1) * (TN / 2);
+    const int fr = lane % 16, fk = lane / 16;
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+        const int64_t o = outidx[wc + 16 * j + fr];
+        if (o < 0)
+            continue;
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = row0 + wr + 16 * i + fk + 4 * r;
+                if (row < nrows) {
+                    if (ADD)
+                        out[o + row] += acc[i][j][r];
+                    else
+                        out[o + row] = acc[i][j][r];
+                }
+            }
+    }
+}
+
+// Tile of a block: hardware block b runs on XCD b % 8; block b = 8k + x takes
+// column tile 8 floor(k / ntr) + x and row tile k % ntr.
+__device__ inline int64_t block_tile(int ntr, int &rt)
+{
+    const int64_t b = blockIdx.x, kb = b / kXcds;
+    rt = (int)(kb % ntr);
+    return kXcds * (kb / ntr) + b % kXcds;
+}
+
 template <int N>
 __global__ __launch_bounds__(kM2lThreads) void m2l_kernel(M2lPlan plan)
 {
     using S = M2lShape<N>;
-    constexpr int N3 = S::N3, ROWS = S::ROWS, RP = S::RP, KP = S::KP, KT = S::KT;
-    constexpr int FM = 4, FN = TN / 32;  // 16 x 16 fragments per wave
-    constexpr int BPAD = TN + 1;         // padded LDS row of the weights tile
+    constexpr int N3 = S::N3, ROWS = S::ROWS, RP = S::RP, KP = S::KP;
     __shared__ __align__(16) double As[2][TK][TM];
-    __shared__ __align__(16) double Bs[2][TK][BPAD];
-    __shared__ int64_t colpad[TN];
+    __shared__ __align__(16) double Bs[2][TK][TN + 1];
+    __shared__ int64_t colpad[TN], colsrc[TN], outidx[TN];
     __shared__ int64_t list_shift[kMaxList];
     __shared__ int16_t list_o[kMaxList];
     __shared__ int8_t list_cs[kMaxList];
     __shared__ int8_t flag[kOffsets];
     __shared__ int nlist;
 
-    const int ntiles_r = plan.ntr;
-    const int64_t b = blockIdx.x, kb = b / kXcds;
-    int64_t tile = kXcds * (kb / ntiles_r) + b % kXcds;
-    const int rt = (int)(kb % ntiles_r);
+    int rt;
+    int64_t tile = block_tile(plan.ntr, rt);
     if (tile >= plan.ntiles)
         return;
     // the tile's level (a select, not an index, keeps the plan in SGPRs)
@@ -670,6 +762,8 @@ __global__ __launch_bounds__(kM2lThreads) void m2l_kernel(M2lPlan plan)
             }
         }
         colpad[t] = pc;
+        colsrc[t] = pc >= 0 ? pc * N3 : -1;
+        outidx[t] = pc >= 0 ? ((int64_t)ct * P3 + pc) * ROWS : -1;
     }
     if (!__syncthreads_or(mine))
         return;
@@ -713,121 +807,172 @@ __global__ __launch_bounds__(kM2lThreads) void m2l_kernel(M2lPlan plan)
             nlist = base;
     }
     __syncthreads();
-    const int nit = nlist * KT;  // 0: no source, the tile's expansions are zero
-
-    // per-thread share of a tile: A as TK rows of TM (two doubles a piece),
-    // W as TN cells of TK values (k fastest)
-    constexpr int LA = TK * TM / (2 * kM2lThreads), LB = TK * TN / kM2lThreads;
-    dbl2 ra[LA];
-    double rb[LB];
-    auto load = [&](int it) {
-        const int a = it / KT, kt = it % KT;
-        const double *Ao = At + ((int64_t)list_o[a] * KP + kt * TK) * RP + row0;
-#pragma unroll
-        for (int i = 0; i < LA; ++i) {
-            const int e = t + kM2lThreads * i, k = e / (TM / 2), r = 2 * (e % (TM / 2));
-            ra[i] = *reinterpret_cast<const dbl2 *>(Ao + (int64_t)k * RP + r);
-        }
-        const double *Bc = lev.W + ((int64_t)list_cs[a] * P3 + list_shift[a]) * N3;
-#pragma unroll
-        for (int i = 0; i < LB; ++i) {
-            const int e = t + kM2lThreads * i, k = e % TK, cl = e / TK;
-            const int kk = kt * TK + k;
-            const int64_t pc = colpad[cl];
-            rb[i] = (pc >= 0 && kk < N3) ? Bc[pc * N3 + kk] : 0.0;
-        }
-    };
-    auto store = [&](int buf) {
-#pragma unroll
-        for (int i = 0; i < LA; ++i) {
-            const int e = t + kM2lThreads * i, k = e / (TM / 2), r = 2 * (e % (TM / 2));
-            *reinterpret_cast<dbl2 *>(&As[buf][k][r]) = ra[i];
-        }
-#pragma unroll
-        for (int i = 0; i < LB; ++i) {
-            const int e = t + kM2lThreads * i, k = e % TK, cl = e / TK;
-            Bs[buf][k][cl] = rb[i];
-        }
-    };
-
-    dbl4 acc[FM][FN];
-#pragma unroll
-    for (int i = 0; i < FM; ++i)
-#pragma unroll
-        for (int j = 0; j < FN; ++j)
-            acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
-    const int wr = (wave & 1) * 64, wc = (wave >> 1) * (TN / 2);
-    const int fr = lane % 16, fk = lane / 16;
-
-    if (nit > 0) {
-        load(0);
-        store(0);
-    }
-    __syncthreads();
-    for (int it = 0; it < nit; ++it) {
-        const int buf = it & 1;
-        if (it + 1 < nit)
-            load(it + 1);
-#pragma unroll
-        for (int k0 = 0; k0 < TK; k0 += 4) {
-            double a[FM], bb[FN];
-#pragma unroll
-            for (int i = 0; i < FM; ++i)
-                a[i] = As[buf][k0 + fk][wr + 16 * i + fr];
-#pragma unroll
-            for (int j = 0; j < FN; ++j)
-                bb[j] = Bs[buf][k0 + fk][wc + 16 * j + fr];
-#pragma unroll
-            for (int i = 0; i < FM; ++i)
-#pragma unroll
-                for (int j = 0; j < FN; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], bb[j], acc[i][j], 0,
-                                                                     0, 0);
-        }
-        if (it + 1 < nit)
-            store(buf ^ 1);
-        __syncthreads();
-    }
-
-    // accumulator layout of v_mfma_f64_16x16x4: register r of a lane holds row
-    // lane/16 + 4r of column lane % 16
-    double *Cc = lev.L + (int64_t)ct * P3 * ROWS;
-#pragma unroll
-    for (int j = 0; j < FN; ++j) {
-        const int64_t pc = colpad[wc + 16 * j + fr];
-        if (pc < 0)
-            continue;
-#pragma unroll
-        for (int i = 0; i < FM; ++i)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int row = row0 + wr + 16 * i + fk + 4 * r;
-                if (row < ROWS)
-                    Cc[pc * ROWS + row] = acc[i][j][r];
-            }
-    }
+    // no source offset (nlist 0): the tile's expansions are zero
+    dbl4 acc[4][TN / 32];
+    const double *W = lev.W;
+    mfma_gemm<RP, KP, N3>(
+        nlist, [&](int a) { return At + (int64_t)list_o[a] * KP * RP + row0; },
+        [&](int a) { return W + ((int64_t)list_cs[a] * P3 + list_shift[a]) * N3; }, colsrc, As, Bs,
+        acc);
+    mfma_store<false>(acc, outidx, row0, ROWS, lev.L);
 }
 
-// ------------------------------------------------------------------ L2L
+// ------------------------------------------------------------------ M2M, L2L on the matrix cores
+// Both translations are products with the 8 transfer matrices T[pos][m][l]
+// (child position pos, parent node m, child node l):
+//   M2M  W_parent[m] = sum_pos sum_l T[pos][m][l] W_child(pos)[l]
+//   L2L  L_child[c][l] += sum_m T[pos][m][l] L_parent[c][m]
+// Their tables, k-major and padded like the M2L tables:
+//   Tu[pos][k = l][row = m] and Td[pos][k = m][row = l].
 template <int N>
-__global__ __launch_bounds__(EW) void l2l_kernel(Level par, Level chd, const double *Tm)
+struct TransShape {
+    static constexpr int N3 = N * N * N;
+    static constexpr int RP = (N3 + TM - 1) / TM * TM;
+    static constexpr int KP = (N3 + TK - 1) / TK * TK;
+};
+
+template <int N>
+__global__ __launch_bounds__(EW) void transfer_tables_kernel(const double *Tm, double *Tu,
+                                                             double *Td)
 {
-    constexpr int N3 = N * N * N;
-    const int64_t side = chd.side;
-    const int64_t cell = blockIdx.x;
-    const int64_t ix = cell % side, iy = (cell / side) % side, iz = cell / (side * side);
-    if (!chd.tmask[slot(ix, iy, iz, chd.P)])
-        return;                      // nothing reads this cell's expansion
-    const int pos = (int)((ix & 1) + 2 * (iy & 1) + 4 * (iz & 1));
-    const double *lp = par.L + slot(ix >> 1, iy >> 1, iz >> 1, par.P) * 4 * N3;
-    double *lc = chd.L + slot(ix, iy, iz, chd.P) * 4 * N3;
-    for (int e = threadIdx.x; e < 4 * N3; e += EW) {
-        const int c = e / N3, l = e % N3;
-        double a = 0.0;
-        for (int m = 0; m < N3; ++m)
-            a += lp[c * N3 + m] * Tm[((int64_t)pos * N3 + m) * N3 + l];
-        lc[e] += a;
+    using S = TransShape<N>;
+    constexpr int N3 = S::N3;
+    const int64_t e = (int64_t)blockIdx.x * EW + threadIdx.x;
+    if (e >= (int64_t)8 * S::KP * S::RP)
+        return;
+    const int pos = (int)(e / ((int64_t)S::KP * S::RP));
+    const int k = (int)((e / S::RP) % S::KP), row = (int)(e % S::RP);
+    const bool in = k < N3 && row < N3;
+    Tu[e] = in ? Tm[((int64_t)pos * N3 + row) * N3 + k] : 0.0;
+    Td[e] = in ? Tm[((int64_t)pos * N3 + k) * N3 + row] : 0.0;
+}
+
+// M2M of one level: block tiles of parent cells (class ct, sub-grid order) by
+// parent nodes.  A parent's 8 children all sit at its own coordinates in the
+// children's level sub-grids (class pos).  Marks occupied parents.
+template <int N>
+__global__ __launch_bounds__(kM2lThreads) void m2m_kernel(Level par, Level chd, const double *Tu,
+                                                          int ntr, int64_t ntc)
+{
+    using S = TransShape<N>;
+    constexpr int N3 = S::N3, RP = S::RP, KP = S::KP;
+    __shared__ __align__(16) double As[2][TK][TM];
+    __shared__ __align__(16) double Bs[2][TK][TN + 1];
+    __shared__ int64_t colsrc[TN], outidx[TN];
+    __shared__ int list_pos[8];
+    __shared__ int nlist;
+    int rt;
+    const int64_t tile = block_tile(ntr, rt);
+    if (tile >= 8 * ntc)
+        return;
+    const int64_t cti = tile % ntc;
+    const int ct = (int)(tile / ntc);
+    const int64_t P = par.P, P3 = P * P * P, Q = par.side / 2, Q3 = Q * Q * Q;
+    const int64_t Pc = chd.P, Pc3 = Pc * Pc * Pc;
+    const int t = threadIdx.x, lane = t % 64;
+    const int row0 = rt * TM;
+    int mine = 0;
+    if (t < TN) {
+        const int64_t c = cti * TN + t;
+        int64_t src = -1, out = -1;
+        if (c < Q3) {
+            const int64_t ux = c % Q, uy = (c / Q) % Q, uz = c / (Q * Q);
+            const int64_t ix = 2 * ux + (ct & 1), iy = 2 * uy + ((ct >> 1) & 1),
+                          iz = 2 * uz + (ct >> 2);
+            const int64_t cpad = (ix + 2) + Pc * ((iy + 2) + Pc * (iz + 2));
+            for (int pos = 0; pos < 8; ++pos)
+                mine |= chd.occ[pos * Pc3 + cpad];
+            const int64_t pc = (ux + 2) + P * ((uy + 2) + P * (uz + 2));
+            if (mine && rt == 0)
+                par.occ[ct * P3 + pc] = 1;
+            src = cpad * N3;
+            out = ((int64_t)ct * P3 + pc) * N3;
+        }
+        colsrc[t] = src;
+        outidx[t] = out;
     }
+    if (!__syncthreads_or(mine))
+        return;                      // the tile's weights stay zero
+    if (t < 64) {
+        int base = 0;
+        for (int pos = 0; pos < 8; ++pos) {
+            int v = 0;
+            for (int c = lane; c < TN; c += 64)
+                if (colsrc[c] >= 0 && chd.occ[pos * Pc3 + colsrc[c] / N3])
+                    v = 1;
+            if (__ballot(v) != 0) {
+                if (lane == 0)
+                    list_pos[base] = pos;
+                ++base;
+            }
+        }
+        if (lane == 0)
+            nlist = base;
+    }
+    __syncthreads();
+    dbl4 acc[4][TN / 32];
+    const double *Wc = chd.W;
+    mfma_gemm<RP, KP, N3>(
+        nlist, [&](int a) { return Tu + (int64_t)list_pos[a] * KP * RP + row0; },
+        [&](int a) { return Wc + (int64_t)list_pos[a] * Pc3 * N3; }, colsrc, As, Bs, acc);
+    mfma_store<false>(acc, outidx, row0, N3, par.W);
+}
+
+// L2L into one level: block tiles of (child cell, component) columns, 4 per
+// cell, of child class ct (the cells whose expansion is used, from the class's
+// list where there is one) by child nodes.  A child at sub-grid coordinates u
+// of class ct has its parent at coordinates u of the parents' level.
+template <int N>
+__global__ __launch_bounds__(kM2lThreads) void l2l_kernel(Level par, Level chd, const double *Td,
+                                                          int ntr, int64_t ntc)
+{
+    using S = TransShape<N>;
+    constexpr int N3 = S::N3, RP = S::RP, KP = S::KP;
+    __shared__ __align__(16) double As[2][TK][TM];
+    __shared__ __align__(16) double Bs[2][TK][TN + 1];
+    __shared__ int64_t colsrc[TN], outidx[TN];
+    int rt;
+    const int64_t tile = block_tile(ntr, rt);
+    if (tile >= 8 * ntc)
+        return;
+    const int64_t cti = tile % ntc;
+    const int ct = (int)(tile / ntc);
+    const int64_t P = chd.P, P3 = P * P * P, Q = chd.side / 2, Q3 = Q * Q * Q;
+    const int64_t Pp = par.P;
+    const int t = threadIdx.x;
+    const int row0 = rt * TM;
+    int mine = 0;
+    if (t < TN) {
+        const int64_t col = cti * TN + t, c = col / 4, comp = col % 4;
+        int64_t pc = -1;
+        if (chd.tlist) {
+            const int64_t k = chd.tscan[ct * Q3] + c;
+            if (k < chd.tscan[(ct + 1) * Q3])
+                pc = chd.tlist[k];
+        } else if (c < Q3) {
+            const int64_t ux = c % Q, uy = (c / Q) % Q, uz = c / (Q * Q);
+            pc = (ux + 2) + P * ((uy + 2) + P * (uz + 2));
+            if (!chd.tmask[ct * P3 + pc])
+                pc = -1;
+        }
+        int64_t src = -1, out = -1;
+        if (pc >= 0) {
+            mine = 1;
+            const int64_t ux = pc % P - 2, uy = (pc / P) % P - 2, uz = pc / (P * P) - 2;
+            src = slot(ux, uy, uz, Pp) * 4 * N3 + comp * N3;
+            out = ((int64_t)ct * P3 + pc) * 4 * N3 + comp * N3;
+        }
+        colsrc[t] = src;
+        outidx[t] = out;
+    }
+    if (!__syncthreads_or(mine))
+        return;
+    dbl4 acc[4][TN / 32];
+    const double *Lp = par.L;
+    mfma_gemm<RP, KP, N3>(
+        1, [&](int) { return Td + (int64_t)ct * KP * RP + row0; }, [&](int) { return Lp; },
+        colsrc, As, Bs, acc);
+    mfma_store<true>(acc, outidx, row0, N3, chd.L);
 }
 
 // ------------------------------------------------------------------ L2P
@@ -904,6 +1049,17 @@ size_t fmm_level_cells(int level)
     return (size_t)(8 * P * P * P);
 }
 
+size_t fmm_trans_doubles(int order)
+{
+    switch (order) {
+    case 3: return (size_t)8 * TransShape<3>::KP * TransShape<3>::RP;
+    case 4: return (size_t)8 * TransShape<4>::KP * TransShape<4>::RP;
+    case 5: return (size_t)8 * TransShape<5>::KP * TransShape<5>::RP;
+    case 6: return (size_t)8 * TransShape<6>::KP * TransShape<6>::RP;
+    default: return 0;
+    }
+}
+
 size_t fmm_table_doubles(int order)
 {
     switch (order) {
@@ -929,11 +1085,15 @@ size_t fmm_sort_temp_bytes(int64_t p, int depth)
 {
     const int64_t nleaves = int64_t(1) << (3 * depth);
     size_t a = 0, b = 0;
-    hipcub::DeviceRadixSort::SortPairs(nullptr, a, (const uint32_t *)nullptr, (uint32_t *)nullptr,
-                                       (const uint32_t *)nullptr, (uint32_t *)nullptr, (int)p, 0,
-                                       3 * depth);
-    hipcub::DeviceScan::ExclusiveSum(nullptr, b, (const int32_t *)nullptr, (int32_t *)nullptr,
-                                     (int)(nleaves + 1));
+    // a failed query leaves 0; the sort or scan then reports the short buffer
+    if (hipcub::DeviceRadixSort::SortPairs(nullptr, a, (const uint32_t *)nullptr,
+                                           (uint32_t *)nullptr, (const uint32_t *)nullptr,
+                                           (uint32_t *)nullptr, (int)p, 0,
+                                           3 * depth) != hipSuccess)
+        a = 0;
+    if (hipcub::DeviceScan::ExclusiveSum(nullptr, b, (const int32_t *)nullptr, (int32_t *)nullptr,
+                                         (int)(nleaves + 1)) != hipSuccess)
+        b = 0;
     return a > b ? a : b;
 }
 
@@ -1020,11 +1180,21 @@ hipError_t run_typed(const FmmLaunch &f, hipStream_t s)
                                lev[l].tmask, no);
     }
     hipLaunchKernelGGL(transfer_kernel<N>, dim3(ew_blocks(8 * N3 * N3)), dim3(EW), 0, s, ch, f.Tm);
+    using TS = TransShape<N>;
+    const int64_t ntt = (int64_t)8 * TS::KP * TS::RP;
+    hipLaunchKernelGGL(transfer_tables_kernel<N>, dim3(ew_blocks(ntt)), dim3(EW), 0, s, f.Tm, f.Tu,
+                       f.Td);
+    const int ntr_t = TS::RP / TM;
+    auto trans_blocks = [&](int64_t ntc) {
+        return (unsigned)((8 * ntc + kXcds - 1) / kXcds * kXcds * ntr_t);
+    };
     hipLaunchKernelGGL((p2m_kernel<N, T>), dim3((unsigned)ncellsF), dim3(EW), 0, s, xs, ys, zs,
                        f.start, f.box, sideF, f.adaptive, lev[F], ch);
-    for (int l = F - 1; l >= 2; --l)
-        hipLaunchKernelGGL(m2m_kernel<N>, dim3((unsigned)(int64_t(1) << (3 * l))), dim3(EW), 0, s,
-                           lev[l], lev[l + 1], f.Tm);
+    for (int l = F - 1; l >= 2; --l) {
+        const int64_t Q = lev[l].side / 2, ntc = (Q * Q * Q + TN - 1) / TN;
+        hipLaunchKernelGGL(m2m_kernel<N>, dim3(trans_blocks(ntc)), dim3(kM2lThreads), 0, s, lev[l],
+                           lev[l + 1], f.Tu, ntr_t, ntc);
+    }
     if (f.adaptive) {
         // the refined level's target cells, listed per class in sub-grid order
         hipLaunchKernelGGL(tmask_kernel, dim3(ew_blocks(ncellsF)), dim3(EW), 0, s, lev[F],
@@ -1066,9 +1236,11 @@ hipError_t run_typed(const FmmLaunch &f, hipStream_t s)
     }
     const int64_t nblocks = (plan.ntiles + kXcds - 1) / kXcds * kXcds * plan.ntr;
     hipLaunchKernelGGL(m2l_kernel<N>, dim3((unsigned)nblocks), dim3(kM2lThreads), 0, s, plan);
-    for (int l = 3; l <= F; ++l)
-        hipLaunchKernelGGL(l2l_kernel<N>, dim3((unsigned)(int64_t(1) << (3 * l))), dim3(EW), 0, s,
-                           lev[l - 1], lev[l], f.Tm);
+    for (int l = 3; l <= F; ++l) {
+        const int64_t Q = lev[l].side / 2, ntc = (4 * Q * Q * Q + TN - 1) / TN;
+        hipLaunchKernelGGL(l2l_kernel<N>, dim3(trans_blocks(ntc)), dim3(kM2lThreads), 0, s,
+                           lev[l - 1], lev[l], f.Td, ntr_t, ntc);
+    }
     if ((e = hipGetLastError()) != hipSuccess)
         return e;
     // near field (exact pair sums over the 27 cells around each target's cell),
