@@ -84,12 +84,15 @@ enum {
     SPK_FLAG_ROTATION_VARIANT = 2,   /* constraint norms |.| are per-axis maxima (the
                                         l_inf bounds of Sec. "3D K-space sampling")
                                         instead of Euclidean norms                     */
-    SPK_FLAG_LOG_KERNEL = 4          /* H(d) = log(|d|^2 + eps^2) / 2, the logarithmic
+    SPK_FLAG_LOG_KERNEL = 4,         /* H(d) = log(|d|^2 + eps^2) / 2, the logarithmic
                                         kernel the "3D SPARKLING formulation" names as
                                         an alternative, regularised; needs eps > 0
                                         with eps^2 a normal number of the form's type,
                                         and the plain_fp64 or fp32_comp form
                                         (SPK_EUNSUPPORTED otherwise)                   */
+    SPK_FLAG_FIELD_DIRECT = 8        /* sparkling_field sums the node field directly
+                                        over the cells in the precision form instead
+                                        of by FP64 FFT convolution                      */
 };
 
 typedef struct {
@@ -179,6 +182,14 @@ int spk_lipschitz_bound(int64_t p, double eps, double rho_mass, int32_t flags,
                         double *lipschitz);
 
 /*
+ * Workspace bytes of sparkling_field for prm: the FFT buffers (two M^3
+ * complex doubles, M the power of two >= 2G + 1, at least 8; 4.3 GB at
+ * G = 192) when the field is taken by FFT, else spk_workspace_size(prm).
+ * Host only.
+ */
+int spk_field_workspace_size(const spk_params *prm, size_t *bytes);
+
+/*
  * Node field of the grid attraction (Sec. "Evaluating F^a and its gradient":
  * the discrete convolution of the sampled kernel with the sampled density,
  * computed once per density and evaluated off the grid by the trilinear
@@ -186,9 +197,13 @@ int spk_lipschitz_bound(int64_t p, double eps, double rho_mass, int32_t flags,
  * axis (the cell centres plus one node beyond each face), node
  * n = kx + (G+2)*(ky + (G+2)*kz).  field (device, K's type, 16-byte aligned
  * for float, 32 for double) receives 4*(G+2)^3 values laid out
- * [n][U, dU/dx, dU/dy, dU/dz] with U(x) = sum_v rho_v H(x - x_v), summed
- * directly over the cells in the precision form and with the kernel of prm
- * (a field is valid only with the kernel and eps it was built with).  Setting
+ * [n][U, dU/dx, dU/dy, dU/dz] with U(x) = sum_v rho_v H(x - x_v) for the
+ * kernel of prm (a field is valid only with the kernel and eps it was built
+ * with).  When 2G + 1 <= 1024 the convolution runs as FP64 FFTs of size M^3
+ * (exact up to FP64 rounding) and ws must hold spk_field_workspace_size(prm)
+ * bytes; with SPK_FLAG_FIELD_DIRECT, or for larger grids, it is summed
+ * directly over the cells in the precision form with the workspace of
+ * spk_workspace_size(prm).  Setting
  * prm->attraction_field to this buffer makes energy, gradient and step use
  * the interpolant for the attraction (valid for samples inside
  * [-L - h/2, L + h/2]^3; outside, the nearest node layer is extrapolated

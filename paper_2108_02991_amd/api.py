@@ -22,6 +22,7 @@ PRECISIONS = {"plain_fp64": 0, "fp32_comp": 1, "fp32_naive": 2, "fp32_acc64": 3}
 FLAG_DISCREPANCY = 1
 FLAG_ROTATION_VARIANT = 2
 FLAG_LOG_KERNEL = 4
+FLAG_FIELD_DIRECT = 8
 KERNELS = {"distance": 0, "log": FLAG_LOG_KERNEL}
 KIND_REPULSION, KIND_ATTRACTION, KIND_PROJECTION, KIND_OTHER, KIND_INTERPOLATION = 0, 1, 2, 3, 4
 
@@ -64,6 +65,7 @@ def load_library(path: Path | str | None = None):
         "spk_last_error": ([], ctypes.c_char_p),
         "spk_alpha_beta": ([_dbl] * 8 + [_vp, _vp], ctypes.c_int),
         "spk_workspace_size": ([_vp, _vp], ctypes.c_int),
+        "spk_field_workspace_size": ([_vp, _vp], ctypes.c_int),
         "spk_lipschitz_bound": ([_i64, _dbl, _dbl, _i32, _vp], ctypes.c_int),
         "sparkling_energy": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp], ctypes.c_int),
         "sparkling_field": ([_vp, _vp, _vp, _vp, _sz, _vp], ctypes.c_int),
@@ -114,6 +116,7 @@ class Params:
     far_field_depth: int = 0                         # 0: exact repulsion; 2..7: octree depth
     far_field_order: int = 5                         # Chebyshev nodes per axis (3..6)
     far_field_adaptive: bool = False                 # refine dense leaves once more
+    field_direct: bool = False                       # node field summed directly, not by FFT
     _c: SpkParams = field(default=None, repr=False, compare=False)
 
     @property
@@ -135,7 +138,8 @@ class Params:
                          self.n_pit,
                          (FLAG_DISCREPANCY if self.discrepancy else 0)
                          | (FLAG_ROTATION_VARIANT if self.rotation_variant else 0)
-                         | KERNELS[self.kernel],
+                         | KERNELS[self.kernel]
+                         | (FLAG_FIELD_DIRECT if self.field_direct else 0),
                          _vp(f.data_ptr()) if f is not None else None,
                          self.far_field_depth, self.far_field_order if self.far_field_depth else 0,
                          int(bool(self.far_field_adaptive)))
@@ -215,8 +219,14 @@ def attraction_field(rho: torch.Tensor, prm: Params) -> torch.Tensor:
     """
     _check_rho(rho, prm)
     out = torch.empty(((prm.grid + 2) ** 3, 4), dtype=prm.dtype, device=rho.device)
-    ws = workspace(prm, rho.device)
     c = prm.c()
+    n = _sz()
+    _check(load_library().spk_field_workspace_size(ctypes.byref(c), ctypes.byref(n)),
+           "spk_field_workspace_size")
+    if n.value <= workspace_size(prm):
+        ws = workspace(prm, rho.device)
+    else:   # the FFT buffers: a temporary workspace, freed on return
+        ws = torch.empty(n.value, dtype=torch.uint8, device=rho.device)
     _check(load_library().sparkling_field(ctypes.byref(c), _vp(rho.data_ptr()),
                                           _vp(out.data_ptr()), _vp(ws.data_ptr()), ws.numel(),
                                           _stream(rho)), "sparkling_field")

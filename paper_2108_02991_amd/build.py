@@ -17,7 +17,8 @@ OUT = PKG / "libsparkling.so"
 BUILD_DIR = ROOT / "_build"
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["sweep.hip", "reduce.hip", "project.hip", "field.hip", "fmm.hip", "api.cpp"]
+SOURCES = ["sweep.hip", "reduce.hip", "project.hip", "field.hip", "fftfield.hip", "fmm.hip",
+           "api.cpp"]
 
 # Packed FP32 instructions are disabled: scalar and float2 code must not be
 # turned into v_pk_* FP32 operations on this target.

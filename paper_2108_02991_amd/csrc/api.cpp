@@ -136,7 +136,8 @@ int check_params(const spk_params *prm, bool need_projection)
         return fail(SPK_EINVAL, "eps^2 must stay finite in the form's type");
     if (prm->te_index < -1 || prm->te_index >= prm->n_samples)
         return fail(SPK_EINVAL, "te_index must be -1 or in [0, n_samples)");
-    if (prm->flags & ~(SPK_FLAG_DISCREPANCY | SPK_FLAG_ROTATION_VARIANT | SPK_FLAG_LOG_KERNEL))
+    if (prm->flags & ~(SPK_FLAG_DISCREPANCY | SPK_FLAG_ROTATION_VARIANT | SPK_FLAG_LOG_KERNEL |
+                       SPK_FLAG_FIELD_DIRECT))
         return fail(SPK_EINVAL, "unknown flags 0x%x", prm->flags);
     if (prm->flags & SPK_FLAG_LOG_KERNEL) {
         if (prm->precision != SPK_PLAIN_FP64 && prm->precision != SPK_FP32_COMP)
@@ -704,6 +705,19 @@ int spk_workspace_size(const spk_params *prm, size_t *bytes)
     return SPK_OK;
 }
 
+int spk_field_workspace_size(const spk_params *prm, size_t *bytes)
+{
+    g_err.clear();
+    int rc = check_params(prm, false);
+    if (rc)
+        return rc;
+    if (!bytes)
+        return fail(SPK_EINVAL, "bytes is NULL");
+    const size_t fb = (prm->flags & SPK_FLAG_FIELD_DIRECT) ? 0 : field_fft_bytes(prm->grid);
+    *bytes = fb ? fb : make_layout(prm).total;
+    return SPK_OK;
+}
+
 int sparkling_grad(const spk_params *prm, const void *kx, const void *ky, const void *kz,
                    const void *rho, void *gx, void *gy, void *gz, int64_t tgt_begin,
                    int64_t tgt_end, double *pot_a, double *pot_r, double *energy, void *ws,
@@ -767,11 +781,26 @@ int sparkling_field(const spk_params *prm, const void *rho, void *field, void *w
     const size_t al = elt_size(prm->precision);
     if ((rc = check_ptr(rho, "rho", al)) || (rc = check_ptr(field, "field", 4 * al)))
         return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int64_t G = prm->grid, Mn = field_nodes(G);
+    const size_t fb = (prm->flags & SPK_FLAG_FIELD_DIRECT) ? 0 : field_fft_bytes(G);
+    if (fb) {
+        // FFT convolution in FP64 (its own workspace, spk_field_workspace_size)
+        if (!ws)
+            return fail(SPK_EINVAL, "workspace is NULL");
+        if (ws_bytes < fb)
+            return fail(SPK_EWORKSPACE, "workspace of %zu bytes, the FFT field needs %zu", ws_bytes,
+                        fb);
+        const int kern = (prm->flags & SPK_FLAG_LOG_KERNEL) ? kKernelLog : kKernelDistance;
+        Timed tm(SPK_KIND_OTHER, 0.0, s);
+        SPK_HIP(launch_field_fft(prm->precision, kern, G, prm->half_width, prm->eps, rho, field,
+                                 ws, s),
+                "FFT node field");
+        return SPK_OK;
+    }
     Ws w;
     if ((rc = bind_ws(prm, ws, ws_bytes, &w)))
         return rc;
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    const int64_t G = prm->grid, Mn = field_nodes(G);
     const int64_t cap = std::min(Mn, kGridTargetChunk);
     char *pts = static_cast<char *>(w.cells());
     void *nx = pts, *ny = pts + al * cap, *nz = pts + 2 * al * cap;

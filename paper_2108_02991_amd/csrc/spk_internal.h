@@ -96,6 +96,11 @@ hipError_t launch_cell_centres(int precision, int64_t G, double L, int64_t v0, i
 // sums of targets [t0, t0+nt) into acc rows (like a cell sweep would).
 // Node coordinates of nodes n0 .. n0+n-1 into nx, ny, nz[0 .. n-1]; packing of
 // acc rows 0 .. n-1 into field nodes n0 .. n0+n-1.
+// Node field by FP64 FFT convolution (fftfield.hip): workspace bytes, 0 when
+// the grid is too large for it (2G + 1 > 512).
+size_t field_fft_bytes(int64_t G);
+hipError_t launch_field_fft(int precision, int kern, int64_t G, double L, double eps,
+                            const void *rho, void *field, void *ws, hipStream_t s);
 hipError_t launch_node_coords(int precision, int64_t G, double L, int64_t n0, int64_t n, void *nx,
                               void *ny, void *nz, hipStream_t s);
 hipError_t launch_field_pack(int precision, const double *acc, int64_t ld, int64_t n0, int64_t n,

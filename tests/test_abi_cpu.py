@@ -118,7 +118,7 @@ def test_unknown_precision_and_flags(lib):
     n = ctypes.c_size_t()
     assert lib.spk_workspace_size(ctypes.byref(c), ctypes.byref(n)) == EINVAL
     c = good_params().c()
-    c.flags = 8
+    c.flags = 16
     assert lib.spk_workspace_size(ctypes.byref(c), ctypes.byref(n)) == EINVAL
     assert lib.spk_workspace_size(None, ctypes.byref(n)) == EINVAL
 
