@@ -158,6 +158,24 @@ def test_adaptive_far_field_validation(lib):
     assert lib.spk_workspace_size(ctypes.byref(c), ctypes.byref(n)) == EINVAL
 
 
+def test_field_workspace_size(lib):
+    n = ctypes.c_size_t()
+    # G = 7: FFT length M = 16 (>= 2G + 1): two M^3 complex doubles and M/2 twiddles,
+    # each rounded up to 256 bytes, plus 256 bytes of alignment slack
+    c = good_params(grid=7).c()
+    assert lib.spk_field_workspace_size(ctypes.byref(c), ctypes.byref(n)) == 0
+    assert n.value == 2 * 16 ** 3 * 16 + 256 + 256
+    # G = 300 needs M = 1024
+    c = good_params(grid=300).c()
+    assert lib.spk_field_workspace_size(ctypes.byref(c), ctypes.byref(n)) == 0
+    assert n.value == 2 * 1024 ** 3 * 16 + 8192 + 256
+    # the direct sum, and grids beyond the largest transform, use the ordinary workspace
+    for prm in (good_params(grid=7, field_direct=True), good_params(grid=600)):
+        c = prm.c()
+        assert lib.spk_field_workspace_size(ctypes.byref(c), ctypes.byref(n)) == 0
+        assert n.value == spk.workspace_size(prm)
+
+
 def test_log_kernel_validation(lib):
     n = ctypes.c_size_t()
     ok = good_params(kernel="log", eps=0.01).c()

@@ -132,3 +132,27 @@ def test_fft_field_c3_sampled_nodes(gpu):
     err_g = rel_l2(f[nodes, 1:].T, ref["dFa"] * n)
     say(f"  c3 FFT node field {ms:.1f} ms; sampled nodes rel L2 U {err_u:.3e}, grad {err_g:.3e}")
     assert err_u <= 1e-6 and err_g <= 1e-6
+
+
+def test_fft_field_largest_transform_sampled_nodes(gpu):
+    """300^3 cells take transforms of 1024^3 (4 lines per block): sampled nodes
+    against the oracle's attraction potential and gradient."""
+    G, L = 300, 0.5
+    rho = inputs.separable_density(G, seed=3)
+    prm = spk.Params(1, 8, G, precision="plain_fp64")
+    _, rd = device_problem(np.zeros((3, 8)), rho, "plain_fp64", gpu)
+    t0 = time.perf_counter()
+    f = spk.attraction_field(rd, prm)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3
+    Gn = G + 2
+    nodes = inputs.sample_targets(Gn ** 3, 24, seed=10)
+    fs = host64(f[torch.as_tensor(nodes, device=f.device)])
+    del f
+    k = np.stack([nodes % Gn, (nodes // Gn) % Gn, nodes // (Gn * Gn)])
+    X = -L + (k - 0.5) * (2 * L / G)
+    ref = oracle.grad(X, rho, G, L)
+    err_u = rel_l2(fs[:, 0], ref["ua"])
+    err_g = rel_l2(fs[:, 1:].T, ref["dFa"] * X.shape[1])
+    say(f"  G = 300 FFT node field {ms:.0f} ms; sampled nodes rel L2 U {err_u:.3e}, grad {err_g:.3e}")
+    assert err_u <= 1e-12 and err_g <= 1e-12
