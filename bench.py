@@ -94,10 +94,10 @@ def main():
     ap.add_argument("--eta", choices=["fixed", "lipschitz"], default=None,
                     help="fixed step: the workload's (default, distance kernel) or 1/L from "
                          "the Lipschitz bound (default for the log kernel; needs eps > 0)")
-    ap.add_argument("--far-field", default=None, metavar="DEPTH,ORDER[,adaptive]",
+    ap.add_argument("--far-field", default=None, metavar="DEPTH,ORDER[,adaptive[=R]]",
                     help="repulsion by the Chebyshev fast multipole method (e.g. 5,6 or "
-                         "5,6,adaptive) instead of all p^2 pairs; value is then an equivalent "
-                         "rate and roofline null")
+                         "5,6,adaptive=2) instead of all p^2 pairs; value is then an "
+                         "equivalent rate and roofline null")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed region, run a plain 1 GiB device copy three times "
                          "(reference dispatches for HBM byte counters)")

@@ -118,11 +118,13 @@ typedef struct {
                                  each target summed exactly (plain_fp64 and
                                  fp32_comp forms; SPK_EUNSUPPORTED otherwise)    */
     int32_t far_field_order;  /* Chebyshev nodes per axis, 3..6, when depth > 0     */
-    int32_t far_field_adaptive; /* 0: uniform octree.  1: leaves whose near field
-                                   is dense enough are refined once more, their
-                                   targets then summing exactly over the 27
-                                   cells of that level around them only
-                                   (depth 2..6)                                   */
+    int32_t far_field_adaptive; /* refinement levels R, 0..2: 0 is the uniform
+                                   octree.  Leaves whose near field is dense
+                                   enough are refined one level, and (R = 2)
+                                   their children again by the same rule; a
+                                   target then sums exactly over the 27 cells
+                                   around it at its deepest level only
+                                   (depth + R <= 7)                               */
 } spk_params;
 
 /* Text of a status code (static storage). */

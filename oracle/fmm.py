@@ -107,10 +107,11 @@ def _around(counts):
 
 
 def refined_leaves(leaf, fine, depth, n):
-    """Adaptive tree: leaves (depth `depth`) whose targets take their near
-    field one level deeper.  A leaf is refined when the direct pairs this saves,
-    n_L * (samples around L) - sum over children c of n_c * (samples around c),
-    exceed refine_threshold(n); exact integers."""
+    """Adaptive tree: cells (of level `depth`, coordinates `leaf`) whose targets
+    take their near field one level deeper (coordinates `fine`).  A cell is
+    refined when the direct pairs this saves, n_L * (samples around L) - sum
+    over children c of n_c * (samples around c), exceed refine_threshold(n);
+    exact integers."""
     N = 2 ** depth
     cL = np.zeros((N, N, N), dtype=np.int64)
     np.add.at(cL, (leaf[:, 0], leaf[:, 1], leaf[:, 2]), 1)
@@ -121,21 +122,27 @@ def refined_leaves(leaf, fine, depth, n):
     return (cL > 0) & (coarse - fine_pairs > refine_threshold(n))
 
 
-def fmm(X, depth, n, kernel, adaptive=False, info=None):
+def fmm(X, depth, n, kernel, adaptive=0, info=None, only=None):
     """Repulsion sums of every sample by the Chebyshev FMM; X is (p, 3).
 
-    adaptive: the tree goes one level deeper (depth + 1) for the targets of
-    refined leaves (refined_leaves): their local expansion comes from that
-    level (its interactions included) and their near field from the 27 cells
-    of that level around them.  Every other target is treated as in the
-    uniform tree of the given depth.  info (a dict) receives the refine flags.
+    adaptive = R (0, 1 or 2; True counts as 1): refinement levels below the
+    leaves.  A leaf is refined by refined_leaves; with R = 2 a child of a
+    refined leaf is refined again by the same rule one level down.  A
+    target's final level is the deepest level its cells reach: its local
+    expansion comes from that level (its interactions included) and its
+    near field from the 27 cells of that level around it.  A target whose
+    leaf is not refined is treated as in the uniform tree of the given
+    depth.  info (a dict) receives the final level of every target.  only (a
+    boolean mask) limits the near field to those targets; the other rows then
+    hold the far field alone.
     """
     X = np.asarray(X, dtype=np.float64)
     p = X.shape[0]
+    R_ = int(adaptive)
     lo, hi = X.min(axis=0), X.max(axis=0)
     c0 = 0.5 * (lo + hi)
     R = (0.5 * (hi - lo)).max() * (1.0 + 2.0 ** -20) + 1e-30
-    F = depth + 1 if adaptive else depth                 # deepest level
+    F = depth + R_                                       # deepest level
     tb = cheb_nodes(n)
     n3 = n ** 3
     m = np.arange(n3)
@@ -153,15 +160,18 @@ def fmm(X, depth, n, kernel, adaptive=False, info=None):
         Nl = 2 ** level
         return np.clip(np.floor((X - (c0 - R)) / (2 * R / Nl)).astype(np.int64), 0, Nl - 1)
 
-    leaf = cell_of(depth)
-    fine = cell_of(F)
-    ref = np.zeros(p, dtype=bool)
-    if adaptive:
-        rl = refined_leaves(leaf, fine, depth, n)
-        ref = rl[leaf[:, 0], leaf[:, 1], leaf[:, 2]]
-        if info is not None:
-            info["refined_leaves"] = rl
+    cell_at = {l: cell_of(l) for l in range(depth, F + 1)}
+    leaf, fine = cell_at[depth], cell_at[F]
+    final = np.full(p, depth)                            # final level of every target
+    refine_go = np.ones(p, dtype=bool)                   # still refining
+    for l in range(depth, F):
+        rl = refined_leaves(cell_at[l], cell_at[l + 1], l, n)
+        hit = refine_go & rl[cell_at[l][:, 0], cell_at[l][:, 1], cell_at[l][:, 2]]
+        final[hit] = l + 1
+        refine_go = hit
+    ref = final > depth
     if info is not None:
+        info["final_level"] = final
         info["refined_targets"] = ref
 
     # upward pass from the deepest level
@@ -207,7 +217,8 @@ def fmm(X, depth, n, kernel, adaptive=False, info=None):
             b = [pos & 1, (pos >> 1) & 1, (pos >> 2) & 1]
             Lx[lvl + 1][b[0]::2, b[1]::2, b[2]::2] += Lx[lvl] @ T[pos]
     far = np.zeros((p, 4))
-    for level, cellv, sel in ((depth, leaf, ~ref), (F, fine, ref)):
+    for level in range(depth, F + 1):
+        cellv, sel = cell_at[level], final == level
         if not sel.any():
             continue
         cs, hs = centre(level, cellv[sel])
@@ -216,14 +227,14 @@ def fmm(X, depth, n, kernel, adaptive=False, info=None):
                              Sm((X[sel] - cs) / hs))
     g = far[:, :3].copy()
     u = far[:, 3].copy()
-    # near field: the 27 leaves around each target's leaf, or, for the targets
-    # of refined leaves, the 27 cells one level deeper around their cell
-    for cellv, sel in ((leaf, ~ref), (fine, ref)):
+    # near field: the 27 cells of each target's final level around its cell
+    for level in range(depth, F + 1):
+        cellv, sel = cell_at[level], final == level
         members = {}
         for i, key in enumerate(map(tuple, cellv)):
             members.setdefault(key, []).append(i)
         targets = {}
-        for i in np.flatnonzero(sel):
+        for i in np.flatnonzero(sel if only is None else sel & only):
             targets.setdefault(tuple(cellv[i]), []).append(i)
         for key, tgt in targets.items():
             src = [j for o in itertools.product((-1, 0, 1), repeat=3)

@@ -115,7 +115,7 @@ class Params:
     attraction_field: "torch.Tensor | None" = None   # from attraction_field(); None = direct sum
     far_field_depth: int = 0                         # 0: exact repulsion; 2..7: octree depth
     far_field_order: int = 5                         # Chebyshev nodes per axis (3..6)
-    far_field_adaptive: bool = False                 # refine dense leaves once more
+    far_field_adaptive: int = 0                      # refinement levels of dense cells (0..2)
     field_direct: bool = False                       # node field summed directly, not by FFT
     _c: SpkParams = field(default=None, repr=False, compare=False)
 
@@ -142,7 +142,7 @@ class Params:
                          | (FLAG_FIELD_DIRECT if self.field_direct else 0),
                          _vp(f.data_ptr()) if f is not None else None,
                          self.far_field_depth, self.far_field_order if self.far_field_depth else 0,
-                         int(bool(self.far_field_adaptive)))
+                         int(self.far_field_adaptive))
 
 
 def lipschitz_bound(p: int, eps: float, rho_mass: float = 1.0, kernel: str = "distance") -> float:

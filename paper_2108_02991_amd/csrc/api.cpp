@@ -156,11 +156,11 @@ int check_params(const spk_params *prm, bool need_projection)
         if (prm->precision != SPK_PLAIN_FP64 && prm->precision != SPK_FP32_COMP)
             return fail(SPK_EUNSUPPORTED, "the far field runs in the plain_fp64 and fp32_comp "
                                           "forms only");
-        if (prm->far_field_adaptive != 0 && prm->far_field_adaptive != 1)
-            return fail(SPK_EINVAL, "far_field_adaptive must be 0 or 1");
-        if (prm->far_field_adaptive && prm->far_field_depth > kFmmMaxDepth - 1)
-            return fail(SPK_EINVAL, "an adaptive far field needs far_field_depth <= %d",
-                        kFmmMaxDepth - 1);
+        if (prm->far_field_adaptive < 0 || prm->far_field_adaptive > kMaxRefine)
+            return fail(SPK_EINVAL, "far_field_adaptive must be in [0, %d]", kMaxRefine);
+        if (prm->far_field_depth + prm->far_field_adaptive > kFmmMaxDepth)
+            return fail(SPK_EINVAL, "far_field_depth + far_field_adaptive must be <= %d",
+                        kFmmMaxDepth);
     } else if (prm->far_field_adaptive != 0) {
         return fail(SPK_EINVAL, "far_field_adaptive needs far_field_depth > 0");
     }
@@ -239,10 +239,12 @@ struct Layout {
     size_t chunk_sums = 0, info = 0;
     // far field (only with far_field_depth > 0)
     size_t fmm_box_part = 0, fmm_box = 0, fmm_keys_in = 0, fmm_keys_out = 0, fmm_vals_in = 0,
-           fmm_vals_out = 0, fmm_xs = 0, fmm_start = 0, fmm_chunks = 0, fmm_chunk_start = 0,
-           fmm_temp = 0, fmm_temp_bytes = 0, fmm_A = 0, fmm_Tm = 0, fmm_chunks_fine = 0,
-           fmm_chunk_start_fine = 0, fmm_refined = 0, fmm_tmask_fine = 0, fmm_tflag = 0,
-           fmm_tscan = 0, fmm_tlist = 0, fmm_Tu = 0, fmm_Td = 0;
+           fmm_vals_out = 0, fmm_xs = 0, fmm_start = 0,
+           fmm_temp = 0, fmm_temp_bytes = 0, fmm_A = 0, fmm_Tm = 0, fmm_Tu = 0, fmm_Td = 0;
+    size_t fmm_chunks_q[kMaxRefine + 1] = {}, fmm_chunk_start_q[kMaxRefine + 1] = {},
+           fmm_refined[kMaxRefine] = {}, fmm_tmask[kMaxRefine + 1] = {},
+           fmm_tflag[kMaxRefine + 1] = {}, fmm_tscan[kMaxRefine + 1] = {},
+           fmm_tlist[kMaxRefine + 1] = {};
     size_t fmm_W[kFmmMaxDepth + 1] = {}, fmm_L[kFmmMaxDepth + 1] = {},
            fmm_occ[kFmmMaxDepth + 1] = {};
     size_t total = 0;
@@ -297,9 +299,10 @@ Layout make_layout(const spk_params *prm)
     L.chunk_sums = take(sizeof(double) * ((M + kGridTargetChunk - 1) / kGridTargetChunk));
     if (prm->far_field_depth > 0) {
         const int D = prm->far_field_depth, n = prm->far_field_order;
-        const int F = prm->far_field_adaptive ? D + 1 : D;   // deepest level
+        const int R = prm->far_field_adaptive, F = D + R;   // deepest level
         const size_t n3 = (size_t)n * n * n;
-        const int64_t nleaves = int64_t(1) << (3 * D), ncells = int64_t(1) << (3 * F);
+        const int64_t ncells = int64_t(1) << (3 * F);
+        auto cells_at = [&](int q) { return int64_t(1) << (3 * (D + q)); };
         L.fmm_box_part = take(sizeof(double) * 6 * kFmmBoxBlocks);
         L.fmm_box = take(sizeof(double) * 4);
         L.fmm_keys_in = take(sizeof(uint32_t) * p);
@@ -308,16 +311,17 @@ Layout make_layout(const spk_params *prm)
         L.fmm_vals_out = take(sizeof(uint32_t) * p);
         L.fmm_xs = take(elt_size(prm->precision) * 3 * p);
         L.fmm_start = take(sizeof(int32_t) * (ncells + 1));
-        L.fmm_chunks = take(sizeof(int32_t) * (nleaves + 1));
-        L.fmm_chunk_start = take(sizeof(int32_t) * (nleaves + 1));
-        if (F > D) {
-            L.fmm_chunks_fine = take(sizeof(int32_t) * (ncells + 1));
-            L.fmm_chunk_start_fine = take(sizeof(int32_t) * (ncells + 1));
-            L.fmm_refined = take(sizeof(int32_t) * nleaves);
-            L.fmm_tmask_fine = take(sizeof(int32_t) * fmm_level_cells(F));
-            L.fmm_tflag = take(sizeof(int32_t) * (ncells + 1));
-            L.fmm_tscan = take(sizeof(int32_t) * (ncells + 1));
-            L.fmm_tlist = take(sizeof(int32_t) * ncells);
+        for (int q = 0; q <= R; ++q) {
+            L.fmm_chunks_q[q] = take(sizeof(int32_t) * (cells_at(q) + 1));
+            L.fmm_chunk_start_q[q] = take(sizeof(int32_t) * (cells_at(q) + 1));
+        }
+        for (int q = 0; q < R; ++q)
+            L.fmm_refined[q] = take(sizeof(int32_t) * cells_at(q));
+        for (int q = 1; q <= R; ++q) {
+            L.fmm_tmask[q] = take(sizeof(int32_t) * fmm_level_cells(D + q));
+            L.fmm_tflag[q] = take(sizeof(int32_t) * (cells_at(q) + 1));
+            L.fmm_tscan[q] = take(sizeof(int32_t) * (cells_at(q) + 1));
+            L.fmm_tlist[q] = take(sizeof(int32_t) * cells_at(q));
         }
         L.fmm_temp_bytes = fmm_sort_temp_bytes(p, F);
         L.fmm_temp = take(L.fmm_temp_bytes);
@@ -441,7 +445,7 @@ int run_far_field(const spk_params *prm, const void *kx, const void *ky, const v
     f.energy = energy;
     f.depth = prm->far_field_depth;
     f.order = prm->far_field_order;
-    f.adaptive = prm->far_field_adaptive != 0;
+    f.adaptive = prm->far_field_adaptive;
     f.x = kx;
     f.y = ky;
     f.z = kz;
@@ -464,20 +468,21 @@ int run_far_field(const spk_params *prm, const void *kx, const void *ky, const v
     f.ys = xs + al * p;
     f.zs = xs + 2 * al * p;
     f.start = w.at<int32_t>(L.fmm_start);
-    f.chunks = w.at<int32_t>(L.fmm_chunks);
-    f.chunk_start = w.at<int32_t>(L.fmm_chunk_start);
-    if (f.adaptive) {
-        f.chunks_fine = w.at<int32_t>(L.fmm_chunks_fine);
-        f.chunk_start_fine = w.at<int32_t>(L.fmm_chunk_start_fine);
-        f.refined = w.at<int32_t>(L.fmm_refined);
-        f.tmask_fine = w.at<int32_t>(L.fmm_tmask_fine);
-        f.tflag = w.at<int32_t>(L.fmm_tflag);
-        f.tscan = w.at<int32_t>(L.fmm_tscan);
-        f.tlist = w.at<int32_t>(L.fmm_tlist);
+    for (int q = 0; q <= f.adaptive; ++q) {
+        f.chunks[q] = w.at<int32_t>(L.fmm_chunks_q[q]);
+        f.chunk_start[q] = w.at<int32_t>(L.fmm_chunk_start_q[q]);
+    }
+    for (int q = 0; q < f.adaptive; ++q)
+        f.refined[q] = w.at<int32_t>(L.fmm_refined[q]);
+    for (int q = 1; q <= f.adaptive; ++q) {
+        f.tmask[q] = w.at<int32_t>(L.fmm_tmask[q]);
+        f.tflag[q] = w.at<int32_t>(L.fmm_tflag[q]);
+        f.tscan[q] = w.at<int32_t>(L.fmm_tscan[q]);
+        f.tlist[q] = w.at<int32_t>(L.fmm_tlist[q]);
     }
     f.temp = w.at<char>(L.fmm_temp);
     f.temp_bytes = L.fmm_temp_bytes;
-    for (int l = 2; l <= f.depth + (f.adaptive ? 1 : 0); ++l) {
+    for (int l = 2; l <= f.depth + f.adaptive; ++l) {
         f.W[l] = w.at<double>(L.fmm_W[l]);
         f.L[l] = w.at<double>(L.fmm_L[l]);
         f.occ[l] = w.at<int32_t>(L.fmm_occ[l]);

@@ -151,46 +151,23 @@ __device__ inline int64_t leaf_coord(double x, double c, double R, int64_t N)
     return (int64_t)k;
 }
 
-// Cell numbering at the deepest level (N cells per axis): x fastest, or, with
-// fine set, (parent, child) = 8 (x-fastest parent index) + (cx + 2 cy + 4 cz),
-// which keeps every parent's samples contiguous.
-__device__ inline int64_t cell_key(int64_t ix, int64_t iy, int64_t iz, int64_t N, bool fine)
-{
-    if (!fine)
-        return ix + N * (iy + N * iz);
-    const int64_t ps = N >> 1;
-    return ((ix >> 1) + ps * ((iy >> 1) + ps * (iz >> 1))) * 8 +
-           ((ix & 1) | ((iy & 1) << 1) | ((iz & 1) << 2));
-}
-
-__device__ inline void cell_coords(int64_t k, int64_t N, bool fine, int64_t &ix, int64_t &iy,
-                                   int64_t &iz)
-{
-    if (!fine) {
-        ix = k % N;
-        iy = (k / N) % N;
-        iz = k / (N * N);
-        return;
-    }
-    const int64_t ps = N >> 1, par = k >> 3, ch = k & 7;
-    ix = 2 * (par % ps) + (ch & 1);
-    iy = 2 * ((par / ps) % ps) + ((ch >> 1) & 1);
-    iz = 2 * (par / (ps * ps)) + (ch >> 2);
-}
-
+// Samples are keyed by the composite index (comp_index) of their cell R levels
+// below the leaves (R = 0: the x-fastest leaf index), so every cell of every
+// level from the leaves down owns one run of the sorted samples.
 template <typename T>
 __global__ __launch_bounds__(EW) void leaf_keys_kernel(const T *x, const T *y, const T *z, int64_t p,
-                                                       const double *box, int64_t N, bool fine,
+                                                       const double *box, int R, int64_t sD,
                                                        uint32_t *key, uint32_t *val)
 {
     const int64_t i = (int64_t)blockIdx.x * EW + threadIdx.x;
     if (i >= p)
         return;
-    const double R = box[3];
-    const int64_t ix = leaf_coord((double)x[i], box[0], R, N);
-    const int64_t iy = leaf_coord((double)y[i], box[1], R, N);
-    const int64_t iz = leaf_coord((double)z[i], box[2], R, N);
-    key[i] = (uint32_t)cell_key(ix, iy, iz, N, fine);
+    const double R_ = box[3];
+    const int64_t N = sD << R;
+    const int64_t ix = leaf_coord((double)x[i], box[0], R_, N);
+    const int64_t iy = leaf_coord((double)y[i], box[1], R_, N);
+    const int64_t iz = leaf_coord((double)z[i], box[2], R_, N);
+    key[i] = (uint32_t)comp_index(ix, iy, iz, R, sD);
     val[i] = (uint32_t)i;
 }
 
@@ -226,71 +203,76 @@ __global__ __launch_bounds__(EW) void leaf_bounds_kernel(const uint32_t *ks, int
     start[k] = (int32_t)lo;
 }
 
-// Near-field target chunks: chunks[k] = ceil(count_k / tpb) for the cells k <
-// ncells whose samples are targets of this near field, else 0; chunks[ncells]
-// = 0.  Cell k owns [start[stride k], start[stride (k+1)]).  With a refine
-// flag array, cell k is a target cell when refined[k >> shift] equals want.
+// Near-field target chunks of the cells of one level: chunks[k] = ceil(count_k
+// / tpb) for the cells k < ncells whose samples are targets of this near field,
+// else 0; chunks[ncells] = 0.  Cell k owns [start[stride k], start[stride
+// (k+1)]).  It is a target cell when (a null or a[k >> 3] set: its parent is
+// refined) and (b null or b[k] clear: it is not refined itself).
 __global__ __launch_bounds__(EW) void leaf_chunks_kernel(const int32_t *start, int64_t ncells,
-                                                         int64_t stride, int tpb,
-                                                         const int32_t *refined, int shift,
-                                                         bool want, int32_t *chunks)
+                                                         int64_t stride, int tpb, const int32_t *a,
+                                                         const int32_t *b, int32_t *chunks)
 {
     const int64_t k = (int64_t)blockIdx.x * EW + threadIdx.x;
     if (k > ncells)
         return;
     int32_t c = 0;
-    if (k < ncells && (!refined || (refined[k >> shift] != 0) == want))
+    if (k < ncells && (!a || a[k >> 3]) && (!b || !b[k]))
         c = (start[stride * (k + 1)] - start[stride * k] + tpb - 1) / tpb;
     chunks[k] = c;
 }
 
-// Refinement of the base leaves (adaptive tree; samples sorted by (leaf,
-// child)).  A leaf is refined when the direct pairs its targets save by taking
-// their near field over the 27 children-level cells around each child instead
-// of the 27 leaves around the leaf exceed the threshold, a price for the
-// children-level interactions in units of pairs.  Counts are exact integers.
-__global__ __launch_bounds__(EW) void refine_kernel(const int32_t *start, int64_t side,
-                                                    int64_t threshold, int32_t *refined)
+// Samples in the 27 cells around cell (x, y, z) of level D + q, and their count.
+__device__ inline int64_t around_count(const int32_t *start, int64_t x, int64_t y, int64_t z, int q,
+                                       int64_t sD, int64_t stride)
 {
-    const int64_t leaf = (int64_t)blockIdx.x * EW + threadIdx.x;
-    if (leaf >= side * side * side)
-        return;
-    const int64_t ix = leaf % side, iy = (leaf / side) % side, iz = leaf / (side * side);
-    const int64_t n = (int64_t)start[8 * (leaf + 1)] - start[8 * leaf];
-    int32_t r = 0;
-    if (n > 0) {
-        int64_t around = 0;
-        for (int64_t z = iz - 1; z <= iz + 1; ++z)
-            for (int64_t y = iy - 1; y <= iy + 1; ++y) {
-                if (y < 0 || y >= side || z < 0 || z >= side)
+    const int64_t N = sD << q;
+    int64_t a = 0;
+    for (int64_t zz = z - 1; zz <= z + 1; ++zz)
+        for (int64_t yy = y - 1; yy <= y + 1; ++yy)
+            for (int64_t xx = x - 1; xx <= x + 1; ++xx) {
+                if (xx < 0 || xx >= N || yy < 0 || yy >= N || zz < 0 || zz >= N)
                     continue;
-                const int64_t x0 = ix > 0 ? ix - 1 : 0, x1 = ix + 1 < side ? ix + 1 : side - 1;
-                const int64_t row = side * (y + side * z);
-                around += (int64_t)start[8 * (x1 + row + 1)] - start[8 * (x0 + row)];
+                const int64_t kk = comp_index(xx, yy, zz, q, sD);
+                a += (int64_t)start[stride * (kk + 1)] - start[stride * kk];
             }
-        const int64_t N = 2 * side;
-        int64_t fine_pairs = 0;
+    return a;
+}
+
+// Refinement of the cells of level D + q (adaptive tree; samples keyed R levels
+// below the leaves; q < R).  A cell (whose parent is refined, for q > 0) is
+// refined when the direct pairs its targets save by taking their near field
+// over the 27 cells one level down around each child instead of the 27 cells
+// around it exceed the threshold, a price for the children's interactions in
+// units of pairs.  Counts are exact integers.
+__global__ __launch_bounds__(EW) void refine_kernel(const int32_t *start, int q, int R, int64_t sD,
+                                                    int64_t threshold, const int32_t *parent,
+                                                    int32_t *refined)
+{
+    const int64_t N = sD << q, k = (int64_t)blockIdx.x * EW + threadIdx.x;
+    if (k >= N * N * N)
+        return;
+    int64_t s1 = 1;                  // start stride of the children's level
+    for (int r = q + 1; r < R; ++r)
+        s1 *= 8;
+    const int64_t s0 = 8 * s1;       // start stride of this level
+    const int64_t n = (int64_t)start[s0 * (k + 1)] - start[s0 * k];
+    int32_t r = 0;
+    if (n > 0 && (!parent || parent[k >> 3])) {
+        int64_t x, y, z;
+        comp_coords(k, q, sD, x, y, z);
+        const int64_t coarse = n * around_count(start, x, y, z, q, sD, s0);
+        int64_t fine = 0;
         for (int ch = 0; ch < 8; ++ch) {
-            const int64_t cx = 2 * ix + (ch & 1), cy = 2 * iy + ((ch >> 1) & 1),
-                          cz = 2 * iz + (ch >> 2);
-            const int64_t k = leaf * 8 + ch;
-            const int64_t nc = (int64_t)start[k + 1] - start[k];
+            const int64_t kc = 8 * k + ch;
+            const int64_t nc = (int64_t)start[s1 * (kc + 1)] - start[s1 * kc];
             if (nc == 0)
                 continue;
-            int64_t a = 0;
-            for (int64_t z = cz - 1; z <= cz + 1; ++z)
-                for (int64_t y = cy - 1; y <= cy + 1; ++y)
-                    for (int64_t x = cx - 1; x <= cx + 1; ++x) {
-                        if (x < 0 || x >= N || y < 0 || y >= N || z < 0 || z >= N)
-                            continue;
-                        const int64_t kk = cell_key(x, y, z, N, true);
-                        a += (int64_t)start[kk + 1] - start[kk];
-                    }
-            fine_pairs += nc * a;
+            fine += nc * around_count(start, 2 * x + (ch & 1), 2 * y + ((ch >> 1) & 1),
+                                      2 * z + (ch >> 2), q + 1, sD, s1);
         }
-        r = n * around - fine_pairs > threshold ? 1 : 0;
+        r = coarse - fine > threshold ? 1 : 0;
     }
-    refined[leaf] = r;
+    refined[k] = r;
 }
 
 __global__ __launch_bounds__(EW) void fill_kernel(double *a, int64_t n)
@@ -345,7 +327,7 @@ __device__ inline int64_t slot(int64_t ix, int64_t iy, int64_t iz, int64_t P)
 template <int N, typename T>
 __global__ __launch_bounds__(EW) void p2m_kernel(const T *xs, const T *ys, const T *zs,
                                                  const int32_t *start, const double *box,
-                                                 int64_t side, bool fine, Level lev, Cheb ch)
+                                                 int R, int64_t sD, Level lev, Cheb ch)
 {
     constexpr int N3 = N * N * N;
     static_assert(N3 <= EW, "one thread per node");
@@ -355,12 +337,12 @@ __global__ __launch_bounds__(EW) void p2m_kernel(const T *xs, const T *ys, const
     if (j0 == j1)
         return;
     int64_t ix, iy, iz;
-    cell_coords(leaf, side, fine, ix, iy, iz);
-    const double R = box[3];
-    const double h = 2.0 * R / (double)side, hh = 0.5 * h;
-    const double cx = box[0] - R + ((double)ix + 0.5) * h;
-    const double cy = box[1] - R + ((double)iy + 0.5) * h;
-    const double cz = box[2] - R + ((double)iz + 0.5) * h;
+    comp_coords(leaf, R, sD, ix, iy, iz);
+    const double Rb = box[3];
+    const double h = 2.0 * Rb / (double)(sD << R), hh = 0.5 * h;
+    const double cx = box[0] - Rb + ((double)ix + 0.5) * h;
+    const double cy = box[1] - Rb + ((double)iy + 0.5) * h;
+    const double cz = box[2] - Rb + ((double)iz + 0.5) * h;
     double *w = lev.W + slot(ix, iy, iz, lev.P) * N3;
     if (threadIdx.x == 0)
         lev.occ[slot(ix, iy, iz, lev.P)] = 1;
@@ -395,15 +377,17 @@ __global__ __launch_bounds__(EW) void p2m_kernel(const T *xs, const T *ys, const
         w[m] = a;
 }
 
-// Target mask of the refined level: occupied cells whose parent leaf is refined.
-__global__ __launch_bounds__(EW) void tmask_kernel(Level lev, const int32_t *refined)
+// Target mask of a refined level (D + q, q >= 1): occupied cells whose parent
+// (composite index at level D + q - 1) is refined.
+__global__ __launch_bounds__(EW) void tmask_kernel(Level lev, const int32_t *refined, int q,
+                                                   int64_t sD)
 {
     const int64_t side = lev.side, k = (int64_t)blockIdx.x * EW + threadIdx.x;
     if (k >= side * side * side)
         return;
     const int64_t ix = k % side, iy = (k / side) % side, iz = k / (side * side);
-    const int64_t ps = side >> 1, sl = slot(ix, iy, iz, lev.P);
-    const int64_t par = (ix >> 1) + ps * ((iy >> 1) + ps * (iz >> 1));
+    const int64_t sl = slot(ix, iy, iz, lev.P);
+    const int64_t par = comp_index(ix >> 1, iy >> 1, iz >> 1, q - 1, sD);
     lev.tmask[sl] = lev.occ[sl] && refined[par] ? 1 : 0;
 }
 
@@ -976,14 +960,21 @@ __global__ __launch_bounds__(kM2lThreads) void l2l_kernel(Level par, Level chd, 
 }
 
 // ------------------------------------------------------------------ L2P
-// Sample j (sorted) evaluates the local expansion of its leaf, or, in the
-// adaptive tree when its leaf is refined, of its cell one level deeper.
+// Sample j (sorted, key = composite index R levels below the leaves) evaluates
+// the local expansion of its cell at its final level: the leaves' level, or
+// one (two) levels down while its cells there are refined.
+struct L2pLevels {
+    Level lev[kMaxRefine + 1];          // levels D .. D + R
+    const int32_t *refined[kMaxRefine]; // refine flags of levels D .. D + R - 1
+    int R;
+    int64_t sD;
+};
+
 template <int N, typename T>
 __global__ __launch_bounds__(EW) void l2p_kernel(const T *xs, const T *ys, const T *zs,
                                                  const uint32_t *ks, const uint32_t *order,
-                                                 int64_t p, const double *box, Level leaves,
-                                                 Level fine, const int32_t *refined, Cheb ch,
-                                                 int64_t t0, int64_t nt, bool energy,
+                                                 int64_t p, const double *box, L2pLevels lv,
+                                                 Cheb ch, int64_t t0, int64_t nt, bool energy,
                                                  double *acc, int64_t ld)
 {
     constexpr int N3 = N * N * N;
@@ -994,28 +985,22 @@ __global__ __launch_bounds__(EW) void l2p_kernel(const T *xs, const T *ys, const
     if (i < 0 || i >= nt)
         return;
     const int64_t key = ks[j];
-    int64_t ix, iy, iz, side;
-    const Level *lv = &leaves;
-    if (refined) {                           // keys are (leaf, child)
-        if (refined[key >> 3]) {
-            lv = &fine;
-            side = fine.side;
-            cell_coords(key, side, true, ix, iy, iz);
-        } else {
-            side = leaves.side;
-            cell_coords(key >> 3, side, false, ix, iy, iz);
-        }
-    } else {
-        side = leaves.side;
-        cell_coords(key, side, false, ix, iy, iz);
+    int q = 0;
+    if (lv.R > 0 && lv.refined[0][key >> (3 * lv.R)]) {
+        q = 1;
+        if (lv.R > 1 && lv.refined[1][key >> (3 * (lv.R - 1))])
+            q = 2;
     }
+    const Level L = q == 0 ? lv.lev[0] : (q == 1 ? lv.lev[1] : lv.lev[2]);
+    int64_t ix, iy, iz;
+    comp_coords(key >> (3 * (lv.R - q)), q, lv.sD, ix, iy, iz);
     const double R = box[3];
-    const double h = 2.0 * R / (double)side, hh = 0.5 * h;
+    const double h = 2.0 * R / (double)L.side, hh = 0.5 * h;
     double sx[N], sy[N], sz[N];
     cheb_s<N>(ch, ((double)xs[j] - (box[0] - R + ((double)ix + 0.5) * h)) / hh, sx);
     cheb_s<N>(ch, ((double)ys[j] - (box[1] - R + ((double)iy + 0.5) * h)) / hh, sy);
     cheb_s<N>(ch, ((double)zs[j] - (box[2] - R + ((double)iz + 0.5) * h)) / hh, sz);
-    const double *lf = lv->L + slot(ix, iy, iz, lv->P) * 4 * N3;
+    const double *lf = L.L + slot(ix, iy, iz, L.P) * 4 * N3;
     double f[4] = {0.0, 0.0, 0.0, 0.0};
     for (int mz = 0; mz < N; ++mz)
         for (int my = 0; my < N; ++my) {
@@ -1119,9 +1104,11 @@ hipError_t run_typed(const FmmLaunch &f, hipStream_t s)
     const T *x = static_cast<const T *>(f.x), *y = static_cast<const T *>(f.y),
             *z = static_cast<const T *>(f.z);
     T *xs = static_cast<T *>(f.xs), *ys = static_cast<T *>(f.ys), *zs = static_cast<T *>(f.zs);
-    const int D = f.depth, F = f.adaptive ? D + 1 : D;
-    const int64_t p = f.p, side = int64_t(1) << D, nleaves = side * side * side;
-    const int64_t sideF = int64_t(1) << F, ncellsF = sideF * sideF * sideF;
+    const int D = f.depth, R = f.adaptive, F = D + R;
+    const int64_t p = f.p, sD = int64_t(1) << D;
+    auto ncells_at = [&](int q) { return int64_t(1) << (3 * (D + q)); };
+    auto stride_at = [&](int q) { return int64_t(1) << (3 * (R - q)); };
+    const int64_t ncellsF = ncells_at(R);
     const Cheb ch = make_cheb(N);
     hipError_t e;
     // root box
@@ -1130,7 +1117,7 @@ hipError_t run_typed(const FmmLaunch &f, hipStream_t s)
     hipLaunchKernelGGL(box_stage2, dim3(1), dim3(64), 0, s, f.box_part, nb, f.box);
     // cell keys at the deepest level, stable sort, sorted coordinates, cell ranges
     hipLaunchKernelGGL(leaf_keys_kernel<T>, dim3(ew_blocks(p)), dim3(EW), 0, s, x, y, z, p, f.box,
-                       sideF, f.adaptive, f.keys_in, f.vals_in);
+                       R, sD, f.keys_in, f.vals_in);
     size_t tb = f.temp_bytes;
     if ((e = hipcub::DeviceRadixSort::SortPairs(f.temp, tb, f.keys_in, f.keys_out, f.vals_in,
                                                 f.vals_out, (int)p, 0, 3 * F, s)) != hipSuccess)
@@ -1139,25 +1126,19 @@ hipError_t run_typed(const FmmLaunch &f, hipStream_t s)
                        p, xs, ys, zs);
     hipLaunchKernelGGL(leaf_bounds_kernel, dim3(ew_blocks(ncellsF + 1)), dim3(EW), 0, s,
                        f.keys_out, p, ncellsF, f.start);
-    // refinement and near-field target chunks
-    const int64_t stride = f.adaptive ? 8 : 1;
-    if (f.adaptive)
-        hipLaunchKernelGGL(refine_kernel, dim3(ew_blocks(nleaves)), dim3(EW), 0, s, f.start, side,
-                           fmm_refine_threshold(N), f.refined);
-    hipLaunchKernelGGL(leaf_chunks_kernel, dim3(ew_blocks(nleaves + 1)), dim3(EW), 0, s, f.start,
-                       nleaves, stride, f.near_tpb, f.adaptive ? f.refined : nullptr, 0, false,
-                       f.chunks);
-    tb = f.temp_bytes;
-    if ((e = hipcub::DeviceScan::ExclusiveSum(f.temp, tb, f.chunks, f.chunk_start,
-                                              (int)(nleaves + 1), s)) != hipSuccess)
-        return e;
-    if (f.adaptive) {
-        hipLaunchKernelGGL(leaf_chunks_kernel, dim3(ew_blocks(ncellsF + 1)), dim3(EW), 0, s,
-                           f.start, ncellsF, (int64_t)1, f.near_tpb, f.refined, 3, true,
-                           f.chunks_fine);
+    // refinement, level by level, and the near-field target chunks of every level
+    for (int q = 0; q < R; ++q)
+        hipLaunchKernelGGL(refine_kernel, dim3(ew_blocks(ncells_at(q))), dim3(EW), 0, s, f.start,
+                           q, R, sD, fmm_refine_threshold(N), q > 0 ? f.refined[q - 1] : nullptr,
+                           f.refined[q]);
+    for (int q = 0; q <= R; ++q) {
+        const int64_t nc = ncells_at(q);
+        hipLaunchKernelGGL(leaf_chunks_kernel, dim3(ew_blocks(nc + 1)), dim3(EW), 0, s, f.start,
+                           nc, stride_at(q), f.near_tpb, q > 0 ? f.refined[q - 1] : nullptr,
+                           q < R ? f.refined[q] : nullptr, f.chunks[q]);
         tb = f.temp_bytes;
-        if ((e = hipcub::DeviceScan::ExclusiveSum(f.temp, tb, f.chunks_fine, f.chunk_start_fine,
-                                                  (int)(ncellsF + 1), s)) != hipSuccess)
+        if ((e = hipcub::DeviceScan::ExclusiveSum(f.temp, tb, f.chunks[q], f.chunk_start[q],
+                                                  (int)(nc + 1), s)) != hipSuccess)
             return e;
     }
     // multipole weights: zero (padding included), the deepest level, then upward
@@ -1168,7 +1149,7 @@ hipError_t run_typed(const FmmLaunch &f, hipStream_t s)
         lev[l].W = f.W[l];
         lev[l].L = f.L[l];
         lev[l].occ = f.occ[l];
-        lev[l].tmask = (f.adaptive && l == F) ? f.tmask_fine : f.occ[l];
+        lev[l].tmask = l > D ? f.tmask[l - D] : f.occ[l];
         lev[l].tlist = nullptr;
         lev[l].tscan = nullptr;
         const int64_t nw = (int64_t)fmm_level_cells(l) * N3;
@@ -1189,28 +1170,28 @@ hipError_t run_typed(const FmmLaunch &f, hipStream_t s)
         return (unsigned)((8 * ntc + kXcds - 1) / kXcds * kXcds * ntr_t);
     };
     hipLaunchKernelGGL((p2m_kernel<N, T>), dim3((unsigned)ncellsF), dim3(EW), 0, s, xs, ys, zs,
-                       f.start, f.box, sideF, f.adaptive, lev[F], ch);
+                       f.start, f.box, R, sD, lev[F], ch);
     for (int l = F - 1; l >= 2; --l) {
         const int64_t Q = lev[l].side / 2, ntc = (Q * Q * Q + TN - 1) / TN;
         hipLaunchKernelGGL(m2m_kernel<N>, dim3(trans_blocks(ntc)), dim3(kM2lThreads), 0, s, lev[l],
                            lev[l + 1], f.Tu, ntr_t, ntc);
     }
-    if (f.adaptive) {
-        // the refined level's target cells, listed per class in sub-grid order
-        hipLaunchKernelGGL(tmask_kernel, dim3(ew_blocks(ncellsF)), dim3(EW), 0, s, lev[F],
-                           f.refined);
-        hipLaunchKernelGGL(tflag_kernel, dim3(ew_blocks(ncellsF)), dim3(EW), 0, s, lev[F],
-                           f.tflag);
-        hipLaunchKernelGGL(fill_int_kernel, dim3(1), dim3(EW), 0, s, f.tflag + ncellsF,
-                           (int64_t)1);
+    // the refined levels' target cells, listed per class in sub-grid order
+    for (int q = 1; q <= R; ++q) {
+        const int l = D + q;
+        const int64_t nc = ncells_at(q);
+        hipLaunchKernelGGL(tmask_kernel, dim3(ew_blocks(nc)), dim3(EW), 0, s, lev[l],
+                           f.refined[q - 1], q, sD);
+        hipLaunchKernelGGL(tflag_kernel, dim3(ew_blocks(nc)), dim3(EW), 0, s, lev[l], f.tflag[q]);
+        hipLaunchKernelGGL(fill_int_kernel, dim3(1), dim3(EW), 0, s, f.tflag[q] + nc, (int64_t)1);
         tb = f.temp_bytes;
-        if ((e = hipcub::DeviceScan::ExclusiveSum(f.temp, tb, f.tflag, f.tscan,
-                                                  (int)(ncellsF + 1), s)) != hipSuccess)
+        if ((e = hipcub::DeviceScan::ExclusiveSum(f.temp, tb, f.tflag[q], f.tscan[q],
+                                                  (int)(nc + 1), s)) != hipSuccess)
             return e;
-        hipLaunchKernelGGL(tlist_kernel, dim3(ew_blocks(ncellsF)), dim3(EW), 0, s, lev[F],
-                           f.tflag, f.tscan, f.tlist);
-        lev[F].tlist = f.tlist;
-        lev[F].tscan = f.tscan;
+        hipLaunchKernelGGL(tlist_kernel, dim3(ew_blocks(nc)), dim3(EW), 0, s, lev[l], f.tflag[q],
+                           f.tscan[q], f.tlist[q]);
+        lev[l].tlist = f.tlist[q];
+        lev[l].tscan = f.tscan[q];
     }
     // interactions (every level in one launch), then the downward pass
     const int64_t ntab = (int64_t)kOffsets * M2lShape<N>::KP * M2lShape<N>::RP;
@@ -1243,8 +1224,8 @@ hipError_t run_typed(const FmmLaunch &f, hipStream_t s)
     }
     if ((e = hipGetLastError()) != hipSuccess)
         return e;
-    // near field (exact pair sums over the 27 cells around each target's cell),
-    // then the far field
+    // near field (exact pair sums over the 27 cells around each target's cell
+    // at its final level), then the far field
     NearLaunch nl;
     nl.precision = f.precision;
     nl.kernel = f.kernel;
@@ -1254,31 +1235,32 @@ hipError_t run_typed(const FmmLaunch &f, hipStream_t s)
     nl.zs = zs;
     nl.order = f.vals_out;
     nl.start = f.start;
-    nl.stride = stride;
-    nl.chunk_start = f.chunk_start;
-    nl.ncells = nleaves;
-    nl.side = side;
+    nl.sD = sD;
     nl.t0 = f.t0;
     nl.nt = f.nt;
     nl.eps = f.eps;
     nl.acc = f.acc;
     nl.ld = f.ld;
-    nl.max_blocks = (p + f.near_tpb - 1) / f.near_tpb + nleaves;
-    if ((e = launch_near(nl, s)) != hipSuccess)
-        return e;
-    if (f.adaptive) {
-        nl.fine = true;
-        nl.stride = 1;
-        nl.chunk_start = f.chunk_start_fine;
-        nl.ncells = ncellsF;
-        nl.side = sideF;
-        nl.max_blocks = (p + f.near_tpb - 1) / f.near_tpb + ncellsF;
+    for (int q = 0; q <= R; ++q) {
+        nl.sub = q;
+        nl.stride = stride_at(q);
+        nl.chunk_start = f.chunk_start[q];
+        nl.ncells = ncells_at(q);
+        nl.side = sD << q;
+        nl.max_blocks = (p + f.near_tpb - 1) / f.near_tpb + ncells_at(q);
         if ((e = launch_near(nl, s)) != hipSuccess)
             return e;
     }
+    L2pLevels lv{};
+    lv.R = R;
+    lv.sD = sD;
+    for (int q = 0; q <= R; ++q)
+        lv.lev[q] = lev[D + q];
+    for (int q = 0; q < R; ++q)
+        lv.refined[q] = f.refined[q];
     hipLaunchKernelGGL((l2p_kernel<N, T>), dim3(ew_blocks(p)), dim3(EW), 0, s, xs, ys, zs,
-                       f.keys_out, f.vals_out, p, f.box, lev[D], lev[F],
-                       f.adaptive ? f.refined : nullptr, ch, f.t0, f.nt, f.energy, f.acc, f.ld);
+                       f.keys_out, f.vals_out, p, f.box, lv, ch, f.t0, f.nt, f.energy, f.acc,
+                       f.ld);
     return hipGetLastError();
 }
 
@@ -1292,7 +1274,8 @@ hipError_t run_order(const FmmLaunch &f, hipStream_t s)
 
 hipError_t launch_fmm_repulsion(const FmmLaunch &f, hipStream_t s)
 {
-    if (f.depth < 2 || f.depth + (f.adaptive ? 1 : 0) > kFmmMaxDepth || f.p < 1)
+    if (f.depth < 2 || f.adaptive < 0 || f.adaptive > kMaxRefine ||
+        f.depth + f.adaptive > kFmmMaxDepth || f.p < 1)
         return hipErrorInvalidValue;
     switch (f.order) {
     case 3: return run_order<3>(f, s);

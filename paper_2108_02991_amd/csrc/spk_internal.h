@@ -22,11 +22,12 @@ constexpr int kFmmMaxDepth = 7;
 constexpr int kFmmMinOrder = 3;
 constexpr int kFmmMaxOrder = 6;
 constexpr int kFmmBoxBlocks = 1024;
+constexpr int kMaxRefine = 2;        // refinement levels of the adaptive tree
 struct FmmLaunch {
     int precision = 0, kernel = kKernelDistance;
     bool energy = false;
     int depth = 0, order = 0;             // base depth D, interpolation order
-    bool adaptive = false;                // refine dense leaves to depth D + 1
+    int adaptive = 0;                     // refinement levels R below the leaves (0..2)
     const void *x = nullptr, *y = nullptr, *z = nullptr;
     int64_t p = 0, t0 = 0, nt = 0;
     double eps = 0.0;
@@ -38,13 +39,15 @@ struct FmmLaunch {
     double *box = nullptr;                // centre[3], half-width
     uint32_t *keys_in = nullptr, *keys_out = nullptr, *vals_in = nullptr, *vals_out = nullptr;
     void *xs = nullptr, *ys = nullptr, *zs = nullptr;
-    // [8^F + 1] with F = D (+1 if adaptive): cell starts, near-field chunks of
-    // the leaves and, when adaptive, of the refined level
-    int32_t *start = nullptr, *chunks = nullptr, *chunk_start = nullptr;
-    int32_t *chunks_fine = nullptr, *chunk_start_fine = nullptr;
-    int32_t *refined = nullptr;           // [8^D] when adaptive
-    int32_t *tmask_fine = nullptr;        // [8][P^3] of level D + 1 when adaptive
-    int32_t *tflag = nullptr, *tscan = nullptr, *tlist = nullptr;   // [8^F + 1] when adaptive
+    // F = D + R: cell starts [8^F + 1]; per level D + q (q = 0..R) the
+    // near-field chunks and their scan [8^(D+q) + 1]
+    int32_t *start = nullptr;
+    int32_t *chunks[kMaxRefine + 1] = {}, *chunk_start[kMaxRefine + 1] = {};
+    int32_t *refined[kMaxRefine] = {};    // refine flags of level D + q, [8^(D+q)]
+    // refined levels D + q (q = 1..R): target masks [8][P^3], their flags,
+    // scans [8^(D+q) + 1] and lists [8^(D+q)]
+    int32_t *tmask[kMaxRefine + 1] = {}, *tflag[kMaxRefine + 1] = {};
+    int32_t *tscan[kMaxRefine + 1] = {}, *tlist[kMaxRefine + 1] = {};
     void *temp = nullptr;
     size_t temp_bytes = 0;
     double *W[kFmmMaxDepth + 1] = {};     // level l: [8][P^3][order^3]

@@ -91,20 +91,48 @@ hipError_t launch_sweep_cells(const SweepLaunch &l, hipStream_t s);
 // targets; chunk_start[k] is the first block of leaf k (an exclusive prefix
 // sum of the per-leaf block counts, nleaves + 1 entries); the grid has
 // max_blocks >= chunk_start[nleaves] blocks and the extra ones return.
-// Cells are numbered in one of two ways.  Plain: x fastest at the cells'
-// level, cell k owns sorted samples [start[stride k], start[stride (k+1)])
-// (stride 8 when the samples are sorted one level deeper).  Fine: the index
-// is (parent, child) = 8 (x-fastest parent index) + (cx + 2 cy + 4 cz) and
-// cell k owns [start[k], start[k+1]).
+// Composite cell index at level D + q (q >= 0 levels below the leaves of
+// level D, sD leaves per axis): the x-fastest index of the level-D ancestor,
+// then q octal digits, the child positions cx + 2 cy + 4 cz from the coarsest
+// down.  Samples sorted by this index at the deepest level keep every cell of
+// every level between contiguous.
+__host__ __device__ inline int64_t comp_index(int64_t x, int64_t y, int64_t z, int q, int64_t sD)
+{
+    int64_t k = (x >> q) + sD * ((y >> q) + sD * (z >> q));
+    for (int r = q - 1; r >= 0; --r)
+        k = 8 * k + (((x >> r) & 1) | (((y >> r) & 1) << 1) | (((z >> r) & 1) << 2));
+    return k;
+}
+
+__host__ __device__ inline void comp_coords(int64_t k, int q, int64_t sD, int64_t &x, int64_t &y,
+                                            int64_t &z)
+{
+    int64_t dx = 0, dy = 0, dz = 0;
+    for (int r = 0; r < q; ++r) {
+        const int64_t c = k & 7;
+        dx |= (c & 1) << r;
+        dy |= ((c >> 1) & 1) << r;
+        dz |= (c >> 2) << r;
+        k >>= 3;
+    }
+    x = ((k % sD) << q) | dx;
+    y = (((k / sD) % sD) << q) | dy;
+    z = ((k / (sD * sD)) << q) | dz;
+}
+
+// Near-field cells are those of level D + sub in composite numbering; cell k
+// owns sorted samples [start[stride k], start[stride (k+1)]) (stride = 8^(R -
+// sub) with samples sorted R levels below the leaves).
 struct NearLaunch {
     int precision = 0;
     int kernel = kKernelDistance;
     bool energy = false;
-    bool fine = false;                 // cell numbering (see above)
+    int sub = 0;                       // levels below the leaves
+    int64_t sD = 0;                    // leaves per axis
     const void *xs = nullptr, *ys = nullptr, *zs = nullptr;   // cell-sorted samples
     const uint32_t *order = nullptr;   // sorted position -> sample index
-    const int32_t *start = nullptr;    // first sorted sample of each cell
-    int64_t stride = 1;                // plain numbering: start index of cell k is stride k
+    const int32_t *start = nullptr;    // first sorted sample of each deepest cell
+    int64_t stride = 1;                // start index of cell k is stride k
     const int32_t *chunk_start = nullptr;  // [ncells + 1] target chunks before each cell
     int64_t ncells = 0, side = 0;      // cells, and cells per axis
     int64_t t0 = 0, nt = 0;

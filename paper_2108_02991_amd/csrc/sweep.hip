@@ -405,21 +405,14 @@ void sweep_cells_kernel(SweepLaunch l)
 
 // Near field of the far-field repulsion: every sample of a cell against the
 // samples of the 27 cells around it (itself included).  Those are runs of the
-// cell-sorted samples: nine runs of three cells along x in plain numbering,
-// 27 single cells in fine numbering.  The block streams the runs as one
+// cell-sorted samples: nine runs of three leaves along x at the leaves' level,
+// 27 single cells below it.  The block streams the runs as one
 // sequence, in run order, through LDS tiles of kSampleTile sources, so tiles
 // fill across run boundaries.  Blocks are one wave (kNearBlock threads), each
 // with kNearBlock * R targets.  Block b takes chunk b - chunk_start[cell] of
 // the cell with chunk_start[cell] <= b < chunk_start[cell + 1]; the pair
 // arithmetic and the accumulation are those of the sample sweep, and the sums
 // are written (not added) to the rows of targets in [t0, t0 + nt).
-__device__ inline int64_t fine_index(int64_t x, int64_t y, int64_t z, int64_t side)
-{
-    const int64_t ps = side >> 1;
-    return ((x >> 1) + ps * ((y >> 1) + ps * (z >> 1))) * 8 +
-           ((x & 1) | ((y & 1) << 1) | ((z & 1) << 2));
-}
-
 template <int MODE, int R, bool ENERGY, int KERN>
 __global__ __launch_bounds__(kNearBlock) __attribute__((amdgpu_waves_per_eu(min_waves<MODE>())))
 void near_kernel(NearLaunch l)
@@ -439,34 +432,22 @@ void near_kernel(NearLaunch l)
             hi = mid;
     }
     const int64_t cell = lo, side = l.side;
-    int64_t ix, iy, iz, t_lo, t_hi;
-    if (l.fine) {
-        const int64_t ps = side >> 1, par = cell >> 3, ch = cell & 7;
-        ix = 2 * (par % ps) + (ch & 1);
-        iy = 2 * ((par / ps) % ps) + ((ch >> 1) & 1);
-        iz = 2 * (par / (ps * ps)) + (ch >> 2);
-        t_lo = l.start[cell];
-        t_hi = l.start[cell + 1];
-    } else {
-        ix = cell % side;
-        iy = (cell / side) % side;
-        iz = cell / (side * side);
-        t_lo = l.start[l.stride * cell];
-        t_hi = l.start[l.stride * (cell + 1)];
-    }
+    int64_t ix, iy, iz;
+    comp_coords(cell, l.sub, l.sD, ix, iy, iz);
+    const int64_t t_lo = l.start[l.stride * cell], t_hi = l.start[l.stride * (cell + 1)];
     // the source runs, in a fixed order (z, y, then x)
     if (threadIdx.x < 27) {
         const int o = (int)threadIdx.x;
         const int64_t x = ix + o % 3 - 1, y = iy + (o / 3) % 3 - 1, z = iz + o / 9 - 1;
         int64_t s0 = 0, s1 = 0;
         const bool in_y = y >= 0 && y < side && z >= 0 && z < side;
-        if (l.fine) {
+        if (l.sub > 0) {
             if (in_y && x >= 0 && x < side) {
-                const int64_t k = fine_index(x, y, z, side);
-                s0 = l.start[k];
-                s1 = l.start[k + 1];
+                const int64_t k = comp_index(x, y, z, l.sub, l.sD);
+                s0 = l.start[l.stride * k];
+                s1 = l.start[l.stride * (k + 1)];
             }
-        } else if (in_y && o % 3 == 0) {     // one run of up to three cells along x
+        } else if (in_y && o % 3 == 0) {     // one run of up to three leaves along x
             const int64_t x0 = ix > 0 ? ix - 1 : 0, x1 = ix + 1 < side ? ix + 1 : side - 1;
             const int64_t row = side * (y + side * z);
             s0 = l.start[l.stride * (x0 + row)];

@@ -35,7 +35,7 @@ def fixed_step(prm: api.Params, rho_mass: float, rule: str, eta_fixed: float) ->
 def run(workload: configs.Workload, precision: str, iters: int, device="cuda:0",
         out=None, log_every: int = 1, rotation_variant: bool = False, kernel: str = "distance",
         eps: float = 0.0, eta_rule: str = "fixed", graph: bool = False,
-        far_field: tuple = (0, 5, False)):
+        far_field: tuple = (0, 5, 0)):
     """Runs `iters` projected gradient steps; returns the list of records.
 
     With graph=True the step runs as two captured HIP graphs (fixed-step and
@@ -48,7 +48,7 @@ def run(workload: configs.Workload, precision: str, iters: int, device="cuda:0",
                      half_width=workload.half_width, eps=eps, a_max=a, b_max=b, te_index=0,
                      n_pit=workload.n_pit, rotation_variant=rotation_variant, kernel=kernel,
                      far_field_depth=far_field[0], far_field_order=far_field[1],
-                     far_field_adaptive=bool(far_field[2:3] and far_field[2]))
+                     far_field_adaptive=int(far_field[2]) if len(far_field) > 2 else 0)
     rho_host = workload.density()
     K = torch.tensor(workload.trajectory(), dtype=prm.dtype, device=dev)
     rho = torch.tensor(rho_host, dtype=prm.dtype, device=dev)
@@ -125,13 +125,16 @@ def _run_graph(K, rho, prm, state, eta, iters, precision, viol0, out, log_every)
 
 
 def parse_far_field(spec):
-    """'DEPTH,ORDER' or 'DEPTH,ORDER,adaptive' -> (depth, order, adaptive); None -> off."""
+    """'DEPTH,ORDER', 'DEPTH,ORDER,adaptive' (one refinement level) or
+    'DEPTH,ORDER,adaptive=R' -> (depth, order, R); None -> off."""
     if not spec:
-        return 0, 5, False
+        return 0, 5, 0
     f = spec.split(",")
-    if len(f) not in (2, 3) or (len(f) == 3 and f[2] != "adaptive"):
-        raise ValueError(f"far field spec {spec!r}: expected DEPTH,ORDER[,adaptive]")
-    return int(f[0]), int(f[1]), len(f) == 3
+    ok = len(f) == 2 or (len(f) == 3 and (f[2] == "adaptive" or f[2].startswith("adaptive=")))
+    if not ok:
+        raise ValueError(f"far field spec {spec!r}: expected DEPTH,ORDER[,adaptive[=R]]")
+    R = 0 if len(f) == 2 else (1 if f[2] == "adaptive" else int(f[2].split("=")[1]))
+    return int(f[0]), int(f[1]), R
 
 
 def _level_depth(depth: int, d: int) -> int:
@@ -174,8 +177,9 @@ def multiresolution(K0: torch.Tensor, rho: torch.Tensor, prm_full: api.Params, l
                          attraction_field=prm_full.attraction_field,
                          far_field_depth=_level_depth(prm_full.far_field_depth, d),
                          far_field_order=prm_full.far_field_order,
-                         far_field_adaptive=(prm_full.far_field_adaptive and
-                                             _level_depth(prm_full.far_field_depth, d) > 0))
+                         far_field_adaptive=(prm_full.far_field_adaptive
+                                             if _level_depth(prm_full.far_field_depth, d) > 0
+                                             else 0))
         if K.shape[1] != prm.p:
             raise ValueError(f"level {d}: K has {K.shape[1]} samples, expected {prm.p}")
         eta = fixed_step(prm, float(rho.sum().item()), eta_rule,
@@ -223,9 +227,9 @@ def main():
                     help="run the single-level loop as captured HIP graphs")
     ap.add_argument("--n-pit", type=int, default=None,
                     help="projection iterations (default: the workload's)")
-    ap.add_argument("--far-field", default=None, metavar="DEPTH,ORDER[,adaptive]",
+    ap.add_argument("--far-field", default=None, metavar="DEPTH,ORDER[,adaptive[=R]]",
                     help="repulsion by the Chebyshev fast multipole method (e.g. 5,6 or "
-                         "5,6,adaptive)")
+                         "5,6,adaptive=2)")
     args = ap.parse_args()
     w = configs.WORKLOADS[args.workload]
     if args.n_pit is not None:

@@ -143,19 +143,23 @@ def test_far_field_validation_and_workspace(lib):
 
 def test_adaptive_far_field_validation(lib):
     n = ctypes.c_size_t()
-    c = good_params(far_field_depth=4, far_field_order=5).c()
+    sizes = []
+    for R in (0, 1, 2):
+        c = good_params(far_field_depth=4, far_field_order=5, far_field_adaptive=R).c()
+        assert lib.spk_workspace_size(ctypes.byref(c), ctypes.byref(n)) == 0
+        sizes.append(n.value)
+    assert sizes[0] < sizes[1] < sizes[2]
+    c = good_params(far_field_depth=5, far_field_adaptive=2).c()
     assert lib.spk_workspace_size(ctypes.byref(c), ctypes.byref(n)) == 0
-    uniform = n.value
-    c = good_params(far_field_depth=4, far_field_order=5, far_field_adaptive=True).c()
-    assert lib.spk_workspace_size(ctypes.byref(c), ctypes.byref(n)) == 0
-    assert n.value > uniform
-    for bad in [dict(far_field_depth=7, far_field_adaptive=True),
-                dict(far_field_depth=0, far_field_adaptive=True)]:
+    for bad in [dict(far_field_depth=7, far_field_adaptive=1),
+                dict(far_field_depth=6, far_field_adaptive=2),
+                dict(far_field_depth=0, far_field_adaptive=1)]:
         c = good_params(**bad).c()
         assert lib.spk_workspace_size(ctypes.byref(c), ctypes.byref(n)) == EINVAL, bad
-    c = good_params(far_field_depth=3).c()
-    c.far_field_adaptive = 2
-    assert lib.spk_workspace_size(ctypes.byref(c), ctypes.byref(n)) == EINVAL
+    for R in (3, -1):
+        c = good_params(far_field_depth=3).c()
+        c.far_field_adaptive = R
+        assert lib.spk_workspace_size(ctypes.byref(c), ctypes.byref(n)) == EINVAL, R
 
 
 def test_field_workspace_size(lib):

@@ -147,32 +147,36 @@ def test_matches_the_reference_fmm(gpu, depth, order):
 # --------------------------------------------------------------------------
 # Adaptive tree: dense leaves refined once more
 # --------------------------------------------------------------------------
-@pytest.mark.parametrize("dense,sparse,depth,order", [(12000, 1000, 2, 3), (40000, 2000, 2, 4)])
-def test_adaptive_matches_the_reference_fmm(gpu, dense, sparse, depth, order):
+@pytest.mark.parametrize("dense,sparse,depth,order,R", [(12000, 1000, 2, 3, 1),
+                                                      (40000, 2000, 2, 4, 1),
+                                                      (48000, 2000, 2, 3, 2)])
+def test_adaptive_matches_the_reference_fmm(gpu, dense, sparse, depth, order, R):
     from oracle import fmm
     K = inputs.two_density_points(dense, sparse, 0.5, seed=57)
     p = K.shape[1]
     prm = spk.Params(1, p, 1, precision="plain_fp64", far_field_depth=depth,
-                     far_field_order=order, far_field_adaptive=True)
+                     far_field_order=order, far_field_adaptive=R)
     Kd, rd = device_problem(K, [0.0], "plain_fp64", gpu)
     g, (pa, pr) = spk.grad(Kd, rd, prm, potentials=True)
     info = {}
-    gr, ur = fmm.fmm(K.T, depth, order, fmm.distance_kernel(), adaptive=True, info=info)
-    nref = int(info["refined_targets"].sum())
+    gr, ur = fmm.fmm(K.T, depth, order, fmm.distance_kernel(), adaptive=R, info=info)
+    final = info["final_level"]
     got = -host64(g) * p * p
     err = np.abs(got - gr.T).max() / np.abs(gr).max()
-    say(f"  adaptive GPU vs reference FMM, depth {depth} order {order}: {err:.3e} "
-        f"({nref} of {p} targets refined)")
-    assert 0 < nref < p
+    counts = [int((final == depth + q).sum()) for q in range(R + 1)]
+    say(f"  adaptive (R = {R}) GPU vs reference FMM, depth {depth} order {order}: {err:.3e} "
+        f"(targets per final level {counts})")
+    assert all(c > 0 for c in counts)
     assert err <= 1e-13
     assert np.abs(host64(pr) - ur).max() <= 1e-13 * np.abs(ur).max()
 
 
-def test_adaptive_rerun_and_chunks_bitwise(gpu):
+@pytest.mark.parametrize("R", [1, 2])
+def test_adaptive_rerun_and_chunks_bitwise(gpu, R):
     K = inputs.two_density_points(60000, 5000, 0.5, seed=58)
     p = K.shape[1]
     prm = spk.Params(1, p, 1, precision="fp32_comp", far_field_depth=2, far_field_order=4,
-                     far_field_adaptive=True)
+                     far_field_adaptive=R)
     Kd, rd = device_problem(K, [0.0], "fp32_comp", gpu)
     full = spk.grad(Kd, rd, prm)
     assert torch.equal(full, spk.grad(Kd, rd, prm))
@@ -183,26 +187,30 @@ def test_adaptive_rerun_and_chunks_bitwise(gpu):
 def test_adaptive_c2_against_exact_sweep(gpu):
     w = configs.C2
     K, rho = w.trajectory(), w.density()
-    for precision, kernel, eps, tol in (("fp32_comp", "distance", 0.0, 5e-5),
-                                        ("plain_fp64", "log", 0.01, 1e-4)):
+    for precision, kernel, eps, tol, R in (("fp32_comp", "distance", 0.0, 5e-5, 1),
+                                           ("plain_fp64", "log", 0.01, 1e-4, 1),
+                                           ("fp32_comp", "distance", 0.0, 5e-5, 2)):
         Nc, Ns = w.n_shots, w.n_samples
         exact = spk.Params(Nc, Ns, w.grid, precision=precision, eps=eps, kernel=kernel)
         far = spk.Params(Nc, Ns, w.grid, precision=precision, eps=eps, kernel=kernel,
-                         far_field_depth=4, far_field_order=6, far_field_adaptive=True)
+                         far_field_depth=4, far_field_order=6, far_field_adaptive=R)
         Kd, rd = device_problem(K, rho, precision, gpu)
         g0, (pa0, pr0), e0 = spk.grad(Kd, rd, exact, potentials=True, with_energy=True)
         g1, (pa1, pr1), e1 = spk.grad(Kd, rd, far, potentials=True, with_energy=True)
         eg, ep = rel_l2(host64(g1), host64(g0)), rel_l2(host64(pr1), host64(pr0))
-        say(f"  c2 adaptive {precision} {kernel}: grad F rel L2 {eg:.3e}, potential {ep:.3e}")
+        say(f"  c2 adaptive (R = {R}) {precision} {kernel}: grad F rel L2 {eg:.3e}, "
+            f"potential {ep:.3e}")
         assert eg <= tol and ep <= tol / 10
 
 
-def test_adaptive_c3_sampled_against_oracle(gpu):
-    """8.4M samples, depth 5 refined to 6 where dense, order 6: rows against the oracle."""
+@pytest.mark.parametrize("R", [1, 2])
+def test_adaptive_c3_sampled_against_oracle(gpu, R):
+    """8.4M samples, depth 5 refined once or twice where dense, order 6: rows
+    against the oracle."""
     w = configs.C3
     K, rho = w.trajectory(), w.density()
     prm = params_for(w, "fp32_comp", far_field_depth=5, far_field_order=6,
-                     far_field_adaptive=True)
+                     far_field_adaptive=R)
     Kd, rd = device_problem(K, rho, "fp32_comp", gpu)
     spk.grad(Kd, rd, prm)                       # warm-up
     torch.cuda.synchronize()
@@ -215,5 +223,6 @@ def test_adaptive_c3_sampled_against_oracle(gpu):
     t = inputs.sample_targets(prm.p, 256, seed=43)
     ref = oracle.grad(host64(Kd), host64(rd), w.grid, 0.5, 0.0, t)
     err = rel_l2(host64(g)[:, t], ref["dF"])
-    say(f"  c3 adaptive far field: repulsion {rep_ms:.1f} ms, grad rel L2 vs oracle {err:.3e}")
+    say(f"  c3 adaptive (R = {R}) far field: repulsion {rep_ms:.1f} ms, grad rel L2 vs "
+        f"oracle {err:.3e}")
     assert err <= 5e-5

@@ -760,22 +760,22 @@ def test_fmm_reference_refine_rule_by_brute_force():
 
 
 def test_fmm_reference_adaptive_is_the_uniform_tree_per_target():
-    """M2M is exact, so a refined target's sums are those of the uniform tree one
-    level deeper, and any other target's those of the uniform tree."""
+    """M2M is exact, so a target whose final level is l has the sums of the
+    uniform tree of depth l (one and two refinement levels)."""
     from oracle import fmm
-    X = inputs.two_density_points(12000, 1000, 0.5, seed=55).T.copy()
     k = fmm.distance_kernel()
-    info = {}
-    ga, ua = fmm.fmm(X, 2, 3, k, adaptive=True, info=info)
-    ref = info["refined_targets"]
-    assert 0 < ref.sum() < X.shape[0]
-    g2, u2 = fmm.fmm(X, 2, 3, k)
-    g3, u3 = fmm.fmm(X, 3, 3, k)
-    scale = np.abs(g2).max()
-    assert np.abs(ga[~ref] - g2[~ref]).max() <= 1e-12 * scale
-    assert np.abs(ga[ref] - g3[ref]).max() <= 1e-12 * scale
-    assert np.abs(ua[~ref] - u2[~ref]).max() <= 1e-12 * np.abs(u2).max()
-    assert np.abs(ua[ref] - u3[ref]).max() <= 1e-12 * np.abs(u3).max()
+    for R, (dense, sparse) in ((1, (12000, 1000)), (2, (48000, 2000))):
+        X = inputs.two_density_points(dense, sparse, 0.5, seed=55).T.copy()
+        info = {}
+        ga, ua = fmm.fmm(X, 2, 3, k, adaptive=R, info=info)
+        final = info["final_level"]
+        for lvl in range(2, 3 + R):
+            sel = final == lvl
+            assert 0 < sel.sum() < X.shape[0], (R, lvl)
+            gu, uu = fmm.fmm(X, lvl, 3, k, only=sel)
+            scale = np.abs(gu[sel]).max()
+            assert np.abs(ga[sel] - gu[sel]).max() <= 1e-12 * scale, (R, lvl)
+            assert np.abs(ua[sel] - uu[sel]).max() <= 1e-12 * np.abs(uu[sel]).max(), (R, lvl)
 
 
 def test_fmm_reference_adaptive_exact_for_polynomial_kernel():
@@ -783,8 +783,9 @@ def test_fmm_reference_adaptive_exact_for_polynomial_kernel():
     X = inputs.two_density_points(12000, 1000, 0.5, seed=56).T.copy()
     k = fmm.square_kernel()
     ge, ue = fmm.exact(X, k)
-    info = {}
-    g, u = fmm.fmm(X, 2, 3, k, adaptive=True, info=info)
-    assert 0 < info["refined_targets"].sum() < X.shape[0]
-    assert np.abs(g - ge).max() <= 1e-10 * np.abs(ge).max()
-    assert np.abs(u - ue).max() <= 1e-10 * np.abs(ue).max()
+    for R in (1, 2):
+        info = {}
+        g, u = fmm.fmm(X, 2, 3, k, adaptive=R, info=info)
+        assert 0 < info["refined_targets"].sum() < X.shape[0]
+        assert np.abs(g - ge).max() <= 1e-10 * np.abs(ge).max()
+        assert np.abs(u - ue).max() <= 1e-10 * np.abs(ue).max()
