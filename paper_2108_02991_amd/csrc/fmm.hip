@@ -32,6 +32,8 @@
 #include <algorithm>
 #include <cfloat>
 #include <cmath>
+#include <mutex>
+#include <vector>
 
 #include <hipcub/hipcub.hpp>
 
@@ -1097,6 +1099,34 @@ Cheb make_cheb(int n)
     return ch;
 }
 
+// 1: the near field runs on a second stream beside the upward pass and the
+// interactions (0: on the caller's stream, in order).
+#ifndef SPK_FMM_OVERLAP
+#define SPK_FMM_OVERLAP 1
+#endif
+
+// A second stream per device (default priority) for the near field, which
+// then runs beside the M2L: the two use the vector ALUs and the matrix cores.
+// The caller's stream forks to it after the tree is built and joins it before
+// the L2P adds the far field, so the pair stays ordered on the caller's stream.
+hipError_t side_stream(hipStream_t *out)
+{
+    static std::mutex mu;
+    static std::vector<hipStream_t> streams;
+    int dev = 0;
+    hipError_t e;
+    if ((e = hipGetDevice(&dev)) != hipSuccess)
+        return e;
+    std::lock_guard<std::mutex> lock(mu);
+    if ((int)streams.size() <= dev)
+        streams.resize(dev + 1, nullptr);
+    if (!streams[dev] &&
+        (e = hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking)) != hipSuccess)
+        return e;
+    *out = streams[dev];
+    return hipSuccess;
+}
+
 template <int N, typename T>
 hipError_t run_typed(const FmmLaunch &f, hipStream_t s)
 {
@@ -1139,6 +1169,56 @@ hipError_t run_typed(const FmmLaunch &f, hipStream_t s)
         tb = f.temp_bytes;
         if ((e = hipcub::DeviceScan::ExclusiveSum(f.temp, tb, f.chunks[q], f.chunk_start[q],
                                                   (int)(nc + 1), s)) != hipSuccess)
+            return e;
+    }
+    // near field (exact pair sums over the 27 cells around each target's cell
+    // at its final level), on the side stream from here to the L2P
+    hipStream_t ns = s;
+    struct Events {   // released on every path (a pending event may be destroyed)
+        hipEvent_t fork = nullptr, join = nullptr;
+        ~Events()
+        {
+            if (fork)
+                (void)hipEventDestroy(fork);
+            if (join)
+                (void)hipEventDestroy(join);
+        }
+    } ev;
+    if (SPK_FMM_OVERLAP) {
+        if ((e = side_stream(&ns)) != hipSuccess ||
+            (e = hipEventCreateWithFlags(&ev.fork, hipEventDisableTiming)) != hipSuccess ||
+            (e = hipEventCreateWithFlags(&ev.join, hipEventDisableTiming)) != hipSuccess ||
+            (e = hipEventRecord(ev.fork, s)) != hipSuccess ||
+            (e = hipStreamWaitEvent(ns, ev.fork, 0)) != hipSuccess)
+            return e;
+    }
+    NearLaunch nl;
+    nl.precision = f.precision;
+    nl.kernel = f.kernel;
+    nl.energy = f.energy;
+    nl.xs = xs;
+    nl.ys = ys;
+    nl.zs = zs;
+    nl.order = f.vals_out;
+    nl.start = f.start;
+    nl.sD = sD;
+    nl.t0 = f.t0;
+    nl.nt = f.nt;
+    nl.eps = f.eps;
+    nl.acc = f.acc;
+    nl.ld = f.ld;
+    for (int q = 0; q <= R; ++q) {
+        nl.sub = q;
+        nl.stride = stride_at(q);
+        nl.chunk_start = f.chunk_start[q];
+        nl.ncells = ncells_at(q);
+        nl.side = sD << q;
+        nl.max_blocks = (p + f.near_tpb - 1) / f.near_tpb + ncells_at(q);
+        if ((e = launch_near(nl, ns)) != hipSuccess)
+            return e;
+    }
+    if (SPK_FMM_OVERLAP) {
+        if ((e = hipEventRecord(ev.join, ns)) != hipSuccess)
             return e;
     }
     // multipole weights: zero (padding included), the deepest level, then upward
@@ -1224,31 +1304,9 @@ hipError_t run_typed(const FmmLaunch &f, hipStream_t s)
     }
     if ((e = hipGetLastError()) != hipSuccess)
         return e;
-    // near field (exact pair sums over the 27 cells around each target's cell
-    // at its final level), then the far field
-    NearLaunch nl;
-    nl.precision = f.precision;
-    nl.kernel = f.kernel;
-    nl.energy = f.energy;
-    nl.xs = xs;
-    nl.ys = ys;
-    nl.zs = zs;
-    nl.order = f.vals_out;
-    nl.start = f.start;
-    nl.sD = sD;
-    nl.t0 = f.t0;
-    nl.nt = f.nt;
-    nl.eps = f.eps;
-    nl.acc = f.acc;
-    nl.ld = f.ld;
-    for (int q = 0; q <= R; ++q) {
-        nl.sub = q;
-        nl.stride = stride_at(q);
-        nl.chunk_start = f.chunk_start[q];
-        nl.ncells = ncells_at(q);
-        nl.side = sD << q;
-        nl.max_blocks = (p + f.near_tpb - 1) / f.near_tpb + ncells_at(q);
-        if ((e = launch_near(nl, s)) != hipSuccess)
+    // the near field's sums are in acc before the far field is added
+    if (SPK_FMM_OVERLAP) {
+        if ((e = hipStreamWaitEvent(s, ev.join, 0)) != hipSuccess)
             return e;
     }
     L2pLevels lv{};
