@@ -1099,16 +1099,17 @@ Cheb make_cheb(int n)
     return ch;
 }
 
-// 1: the near field runs on a second stream beside the upward pass and the
-// interactions (0: on the caller's stream, in order).
+// 1: the near field runs on a second stream beside the interactions (0: on
+// the caller's stream, in order).
 #ifndef SPK_FMM_OVERLAP
 #define SPK_FMM_OVERLAP 1
 #endif
 
 // A second stream per device (default priority) for the near field, which
 // then runs beside the M2L: the two use the vector ALUs and the matrix cores.
-// The caller's stream forks to it after the tree is built and joins it before
-// the L2P adds the far field, so the pair stays ordered on the caller's stream.
+// The caller's stream forks to it after the upward pass (which then keeps the
+// whole chip) and joins it before the L2P adds the far field, so the pair
+// stays ordered on the caller's stream.
 hipError_t side_stream(hipStream_t *out)
 {
     static std::mutex mu;
@@ -1169,56 +1170,6 @@ hipError_t run_typed(const FmmLaunch &f, hipStream_t s)
         tb = f.temp_bytes;
         if ((e = hipcub::DeviceScan::ExclusiveSum(f.temp, tb, f.chunks[q], f.chunk_start[q],
                                                   (int)(nc + 1), s)) != hipSuccess)
-            return e;
-    }
-    // near field (exact pair sums over the 27 cells around each target's cell
-    // at its final level), on the side stream from here to the L2P
-    hipStream_t ns = s;
-    struct Events {   // released on every path (a pending event may be destroyed)
-        hipEvent_t fork = nullptr, join = nullptr;
-        ~Events()
-        {
-            if (fork)
-                (void)hipEventDestroy(fork);
-            if (join)
-                (void)hipEventDestroy(join);
-        }
-    } ev;
-    if (SPK_FMM_OVERLAP) {
-        if ((e = side_stream(&ns)) != hipSuccess ||
-            (e = hipEventCreateWithFlags(&ev.fork, hipEventDisableTiming)) != hipSuccess ||
-            (e = hipEventCreateWithFlags(&ev.join, hipEventDisableTiming)) != hipSuccess ||
-            (e = hipEventRecord(ev.fork, s)) != hipSuccess ||
-            (e = hipStreamWaitEvent(ns, ev.fork, 0)) != hipSuccess)
-            return e;
-    }
-    NearLaunch nl;
-    nl.precision = f.precision;
-    nl.kernel = f.kernel;
-    nl.energy = f.energy;
-    nl.xs = xs;
-    nl.ys = ys;
-    nl.zs = zs;
-    nl.order = f.vals_out;
-    nl.start = f.start;
-    nl.sD = sD;
-    nl.t0 = f.t0;
-    nl.nt = f.nt;
-    nl.eps = f.eps;
-    nl.acc = f.acc;
-    nl.ld = f.ld;
-    for (int q = 0; q <= R; ++q) {
-        nl.sub = q;
-        nl.stride = stride_at(q);
-        nl.chunk_start = f.chunk_start[q];
-        nl.ncells = ncells_at(q);
-        nl.side = sD << q;
-        nl.max_blocks = (p + f.near_tpb - 1) / f.near_tpb + ncells_at(q);
-        if ((e = launch_near(nl, ns)) != hipSuccess)
-            return e;
-    }
-    if (SPK_FMM_OVERLAP) {
-        if ((e = hipEventRecord(ev.join, ns)) != hipSuccess)
             return e;
     }
     // multipole weights: zero (padding included), the deepest level, then upward
@@ -1294,6 +1245,56 @@ hipError_t run_typed(const FmmLaunch &f, hipStream_t s)
         plan.ntc[i] = (Q3 + TN - 1) / TN;
         plan.first[i] = plan.ntiles;
         plan.ntiles += 8 * plan.ntc[i];
+    }
+    // near field (exact pair sums over the 27 cells around each target's cell
+    // at its final level), on the side stream beside the M2L, up to the L2P
+    hipStream_t ns = s;
+    struct Events {   // released on every path (a pending event may be destroyed)
+        hipEvent_t fork = nullptr, join = nullptr;
+        ~Events()
+        {
+            if (fork)
+                (void)hipEventDestroy(fork);
+            if (join)
+                (void)hipEventDestroy(join);
+        }
+    } ev;
+    if (SPK_FMM_OVERLAP) {
+        if ((e = side_stream(&ns)) != hipSuccess ||
+            (e = hipEventCreateWithFlags(&ev.fork, hipEventDisableTiming)) != hipSuccess ||
+            (e = hipEventCreateWithFlags(&ev.join, hipEventDisableTiming)) != hipSuccess ||
+            (e = hipEventRecord(ev.fork, s)) != hipSuccess ||
+            (e = hipStreamWaitEvent(ns, ev.fork, 0)) != hipSuccess)
+            return e;
+    }
+    NearLaunch nl;
+    nl.precision = f.precision;
+    nl.kernel = f.kernel;
+    nl.energy = f.energy;
+    nl.xs = xs;
+    nl.ys = ys;
+    nl.zs = zs;
+    nl.order = f.vals_out;
+    nl.start = f.start;
+    nl.sD = sD;
+    nl.t0 = f.t0;
+    nl.nt = f.nt;
+    nl.eps = f.eps;
+    nl.acc = f.acc;
+    nl.ld = f.ld;
+    for (int q = 0; q <= R; ++q) {
+        nl.sub = q;
+        nl.stride = stride_at(q);
+        nl.chunk_start = f.chunk_start[q];
+        nl.ncells = ncells_at(q);
+        nl.side = sD << q;
+        nl.max_blocks = (p + f.near_tpb - 1) / f.near_tpb + ncells_at(q);
+        if ((e = launch_near(nl, ns)) != hipSuccess)
+            return e;
+    }
+    if (SPK_FMM_OVERLAP) {
+        if ((e = hipEventRecord(ev.join, ns)) != hipSuccess)
+            return e;
     }
     const int64_t nblocks = (plan.ntiles + kXcds - 1) / kXcds * kXcds * plan.ntr;
     hipLaunchKernelGGL(m2l_kernel<N>, dim3((unsigned)nblocks), dim3(kM2lThreads), 0, s, plan);
