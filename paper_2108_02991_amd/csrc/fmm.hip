@@ -447,7 +447,7 @@ __global__ __launch_bounds__(EW) void transfer_kernel(Cheb ch, double *Tm)
 #define SPK_M2L_TN 64
 #endif
 #ifndef SPK_M2L_TK
-#define SPK_M2L_TK 16
+#define SPK_M2L_TK 8     // 216 = 27 x 8: no k padding at order 6
 #endif
 constexpr int TM = 128, TN = SPK_M2L_TN, TK = SPK_M2L_TK;
 constexpr int kM2lThreads = 256, kXcds = 8, kOffsets = 343, kMaxList = 189;
