@@ -226,3 +226,48 @@ def test_adaptive_c3_sampled_against_oracle(gpu, R):
     say(f"  c3 adaptive (R = {R}) far field: repulsion {rep_ms:.1f} ms, grad rel L2 vs "
         f"oracle {err:.3e}")
     assert err <= 5e-5
+
+
+def test_adaptive_edge_cases(gpu):
+    """Adaptive trees on degenerate inputs: coincident samples (nothing is
+    refined, all pairs are near: the exact sum), samples outside [-L, L]^3,
+    and tiny p."""
+    def pair(K, depth, order, R, precision="plain_fp64"):
+        Nc, Ns = 1, K.shape[1]
+        exact = spk.Params(Nc, Ns, 4, precision=precision)
+        far = spk.Params(Nc, Ns, 4, precision=precision, far_field_depth=depth,
+                         far_field_order=order, far_field_adaptive=R)
+        Kd, rd = device_problem(K, inputs.uniform_density(4), precision, gpu)
+        g0 = host64(spk.grad(Kd, rd, exact))
+        g1 = host64(spk.grad(Kd, rd, far))
+        return g0, g1
+
+    for R in (1, 2):
+        g0, g1 = pair(np.full((3, 700), 0.125), 3, 5, R)
+        assert np.array_equal(g0, g1), R
+        K = inputs.uniform_points(3000, 0.5, seed=5) * np.array([[3.0], [0.7], [1.5]])
+        g0, g1 = pair(K, 3, 6, R)
+        say(f"  adaptive R = {R}, outside the box: grad rel L2 vs exact {rel_l2(g1, g0):.3e}")
+        assert rel_l2(g1, g0) <= 3e-5
+        # one sample: no pair at all; a few: far pairs are interpolated (order 4)
+        g0, g1 = pair(inputs.uniform_points(1, 0.5, seed=1), 2, 4, R)
+        assert np.array_equal(g0, g1), R
+        for p in (2, 5):
+            g0, g1 = pair(inputs.uniform_points(p, 0.5, seed=p), 2, 4, R)
+            assert rel_l2(g1, g0) <= 1e-3, (R, p)
+
+
+def test_adaptive_two_levels_fp64_against_the_oracle(gpu):
+    """Plain FP64 with two refinement levels on a dense two-density input,
+    against the FP64 oracle's exact sums."""
+    K = inputs.two_density_points(48000, 2000, 0.5, seed=59)
+    p = K.shape[1]
+    prm = spk.Params(1, p, 1, precision="plain_fp64", far_field_depth=3, far_field_order=6,
+                     far_field_adaptive=2)
+    Kd, rd = device_problem(K, [1.0], "plain_fp64", gpu)
+    g = host64(spk.grad(Kd, rd, prm))
+    t = inputs.sample_targets(p, 400, seed=60)
+    ref = oracle.grad(host64(Kd), host64(rd), 1, 0.5, 0.0, t)
+    err = rel_l2(g[:, t], ref["dF"])
+    say(f"  adaptive R = 2, FP64, 50k samples: grad rel L2 vs oracle {err:.3e}")
+    assert err <= 3e-5
