@@ -1,6 +1,9 @@
 // Far field of the repulsion sums by a Chebyshev-interpolation fast multipole
-// method on a uniform octree (the hierarchical far field for very large p; the
-// paper uses a CPU FMM of this family, "Evaluating F^r and its gradient").
+// method on an octree (the hierarchical far field for very large p; the paper
+// uses a CPU FMM of this family, "Evaluating F^r and its gradient").  The
+// octree is uniform to depth D; optionally, cells whose near field is dense
+// are refined up to R = 2 levels further, and a target then takes its near
+// field and its local expansion at the deepest level its cells reach.
 //
 // For target i and every sample j farther than the 27 leaves around i's leaf,
 // H(x_i - x_j) and grad H(x_i - x_j) are replaced by their tensor Chebyshev
@@ -16,18 +19,22 @@
 // Chebyshev interpolation polynomials
 //   S_k(t) = 1/n + (2/n) sum_{i=1}^{n-1} T_i(tbar_k) T_i(t),  tbar_k = cos((2k+1) pi / 2n),
 // and t the coordinate in the cell scaled to [-1, 1].  The near field (27
-// leaves) is summed exactly by the sample sweep's pair arithmetic (sweep.hip).
+// cells) is summed exactly by the sample sweep's pair arithmetic (sweep.hip),
+// on a second stream beside the M2L.
 //
-// Layout.  Samples are sorted by leaf (stable radix sort of the leaf index,
-// x fastest); leaf k owns sorted samples [start[k], start[k+1]).  The cells of
-// level l (2^l per axis) are split into 8 parity classes; each class is a
-// sub-grid of side Q = 2^l / 2 padded by 2 zero cells on every side (side
-// P = Q + 4).  A target class and an offset of its interaction list then map
-// every target to its source by one constant shift of the padded linear
-// index, so M2L is a GEMM over the class's cells: C[col][row] +=
-// A_o[row][k] B[col + shift][k], with rows (component, node) and k the source
-// nodes.  Empty cells (no samples) are skipped.  Every stage runs in double
-// precision and in a fixed order.
+// Layout.  Samples are sorted (stable radix sort) by the composite index of
+// their cell R levels below the leaves (comp_index: x-fastest leaf index, then
+// child positions), so every cell of every level from the leaves down owns
+// one run of the sorted samples.  The cells of level l (2^l per axis) are
+// split into 8 parity classes; each class is a sub-grid of side Q = 2^l / 2
+// padded by 2 zero cells on every side (side P = Q + 4).  A target class and
+// an offset of its interaction list then map every target to its source by
+// one constant shift of the padded linear index, so M2L is a GEMM over the
+// class's cells, run on the FP64 matrix cores: C[col][row] += A_o[row][k]
+// B[col + shift][k], with rows (component, node) and k the source nodes.  M2M
+// and L2L use the same GEMM loop with the transfer matrices.  Empty cells (no
+// samples) are skipped.  Every stage runs in double precision and in a fixed
+// order.
 
 #include <algorithm>
 #include <cfloat>
