@@ -13,9 +13,9 @@
 // two real kernels share one complex transform (K_a + i K_b): since rho is
 // real, the real and imaginary parts of the inverse are the two convolutions.
 //
-// The 3-D transform is three passes of 1-D radix-2 transforms of length M, 8
-// lines per block in LDS (4 at M = 1024; bit-reversed load, in-place
-// butterflies).  Along x the lines are contiguous; along y and z a block takes
+// The 3-D transform is three passes of 1-D transforms of length M, 8 lines
+// per block in LDS (4 at M = 1024; bit-reversed load, in-place radix-2
+// butterflies taken two stages at a time).  Along x the lines are contiguous; along y and z a block takes
 // neighbouring lines in x, so each step along the line reads 8 (4) consecutive
 // complex values.
 
@@ -128,18 +128,47 @@ __global__ __launch_bounds__(kFftThreads) void fft_kernel(Cx *a, int axis, const
         s[i][rj] = a[at(i, j)];
     }
     __syncthreads();
+    // u +- w v for stage st's twiddle index k (conjugate when inverse)
+    auto bfly = [&](Cx &u, Cx &v, int k) {
+        const Cx w = tw[k];
+        const double wi = inverse ? -w.im : w.im;
+        const Cx vw = Cx{v.re * w.re - v.im * wi, v.re * wi + v.im * w.re};
+        const Cx a = u;
+        u = Cx{a.re + vw.re, a.im + vw.im};
+        v = Cx{a.re - vw.re, a.im - vw.im};
+    };
+    // stages st and st + 1 together: each group of 4 elements (distance
+    // half = 2^(st-1)) does stage st's two butterflies, then stage st+1's two,
+    // in registers; one barrier per pair of stages
+    int st = 1;
 #pragma unroll 1
-    for (int st = 1; st <= LOG2M; ++st) {
+    for (; st + 1 <= LOG2M; st += 2) {
+        const int half = 1 << (st - 1);
+        for (int q = t; q < kLines * (M / 4); q += kFftThreads) {
+            const int i = q / (M / 4), r = q % (M / 4);
+            const int pos = r & (half - 1), lo = 4 * (r - pos) + pos;
+            Cx a0 = s[i][lo], a1 = s[i][lo + half], a2 = s[i][lo + 2 * half],
+               a3 = s[i][lo + 3 * half];
+            bfly(a0, a1, pos << (LOG2M - st));
+            bfly(a2, a3, pos << (LOG2M - st));
+            bfly(a0, a2, pos << (LOG2M - st - 1));
+            bfly(a1, a3, (pos + half) << (LOG2M - st - 1));
+            s[i][lo] = a0;
+            s[i][lo + half] = a1;
+            s[i][lo + 2 * half] = a2;
+            s[i][lo + 3 * half] = a3;
+        }
+        __syncthreads();
+    }
+    if (st == LOG2M) {   // odd number of stages: the last one alone
         const int half = 1 << (st - 1);
         for (int q = t; q < kLines * (M / 2); q += kFftThreads) {
             const int i = q / (M / 2), r = q % (M / 2);
-            const int pos = r & (half - 1), lo = 2 * (r - pos) + pos, hi = lo + half;
-            const Cx w = tw[pos << (LOG2M - st)];
-            const double wi = inverse ? -w.im : w.im;
-            const Cx u = s[i][lo], v = s[i][hi];
-            const Cx vw = Cx{v.re * w.re - v.im * wi, v.re * wi + v.im * w.re};
-            s[i][lo] = Cx{u.re + vw.re, u.im + vw.im};
-            s[i][hi] = Cx{u.re - vw.re, u.im - vw.im};
+            const int pos = r & (half - 1), lo = 2 * (r - pos) + pos;
+            Cx u = s[i][lo], v = s[i][lo + half];
+            bfly(u, v, pos << (LOG2M - st));
+            s[i][lo] = u;
+            s[i][lo + half] = v;
         }
         __syncthreads();
     }
