@@ -240,7 +240,8 @@ struct Layout {
     // far field (only with far_field_depth > 0)
     size_t fmm_box_part = 0, fmm_box = 0, fmm_keys_in = 0, fmm_keys_out = 0, fmm_vals_in = 0,
            fmm_vals_out = 0, fmm_xs = 0, fmm_start = 0,
-           fmm_temp = 0, fmm_temp_bytes = 0, fmm_A = 0, fmm_Tm = 0, fmm_Tu = 0, fmm_Td = 0;
+           fmm_temp = 0, fmm_temp_bytes = 0, fmm_A = 0, fmm_Tm = 0, fmm_Tu = 0, fmm_Td = 0,
+           fmm_part = 0;
     size_t fmm_chunks_q[kMaxRefine + 1] = {}, fmm_chunk_start_q[kMaxRefine + 1] = {},
            fmm_refined[kMaxRefine] = {}, fmm_tmask[kMaxRefine + 1] = {},
            fmm_tflag[kMaxRefine + 1] = {}, fmm_tscan[kMaxRefine + 1] = {},
@@ -334,6 +335,7 @@ Layout make_layout(const spk_params *prm)
         L.fmm_Tm = take(sizeof(double) * 8 * n3 * n3);
         L.fmm_Tu = take(sizeof(double) * fmm_trans_doubles(n));
         L.fmm_Td = take(sizeof(double) * fmm_trans_doubles(n));
+        L.fmm_part = take(sizeof(double) * fmm_split_doubles(n, F));
     }
     L.total = off + 256;   // slack for aligning the caller's base pointer
     return L;
@@ -491,6 +493,7 @@ int run_far_field(const spk_params *prm, const void *kx, const void *ky, const v
     f.Tm = w.at<double>(L.fmm_Tm);
     f.Tu = w.at<double>(L.fmm_Tu);
     f.Td = w.at<double>(L.fmm_Td);
+    f.part = w.at<double>(L.fmm_part);
     Timed tm(SPK_KIND_REPULSION, 0.0, s);
     SPK_HIP(launch_fmm_repulsion(f, s), "far-field repulsion");
     return SPK_OK;

@@ -567,10 +567,89 @@ struct M2lPlan {
     Level lev[kMaxLevels];
     const double *At[kMaxLevels];  // table of each level
     int64_t ntc[kMaxLevels];       // column tiles per class of each level
-    int64_t first[kMaxLevels];     // first column tile (all classes) of each level
+    int64_t first[kMaxLevels];     // first tile (all classes and parts) of each level
+    int nsplit[kMaxLevels];        // parts of each tile's interaction list
+    int64_t pfirst[kMaxLevels];    // first partial tile of each level (nsplit > 1)
+    double *part;                  // partial tiles, TM x TN each
     int nlev, ntr;                 // levels, row tiles
-    int64_t ntiles;                // column tiles of all levels and classes
+    int64_t ntiles;                // tiles of all levels, classes and parts
 };
+
+// Parts of every tile's interaction list at a level with `blocks` tile
+// blocks: levels with few tiles (the coarse ones) split their lists so that
+// the long chain of one tile's offsets runs on several blocks.
+inline int m2l_split(int64_t blocks)
+{
+    int s = 1;
+    while (s < 8 && blocks * s * 2 <= 1024)
+        s *= 2;
+    return s;
+}
+
+// Columns of tile (class ct, column tile cti) of a level: colpad (padded
+// index of the target cell, -1 for none), colsrc (its weights' offset) and
+// outidx (its expansion's offset).  Returns 1 when this thread's column holds
+// a target cell.  Threads t < TN only.
+template <int N3, int ROWS>
+__device__ inline int tile_column(const Level &lev, int ct, int64_t cti, int t, int64_t *colpad,
+                                  int64_t *colsrc, int64_t *outidx)
+{
+    const int64_t P = lev.P, P3 = P * P * P, Q = lev.side / 2, Q3 = Q * Q * Q;
+    const int64_t c0 = cti * TN;
+    int64_t pc = -1;
+    int mine = 0;
+    if (lev.tlist) {          // columns from the class's list of target cells
+        const int64_t c = lev.tscan[ct * Q3] + c0 + t;
+        if (c < lev.tscan[(ct + 1) * Q3]) {
+            pc = lev.tlist[c];
+            mine = 1;
+        }
+    } else {
+        const int64_t c = c0 + t;
+        if (c < Q3) {
+            const int64_t ux = c % Q, uy = (c / Q) % Q, uz = c / (Q * Q);
+            pc = (ux + 2) + P * ((uy + 2) + P * (uz + 2));
+            mine = lev.tmask[(int64_t)ct * P3 + pc];
+        }
+    }
+    colpad[t] = pc;
+    colsrc[t] = pc >= 0 ? pc * N3 : -1;
+    outidx[t] = pc >= 0 ? ((int64_t)ct * P3 + pc) * ROWS : -1;
+    return mine;
+}
+
+// The tile of a block in the plan: level i, class ct, column tile cti and
+// part a of its interaction list.
+__device__ inline int plan_tile(const M2lPlan &plan, int64_t tile, Level &lev, const double *&At,
+                                int64_t &cti, int &ct, int &a, int &nsplit, int64_t &pbase)
+{
+    int li = 0;
+#pragma unroll
+    for (int i = 1; i < kMaxLevels; ++i)
+        if (i < plan.nlev && tile >= plan.first[i])
+            li = i;
+    // a select, not an index, keeps the plan in SGPRs
+    lev = plan.lev[0];
+    At = plan.At[0];
+    int64_t ntc = plan.ntc[0], first = 0, pfirst = plan.pfirst[0];
+    nsplit = plan.nsplit[0];
+#pragma unroll
+    for (int i = 1; i < kMaxLevels; ++i)
+        if (i == li) {
+            lev = plan.lev[i];
+            At = plan.At[i];
+            ntc = plan.ntc[i];
+            first = plan.first[i];
+            nsplit = plan.nsplit[i];
+            pfirst = plan.pfirst[i];
+        }
+    const int64_t local = tile - first, base = local / nsplit;
+    a = (int)(local % nsplit);
+    cti = base % ntc;
+    ct = (int)(base / ntc);
+    pbase = pfirst + base * plan.ntr * nsplit;   // + rt * nsplit + a
+    return li;
+}
 
 // The matrix-core loop shared by M2L, M2M and L2L: acc += sum over the nlist
 // entries a and the k tiles of A_a[rows][k] B_a[k][columns].  A_a is stored
@@ -713,51 +792,20 @@ __global__ __launch_bounds__(kM2lThreads) void m2l_kernel(M2lPlan plan)
     __shared__ int nlist;
 
     int rt;
-    int64_t tile = block_tile(plan.ntr, rt);
+    const int64_t tile = block_tile(plan.ntr, rt);
     if (tile >= plan.ntiles)
         return;
-    // the tile's level (a select, not an index, keeps the plan in SGPRs)
-    Level lev = plan.lev[0];
-    const double *At = plan.At[0];
-    int64_t ntiles_c = plan.ntc[0], lfirst = 0;
-#pragma unroll
-    for (int i = 1; i < kMaxLevels; ++i)
-        if (i < plan.nlev && tile >= plan.first[i]) {
-            lev = plan.lev[i];
-            At = plan.At[i];
-            ntiles_c = plan.ntc[i];
-            lfirst = plan.first[i];
-        }
-    tile -= lfirst;
-    const int64_t cti = tile % ntiles_c;
-    const int ct = (int)(tile / ntiles_c);
-
-    const int64_t P = lev.P, P3 = P * P * P, Q = lev.side / 2, Q3 = Q * Q * Q;
+    Level lev;
+    const double *At;
+    int64_t cti, pbase;
+    int ct, part, nsplit;
+    plan_tile(plan, tile, lev, At, cti, ct, part, nsplit, pbase);
+    const int64_t P = lev.P, P3 = P * P * P;
     const int row0 = rt * TM;
-    const int64_t c0 = cti * TN;
     const int t = threadIdx.x, lane = t % 64, wave = t / 64;
-    const int32_t *occ_t = lev.tmask + (int64_t)ct * P3;
     int mine = 0;
-    if (t < TN) {
-        int64_t pc = -1;
-        if (lev.tlist) {          // columns from the class's list of target cells
-            const int64_t c = lev.tscan[ct * Q3] + c0 + t;
-            if (c < lev.tscan[(ct + 1) * Q3]) {
-                pc = lev.tlist[c];
-                mine = 1;
-            }
-        } else {
-            const int64_t c = c0 + t;
-            if (c < Q3) {
-                const int64_t ux = c % Q, uy = (c / Q) % Q, uz = c / (Q * Q);
-                pc = (ux + 2) + P * ((uy + 2) + P * (uz + 2));
-                mine = occ_t[pc];
-            }
-        }
-        colpad[t] = pc;
-        colsrc[t] = pc >= 0 ? pc * N3 : -1;
-        outidx[t] = pc >= 0 ? ((int64_t)ct * P3 + pc) * ROWS : -1;
-    }
+    if (t < TN)
+        mine = tile_column<N3, ROWS>(lev, ct, cti, t, colpad, colsrc, outidx);
     if (!__syncthreads_or(mine))
         return;
 
@@ -800,14 +848,65 @@ __global__ __launch_bounds__(kM2lThreads) void m2l_kernel(M2lPlan plan)
             nlist = base;
     }
     __syncthreads();
-    // no source offset (nlist 0): the tile's expansions are zero
+    // this part's share of the interaction list (no offset at all: zeros)
+    const int lo = part * nlist / nsplit, hi = (part + 1) * nlist / nsplit;
     dbl4 acc[4][TN / 32];
     const double *W = lev.W;
     mfma_gemm<RP, KP, N3>(
-        nlist, [&](int a) { return At + (int64_t)list_o[a] * KP * RP + row0; },
-        [&](int a) { return W + ((int64_t)list_cs[a] * P3 + list_shift[a]) * N3; }, colsrc, As, Bs,
-        acc);
-    mfma_store<false>(acc, outidx, row0, ROWS, lev.L);
+        hi - lo, [&](int a) { return At + (int64_t)list_o[lo + a] * KP * RP + row0; },
+        [&](int a) { return W + ((int64_t)list_cs[lo + a] * P3 + list_shift[lo + a]) * N3; },
+        colsrc, As, Bs, acc);
+    if (nsplit == 1) {
+        mfma_store<false>(acc, outidx, row0, ROWS, lev.L);
+        return;
+    }
+    // partial tile [column][row] (TM rows), summed into the expansions by
+    // m2l_reduce_kernel
+    __syncthreads();
+    if (t < TN)
+        outidx[t] = (int64_t)t * TM;
+    __syncthreads();
+    mfma_store<false>(acc, outidx, 0, TM, plan.part + (pbase + (int64_t)rt * nsplit + part) * TM * TN);
+}
+
+// Sums the partial tiles of split levels in part order into the expansions.
+template <int N>
+__global__ __launch_bounds__(kM2lThreads) void m2l_reduce_kernel(M2lPlan plan, int li)
+{
+    using S = M2lShape<N>;
+    constexpr int N3 = S::N3, ROWS = S::ROWS;
+    __shared__ int64_t colpad[TN], colsrc[TN], outidx[TN];
+    Level lev = plan.lev[0];
+    int64_t ntc = plan.ntc[0], pfirst = plan.pfirst[0];
+    int nsplit = plan.nsplit[0];
+    for (int i = 1; i < kMaxLevels; ++i)
+        if (i == li) {
+            lev = plan.lev[i];
+            ntc = plan.ntc[i];
+            pfirst = plan.pfirst[i];
+            nsplit = plan.nsplit[i];
+        }
+    const int64_t b = blockIdx.x, base = b / plan.ntr;
+    const int rt = (int)(b % plan.ntr);
+    const int64_t cti = base % ntc;
+    const int ct = (int)(base / ntc);
+    const int t = threadIdx.x;
+    int mine = 0;
+    if (t < TN)
+        mine = tile_column<N3, ROWS>(lev, ct, cti, t, colpad, colsrc, outidx);
+    if (!__syncthreads_or(mine))
+        return;                      // the M2L skipped this tile as well
+    const double *pp = plan.part + (pfirst + (base * plan.ntr + rt) * nsplit) * TM * TN;
+    for (int e = t; e < TM * TN; e += kM2lThreads) {
+        const int col = e / TM, row = e % TM;
+        const int64_t o = outidx[col];
+        if (o < 0 || rt * TM + row >= ROWS)
+            continue;
+        double v = 0.0;
+        for (int a = 0; a < nsplit; ++a)
+            v += pp[(int64_t)a * TM * TN + e];
+        lev.L[o + rt * TM + row] = v;
+    }
 }
 
 // ------------------------------------------------------------------ M2M, L2L on the matrix cores
@@ -1043,6 +1142,31 @@ size_t fmm_level_cells(int level)
     return (size_t)(8 * P * P * P);
 }
 
+template <int N>
+size_t split_doubles(int F)
+{
+    constexpr int ntr = M2lShape<N>::RP / TM;
+    size_t n = 0;
+    for (int l = 2; l <= F; ++l) {
+        const int64_t Q = (int64_t(1) << l) / 2, ntc = (Q * Q * Q + TN - 1) / TN;
+        const int sp = m2l_split(8 * ntc * ntr);
+        if (sp > 1)
+            n += (size_t)8 * ntc * ntr * sp * TM * TN;
+    }
+    return n;
+}
+
+size_t fmm_split_doubles(int order, int F)
+{
+    switch (order) {
+    case 3: return split_doubles<3>(F);
+    case 4: return split_doubles<4>(F);
+    case 5: return split_doubles<5>(F);
+    case 6: return split_doubles<6>(F);
+    default: return 0;
+    }
+}
+
 size_t fmm_trans_doubles(int order)
 {
     switch (order) {
@@ -1237,6 +1361,7 @@ hipError_t run_typed(const FmmLaunch &f, hipStream_t s)
     plan.nlev = F - 1;
     plan.ntr = M2lShape<N>::RP / TM;
     plan.ntiles = 0;
+    int64_t npart = 0;
     for (int l = 2; l <= F; ++l) {
         double *At = f.A + (l - 2) * ntab;
         if (f.kernel == kKernelLog)
@@ -1250,9 +1375,14 @@ hipError_t run_typed(const FmmLaunch &f, hipStream_t s)
         plan.lev[i] = lev[l];
         plan.At[i] = At;
         plan.ntc[i] = (Q3 + TN - 1) / TN;
+        plan.nsplit[i] = m2l_split(8 * plan.ntc[i] * plan.ntr);
         plan.first[i] = plan.ntiles;
-        plan.ntiles += 8 * plan.ntc[i];
+        plan.ntiles += 8 * plan.ntc[i] * plan.nsplit[i];
+        plan.pfirst[i] = npart;
+        if (plan.nsplit[i] > 1)
+            npart += 8 * plan.ntc[i] * plan.ntr * plan.nsplit[i];
     }
+    plan.part = f.part;
     // near field (exact pair sums over the 27 cells around each target's cell
     // at its final level), on the side stream beside the M2L, up to the L2P
     hipStream_t ns = s;
@@ -1305,6 +1435,11 @@ hipError_t run_typed(const FmmLaunch &f, hipStream_t s)
     }
     const int64_t nblocks = (plan.ntiles + kXcds - 1) / kXcds * kXcds * plan.ntr;
     hipLaunchKernelGGL(m2l_kernel<N>, dim3((unsigned)nblocks), dim3(kM2lThreads), 0, s, plan);
+    for (int i = 0; i < plan.nlev; ++i)
+        if (plan.nsplit[i] > 1)
+            hipLaunchKernelGGL(m2l_reduce_kernel<N>,
+                               dim3((unsigned)(8 * plan.ntc[i] * plan.ntr)), dim3(kM2lThreads),
+                               0, s, plan, i);
     for (int l = 3; l <= F; ++l) {
         const int64_t Q = lev[l].side / 2, ntc = (4 * Q * Q * Q + TN - 1) / TN;
         hipLaunchKernelGGL(l2l_kernel<N>, dim3(trans_blocks(ntc)), dim3(kM2lThreads), 0, s,

@@ -56,12 +56,14 @@ struct FmmLaunch {
     double *A = nullptr;                  // [F-1][343][k padded][rows padded]
     double *Tm = nullptr;                 // [8][order^3][order^3]
     double *Tu = nullptr, *Td = nullptr;  // M2M and L2L tables, [8][k padded][rows padded]
+    double *part = nullptr;               // M2L partial tiles of split levels
 };
 // Padded class side P and cell slots 8 P^3 of level l.
 int64_t fmm_padded_side(int level);
 size_t fmm_level_cells(int level);
 size_t fmm_table_doubles(int order);  // M2L table of one level, padded
 size_t fmm_trans_doubles(int order);  // one M2M or L2L table, padded
+size_t fmm_split_doubles(int order, int deepest);  // M2L partial tiles
 // Temporary bytes of the cell sort (3 * depth key bits) and of the chunk scans.
 size_t fmm_sort_temp_bytes(int64_t p, int depth);
 // Price of refining one leaf, in direct pairs (adaptive tree).
