@@ -543,11 +543,15 @@ __device__ inline void offset_shift(int o, int ct, int64_t P, int &cs, int64_t &
 
 // ------------------------------------------------------------------ M2L (GEMM)
 // Block (row tile, column tile, class ct): rows are (component, node) pairs,
-// columns the class's cells (Q^3 of them, Q = side/2) in sub-grid order.  For
-// every offset of the interaction list, in increasing order, the block adds
+// columns the class's cells (Q^3 of them, Q = side/2) in sub-grid order, or,
+// at a refined level, the class's listed target cells.  For every offset of
+// the interaction list (or of one contiguous part of it, at levels with few
+// tiles), in increasing order, the block adds
 // A_o[rows][k] W[source][k] with v_mfma_f64_16x16x4 into accumulators held
 // by its four waves (wave w: rows 64 (w & 1) .., columns (TN/2)(w >> 1) ..),
-// and writes the tile once.  Tiles of TK k-values go through two LDS buffers:
+// and writes the tile once (a part writes a partial tile, which
+// m2l_reduce_kernel adds up in part order).  Tiles of TK k-values go through
+// two LDS buffers:
 // the next tile is read from global memory into registers while the matrix
 // cores work on the current one.  Tiles without an occupied target cell are
 // skipped (nothing reads the local expansion of an empty cell), and so are
