@@ -7,6 +7,12 @@ update, the per-shot projection and the constraint check.  Inputs are
 synthetic (seeded jittered radial spokes, radial density) and resident in HBM
 before the timed region.
 
+Warm-up and timed steps each stop at a wall budget (--warmup-budget,
+--time-budget): after a step, no further step starts if one more of the mean
+length would pass the budget.  An exact 8.4M-sample step takes about 26 s, so
+the default 20 timed steps become about 4; the line reports the steps actually
+timed (`steps`) beside the requested ones (`steps_requested`).
+
 Prints one JSON line.  `value` is pair interactions per second over the whole
 step (p^2 repulsion + p*G^3 attraction per step); the roofline object is for
 the dominant kernel (the repulsion sweep), timed live with HIP events on the
@@ -75,8 +81,8 @@ def recorded_traffic(workload: str, precision: str, kernel: str = "distance"):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1)
-    ap.add_argument("--warmup", type=int, default=0)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="c3_fp32_comp_8p4M")
     ap.add_argument("--precision", default=None)
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
@@ -98,6 +104,13 @@ def main():
                     help="repulsion by the Chebyshev fast multipole method (e.g. 5,6 or "
                          "5,6,adaptive=2) instead of all p^2 pairs; value is then an "
                          "equivalent rate and roofline null")
+    ap.add_argument("--time-budget", type=float, default=120.0,
+                    help="wall seconds of the timed region: after each step, timing stops "
+                         "early if one more step of the mean length would pass this budget "
+                         "(at least one step is timed)")
+    ap.add_argument("--warmup-budget", type=float, default=30.0,
+                    help="wall seconds of warm-up steps, by the same rule (at least one step "
+                         "when --warmup > 0)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed region, run a plain 1 GiB device copy three times "
                          "(reference dispatches for HBM byte counters)")
@@ -158,11 +171,20 @@ def main():
     torch.cuda.synchronize()
     log("inputs resident, kernels loaded")
 
+    # Warm-up and timed steps each stop at a wall budget: an exact c3 step
+    # takes about 26 s, so the requested counts may not fit.  Each step ends
+    # with a host read of its info (sparkling_step synchronises the stream).
     it = 0
-    for _ in range(args.warmup):
+    warm = 0
+    tw = time.perf_counter()
+    while warm < args.warmup:
         spk.step_(K, rho, prm, state, it, eta)
         it += 1
-        log(f"warmup step done")
+        warm += 1
+        el = time.perf_counter() - tw
+        log(f"warmup step {warm} done ({el:.1f} s)")
+        if el + el / warm > args.warmup_budget:
+            break
     torch.cuda.synchronize()
 
     spk.timing_reset()
@@ -170,13 +192,20 @@ def main():
     infos = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    while len(infos) < args.steps:
         infos.append(spk.step_(K, rho, prm, state, it, eta))
         it += 1
-        log(f"step {it} done: F={infos[-1]['F']:.9e} eta={infos[-1]['eta']:.4g}")
+        el = time.perf_counter() - t0
+        log(f"step {it} done ({el:.1f} s): F={infos[-1]['F']:.9e} eta={infos[-1]['eta']:.4g}")
+        if el + el / len(infos) > args.time_budget:
+            break
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     spk.timing_enable(False)
+    steps = len(infos)
+    if steps < args.steps:
+        log(f"timed {steps} of {args.steps} requested steps within the {args.time_budget:.0f} s "
+            "budget")
 
     kern = {}
     for name, kind in (("repulsion", spk.KIND_REPULSION), ("attraction", spk.KIND_ATTRACTION),
@@ -186,8 +215,8 @@ def main():
         kern[name] = {"ms": ms, "launches": n, "pairs": pairs}
 
     pairs_per_step = float(p) * p + (float(p) * M if args.attraction == "direct" else 0.0)
-    ms_per_step = 1e3 * elapsed / args.steps
-    value = pairs_per_step * args.steps / elapsed
+    ms_per_step = 1e3 * elapsed / steps
+    value = pairs_per_step * steps / elapsed
 
     rep = kern["repulsion"]
     rep_avg_ms = rep["ms"] / max(rep["launches"], 1)
@@ -196,15 +225,18 @@ def main():
     att = kern["attraction"]
     att_tflops = (FLOP_PER_PAIR_ATTRACTION * att["pairs"] / (att["ms"] * 1e-3) / 1e12
                   if att["ms"] > 0 else None)
-    grad_ms = (rep["ms"] + att["ms"] + kern["interpolation"]["ms"] + kern["other"]["ms"]) / args.steps
+    grad_ms = (rep["ms"] + att["ms"] + kern["interpolation"]["ms"] + kern["other"]["ms"]) / steps
 
     result = {
         "metric": "pair-interactions/s & sec per gradient eval at 8.4M samples, FP32-comp vs FP64",
         "value": value,
         "unit": "pair-interactions/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
+        "steps": steps,
+        "warmup": warm,
+        "steps_requested": args.steps,
+        "warmup_requested": args.warmup,
+        "time_budget_s": args.time_budget,
         "ms_per_step": ms_per_step,
         "higher_is_better": True,
         "scaling": "weak",
@@ -219,17 +251,17 @@ def main():
                                  if ff_depth else None)},
         "s_per_grad_eval": grad_ms / 1e3,
         "kernels": {
-            "repulsion": {"ms_per_step": rep["ms"] / args.steps, "launches_per_step":
-                          rep["launches"] / args.steps, "avg_launch_ms": rep_avg_ms,
+            "repulsion": {"ms_per_step": rep["ms"] / steps, "launches_per_step":
+                          rep["launches"] / steps, "avg_launch_ms": rep_avg_ms,
                           "pairs_per_s": rep["pairs"] / (rep["ms"] * 1e-3), "tflops": achieved},
-            "attraction": {"ms_per_step": att["ms"] / args.steps, "launches_per_step":
-                           att["launches"] / args.steps,
+            "attraction": {"ms_per_step": att["ms"] / steps, "launches_per_step":
+                           att["launches"] / steps,
                            "pairs_per_s": att["pairs"] / (att["ms"] * 1e-3) if att["ms"] else None,
                            "tflops": att_tflops},
-            "interpolation_ms_per_step": kern["interpolation"]["ms"] / args.steps,
+            "interpolation_ms_per_step": kern["interpolation"]["ms"] / steps,
             "field_precompute_s": field_s,
-            "projection_ms_per_step": kern["projection"]["ms"] / args.steps,
-            "other_ms_per_step": kern["other"]["ms"] / args.steps,
+            "projection_ms_per_step": kern["projection"]["ms"] / steps,
+            "other_ms_per_step": kern["other"]["ms"] / steps,
         },
         "roofline": ({"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS,
                       "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK_TFLOPS,
@@ -251,13 +283,22 @@ def main():
     if ff_depth:
         result["value_kind"] = ("equivalent: the all-pairs interactions a step stands for, per "
                                 "second; the far field approximates the repulsion")
+    # The comparison legs run after the timed region; a failure in one is
+    # recorded in the line instead of losing it.
     if args.fp64_fraction > 0 and precision != "plain_fp64" and args.attraction == "direct":
-        result["fp64_plain"] = fp64_comparison(spk, torch, w, prm, K, rho, args.fp64_fraction, dev)
+        try:
+            result["fp64_plain"] = fp64_comparison(spk, torch, w, prm, K, rho,
+                                                   args.fp64_fraction, dev)
+        except Exception as e:   # noqa: BLE001
+            result["fp64_plain"] = {"error": f"{type(e).__name__}: {e}"}
 
     if args.cpu_seconds > 0:
-        result["cpu_baseline"] = cpu_baseline(w, K, rho, args.cpu_seconds,
-                                              field=args.attraction == "field", eps=eps,
-                                              kernel=args.kernel)
+        try:
+            result["cpu_baseline"] = cpu_baseline(w, K, rho, args.cpu_seconds,
+                                                  field=args.attraction == "field", eps=eps,
+                                                  kernel=args.kernel)
+        except Exception as e:   # noqa: BLE001
+            result["cpu_baseline"] = {"error": f"{type(e).__name__}: {e}"}
 
     print(json.dumps(result), flush=True)
 
