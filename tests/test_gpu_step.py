@@ -52,6 +52,59 @@ def test_barzilai_borwein_iterations(gpu):
     assert used >= 2
 
 
+@pytest.mark.parametrize("precision", ["plain_fp64", "fp32_comp"])
+@pytest.mark.parametrize("c1, c2, want, used", [
+    (1 / 64, 1 / 16, 320 / 17, True),         # quotient 320/17 inside [1.6, 160]
+    (5.0, 20.0, 1.6, True),                   # quotient 5/85 below: 0.1 * eta_fixed
+    (1 / 6400, 1 / 1600, 160.0, True),        # quotient 32000/17 above: 10 * eta_fixed
+    (-1 / 64, -1 / 16, 16.0, False),          # s.y < 0: the fixed step
+])
+def test_barzilai_borwein_known_quotient(gpu, precision, c1, c2, want, used):
+    """States with a quotient s.s/s.y fixed by construction (tests/bb_states.py),
+    through sparkling_step and sparkling_step_async: the device dots and the
+    step rule give the quotient inside the clamp range, and the oracle's step."""
+    from bb_states import bb_expected, bb_state, quantise
+    w = configs.C1
+    # a 2^-24 grid keeps K, k_prev = K - s and s exact in FP32 storage too
+    K = quantise(inputs.radial_spokes(16, 64, 0.5, seed=7, jitter=0.01), bits=24)
+    rho = w.density()
+    a, b = bounds(w)
+    prm = spk.Params(16, 64, w.grid, precision=precision, a_max=a, b_max=b, n_pit=200)
+    Kd, rd = device_problem(K, rho, precision, gpu)
+    Kh, rh = host64(Kd), host64(rd)
+    g = oracle.grad(Kh, rh, w.grid, 0.5)["dF"]
+    kp_exact, gp = bb_state(Kh, g, c1, c2, bits=24)
+    # the state as the device stores it: k_prev stays exact in FP32, g_prev rounds once more
+    kp = host64(torch.tensor(kp_exact, dtype=prm.dtype))
+    gp = host64(torch.tensor(gp, dtype=prm.dtype))
+    assert np.array_equal(kp, kp_exact)
+    K1, _, _, oinfo = oracle.step(Kh, rh, 16, 64, w.grid, 0.5, a, b, 0, 200, kp, gp, 25, 16.0)
+    assert oinfo["bb_used"] == used
+    tol = 1e-12 if precision == "plain_fp64" else 2e-5
+    if precision == "plain_fp64":
+        assert oinfo["eta"] == pytest.approx(want, rel=1e-13)
+    for mode in ("sync", "async"):
+        say(f"  BB state c=({c1:.4g}, {c2:.4g}) {precision} {mode}")
+        Kg = torch.tensor(Kh, dtype=prm.dtype, device=gpu)
+        state = spk.StepState(prm, gpu)
+        state.k_prev.copy_(torch.tensor(kp, dtype=prm.dtype))
+        state.g_prev.copy_(torch.tensor(gp, dtype=prm.dtype))
+        if mode == "sync":
+            info = spk.step_(Kg, rd, prm, state, 25, 16.0)
+        else:
+            dinfo = torch.zeros(16, dtype=torch.float64, device=gpu)
+            spk.step_async_(Kg, rd, prm, state, 25, 16.0, dinfo)
+            torch.cuda.synchronize()
+            info = spk.info_dict(dinfo)
+        assert info["bb_used"] == used
+        assert info["eta"] == pytest.approx(oinfo["eta"], rel=tol)
+        if used and 1.6 < want < 160.0:
+            assert info["eta"] == pytest.approx(bb_expected(c1, c2), rel=tol)
+        step = info["eta"] * np.abs(g).max()
+        assert np.abs(host64(Kg) - K1).max() <= (1e-10 if precision == "plain_fp64"
+                                                 else 1e-5 * step + 1e-7)
+
+
 def test_fp32_step_and_resume_bitwise(gpu):
     """Saving the caller-owned state and resuming continues bit-identically."""
     w = configs.C4

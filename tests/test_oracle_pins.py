@@ -595,20 +595,33 @@ def test_step_fixed_then_fallback():
     assert info["eta"] == 3.0 and not info["bb_used"]
 
 
-def test_step_barzilai_borwein():
+@pytest.mark.parametrize("c1, c2, want, used", [
+    (1 / 8, 1 / 2, 40 / 17, True),            # inside [0.1, 10] * eta_fixed: the quotient itself
+    (25 / 2, 50.0, 0.3, True),                # quotient 2/85 below: clamped to 0.1 * eta_fixed
+    (1 / 800, 1 / 200, 30.0, True),           # quotient 4000/17 above: clamped to 10 * eta_fixed
+    (-1 / 8, -1 / 2, 3.0, False),             # s.y < 0: the fixed step
+])
+def test_step_barzilai_borwein_known_quotient(c1, c2, want, used):
+    """States whose quotient s.s/s.y is fixed by construction (tests/bb_states.py):
+    the oracle's step size is the quotient inside the clamp range, the clamp
+    bound outside it, and the fixed step when s.y <= 0; its update then uses
+    that step."""
+    from bb_states import bb2_value, bb_expected, bb_state, quantise
     K, rho, a, b = _small_problem()
-    z = np.zeros_like(K)
-    K1, kp, gp, _ = oracle.step(K, rho, 4, 16, 4, 0.5, a, b, 0, 50, z, z, 0, 3.0)
-    _, _, _, info = oracle.step(K1, rho, 4, 16, 4, 0.5, a, b, 0, 50, kp, gp, 25, 3.0)
-    s = K1 - kp
-    y = oracle.grad(K1, rho, 4, 0.5)["dF"] - gp
-    sy = float((s * y).sum())
-    if sy > 0:
-        want = min(max(float((s * s).sum()) / sy, 0.3), 30.0)
-        assert info["bb_used"]
-        assert info["eta"] == pytest.approx(want, rel=1e-12)
-    else:
-        assert not info["bb_used"]
+    K = quantise(K)
+    g = oracle.grad(K, rho, 4, 0.5)["dF"]
+    kp, gp = bb_state(K, g, c1, c2)
+    if used and 0.3 < bb_expected(c1, c2) < 30.0:
+        assert want == pytest.approx(bb_expected(c1, c2), rel=1e-15)
+        assert abs(bb2_value(c1, c2) - want) > 0.1 * want
+    K1, kp1, gp1, info = oracle.step(K, rho, 4, 16, 4, 0.5, a, b, 0, 50, kp, gp, 25, 3.0)
+    assert info["bb_used"] == used
+    assert info["eta"] == pytest.approx(want, rel=1e-14)
+    assert np.array_equal(kp1, K) and np.array_equal(gp1, g)
+    assert np.array_equal(K1, oracle.project(K - info["eta"] * g, 4, 16, 0.5, a, b, 0, 50))
+    # below iteration 20 the same state takes the fixed step
+    _, _, _, info = oracle.step(K, rho, 4, 16, 4, 0.5, a, b, 0, 50, kp, gp, 19, 3.0)
+    assert info["eta"] == 3.0 and not info["bb_used"]
 
 
 # --------------------------------------------------------------------------
