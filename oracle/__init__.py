@@ -42,11 +42,28 @@ def build(force: bool = False) -> Path:
     return _LIB
 
 
+def build_sanitized(out_dir) -> Path:
+    """oracle.c built with AddressSanitizer and UndefinedBehaviorSanitizer (gcc;
+    any undefined behaviour aborts).  Load it by setting SPK_ORACLE_LIB to the
+    returned path in a process started with gcc's libasan in LD_PRELOAD."""
+    out = Path(out_dir) / "liboracle_asan_ubsan.so"
+    cmd = ["gcc", "-std=c99", "-O1", "-g", "-fno-omit-frame-pointer",
+           "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined",
+           "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC", "-shared", "-Wall",
+           "-Wextra", "-o", str(out), str(_SRC), "-lm"]
+    subprocess.run(cmd, check=True)
+    return out
+
+
 def _load():
     global _lib
     if _lib is None:
-        build()
-        lib = ctypes.CDLL(str(_LIB))
+        override = os.environ.get("SPK_ORACLE_LIB")
+        if override:
+            lib = ctypes.CDLL(override)
+        else:
+            build()
+            lib = ctypes.CDLL(str(_LIB))
         for name, args in {
             "orc_grad": [_i64, _p, _p, _p, _i64, _dbl, _p, _dbl, _int, _i64, _p, _p, _p, _p, _p, _p],
             "orc_energy": [_i64, _p, _p, _p, _i64, _dbl, _p, _dbl, _int, _p],

@@ -8,6 +8,7 @@ is no fallback path.
 from __future__ import annotations
 
 import ctypes
+import os
 import dataclasses
 from dataclasses import dataclass, field
 from pathlib import Path
@@ -52,11 +53,12 @@ _lib = None
 
 
 def load_library(path: Path | str | None = None):
-    """Load libsparkling.so (once).  Raises if it has not been built."""
+    """Load libsparkling.so (once): `path`, else $SPK_LIBRARY, else the in-tree
+    build.  Raises if the file does not exist."""
     global _lib
     if _lib is not None:
         return _lib
-    p = Path(path) if path else LIB_PATH
+    p = Path(path) if path else Path(os.environ.get("SPK_LIBRARY") or LIB_PATH)
     if not p.exists():
         raise RuntimeError(f"{p} is missing: build it with `python -m paper_2108_02991_amd.build`")
     lib = ctypes.CDLL(str(p))

@@ -63,5 +63,31 @@ def build(extra_flags=(), out: Path | None = None, build_dir: Path | None = None
     return out
 
 
+# Host-side sanitizers for the debug build: every flag goes to the host pass
+# only (-Xarch_host), device code is compiled as usual.
+SANITIZE_HOST = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+                 "-Xarch_host", "-fno-sanitize-recover=undefined",
+                 "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-g"]
+
+
+def build_sanitized(out_dir) -> Path:
+    """libsparkling.so with AddressSanitizer and UndefinedBehaviorSanitizer in
+    its host code (argument validation, planning, workspace layout).  Load it
+    with SPK_LIBRARY set to the returned path in a process started with
+    clang's ASan runtime in LD_PRELOAD (asan_runtime())."""
+    out_dir = Path(out_dir)
+    return build(SANITIZE_HOST, out=out_dir / "libsparkling_asan_ubsan.so", build_dir=out_dir)
+
+
+def asan_runtime() -> str:
+    """Path of the ASan runtime of the compiler behind hipcc."""
+    clang = Path(HIPCC).resolve().parent.parent / "lib" / "llvm" / "bin" / "clang"
+    if not clang.exists():
+        clang = Path("/opt/rocm/llvm/bin/clang")
+    r = subprocess.run([str(clang), "-print-file-name=libclang_rt.asan-x86_64.so"],
+                       capture_output=True, text=True, check=True)
+    return r.stdout.strip()
+
+
 if __name__ == "__main__":
     print(build(sys.argv[1:]))
