@@ -283,6 +283,7 @@ typedef struct {
     double  viol[4];      /* out: constraint check of the new K                           */
     int32_t bb_used;      /* out: 1 if the Barzilai-Borwein step was taken                */
     int32_t reserved;
+    double  bb_quotient;  /* out: s.s/s.y before the clamp (t >= 20; NaN for t < 20)       */
 } spk_step_info;
 
 /*
@@ -308,7 +309,7 @@ int sparkling_step(const spk_params *prm, void *kx, void *ky, void *kz, const vo
  * kernels run in the same order; the step size is chosen on the device by the
  * same rule, so K, k_prev and g_prev evolve bit for bit as with
  * sparkling_step.  info_dev: device, 10 doubles, receives {eta, F, F^a, F^r,
- * viol[4], bb_used, 0}.  If F is not finite, eta is NaN and K, k_prev and
+ * viol[4], bb_used, bb_quotient}.  If F is not finite, eta is NaN and K, k_prev and
  * g_prev are left unchanged (the constraint check still reports on K).  The
  * launch sequence depends on iter only through iter >= 20, so one captured
  * graph serves every iteration of a phase.  Enqueues kernels only: no host

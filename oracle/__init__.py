@@ -197,7 +197,7 @@ def step(K, rho, n_shots, n_samples, G, L, a, b, te, n_pit, k_prev, g_prev, it, 
                           _ptr(info))
     _check(rc, "step")
     d = {"eta": info[0], "F": info[1], "Fa": info[2], "Fr": info[3],
-         "viol": info[4:8].copy(), "bb_used": bool(info[8])}
+         "viol": info[4:8].copy(), "bb_used": bool(info[8]), "bb_quotient": info[9]}
     return K, k_prev, g_prev, d
 
 

@@ -520,7 +520,8 @@ int orc_constraint_check(int64_t Nc, int64_t Ns, const double *kx, const double 
  *   coordinates, clamped to [0.1, 10] eta_fixed, and eta_fixed if s.y <= 0;
  *   K_prev = K, g_prev = g, K = P_Q(K - eta g).
  * K, k_prev, g_prev are 3 arrays of p each, laid out [c * p + i].
- * info_out[0..9] = eta, F, Fa, Fr, viol[0..3], bb_used, (unused 0).
+ * info_out[0..9] = eta, F, Fa, Fr, viol[0..3], bb_used, and the quotient s.s/s.y
+ * before the clamp (NaN below iteration 20).
  */
 int orc_step(int64_t Nc, int64_t Ns, double *K, int64_t G, double L, const double *rho,
              double eps, int kern, double a, double b, int64_t te, int n_pit, int rv,
@@ -553,7 +554,7 @@ int orc_step(int64_t Nc, int64_t Ns, double *K, int64_t G, double L, const doubl
     double fa = cs_get(&sa) / (double)p;
     double fr = cs_get(&sr) / (2.0 * (double)p * (double)p);
 
-    double eta = eta_fixed, bb_used = 0.0;
+    double eta = eta_fixed, bb_used = 0.0, quotient = NAN;
     if (iter >= 20) {
         csum ss = {0, 0}, sy = {0, 0};
         for (int64_t e = 0; e < 3 * p; ++e) {
@@ -562,6 +563,7 @@ int orc_step(int64_t Nc, int64_t Ns, double *K, int64_t G, double L, const doubl
             cs_add(&sy, sv * yv);
         }
         double vss = cs_get(&ss), vsy = cs_get(&sy);
+        quotient = vss / vsy;
         if (vsy > 0.0 && isfinite(vss / vsy)) {
             eta = vss / vsy;
             if (eta < 0.1 * eta_fixed) eta = 0.1 * eta_fixed;
@@ -585,7 +587,7 @@ int orc_step(int64_t Nc, int64_t Ns, double *K, int64_t G, double L, const doubl
     for (int c = 0; c < 4; ++c)
         info_out[4 + c] = rc ? NAN : viol[c];
     info_out[8] = bb_used;
-    info_out[9] = 0.0;
+    info_out[9] = quotient;
     free(g); free(idx); free(ua); free(ur);
     return rc;
 }

@@ -40,7 +40,8 @@ class SpkParams(ctypes.Structure):
 
 class SpkStepInfo(ctypes.Structure):
     _fields_ = [("iter", _i64), ("eta_fixed", _dbl), ("eta", _dbl), ("F", _dbl), ("Fa", _dbl),
-                ("Fr", _dbl), ("viol", _dbl * 4), ("bb_used", _i32), ("reserved", _i32)]
+                ("Fr", _dbl), ("viol", _dbl * 4), ("bb_used", _i32), ("reserved", _i32),
+                ("bb_quotient", _dbl)]
 
 
 class SparklingError(RuntimeError):
@@ -341,17 +342,19 @@ def step_(K: torch.Tensor, rho: torch.Tensor, prm: Params, state: StepState, it:
                                        ctypes.byref(info), _vp(ws.data_ptr()), ws.numel(), _stream(K))
     _check(rc, "sparkling_step")
     return {"eta": info.eta, "F": info.F, "Fa": info.Fa, "Fr": info.Fr,
-            "viol": np.array(info.viol[:]), "bb_used": bool(info.bb_used)}
+            "viol": np.array(info.viol[:]), "bb_used": bool(info.bb_used),
+            "bb_quotient": info.bb_quotient}
 
 
-INFO_FIELDS = ("eta", "F", "Fa", "Fr", "viol0", "viol1", "viol2", "viol3", "bb_used")
+INFO_FIELDS = ("eta", "F", "Fa", "Fr", "viol0", "viol1", "viol2", "viol3", "bb_used",
+               "bb_quotient")
 
 
 def step_async_(K: torch.Tensor, rho: torch.Tensor, prm: Params, state: StepState, it: int,
                 eta_fixed: float, info: torch.Tensor, ws: torch.Tensor | None = None):
     """Enqueue one projected gradient step on K's current stream with no host
     synchronisation; info (a float64 device tensor of 10) receives eta, F, Fa,
-    Fr, the 4 violations and bb_used.  Pass ws to pin the workspace (needed
+    Fr, the 4 violations, bb_used and the unclamped quotient s.s/s.y.  Pass ws to pin the workspace (needed
     when the call is captured into a graph)."""
     _check_k(K, prm)
     _check_rho(rho, prm)
@@ -372,7 +375,7 @@ def info_dict(info: torch.Tensor) -> dict:
     """The step info of step_async_ (copied to the host) as step_ returns it."""
     v = info.detach().cpu().double().numpy()
     return {"eta": float(v[0]), "F": float(v[1]), "Fa": float(v[2]), "Fr": float(v[3]),
-            "viol": v[4:8].copy(), "bb_used": bool(v[8])}
+            "viol": v[4:8].copy(), "bb_used": bool(v[8]), "bb_quotient": float(v[9])}
 
 
 class StepGraph:

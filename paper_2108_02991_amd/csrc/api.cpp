@@ -972,6 +972,7 @@ int sparkling_step(const spk_params *prm, void *kx, void *ky, void *kz, const vo
         for (int c = 0; c < 4; ++c)
             info->viol[c] = NAN;
         info->bb_used = 0;
+        info->bb_quotient = NAN;
         return fail(SPK_ENONFINITE, "energy is not finite (F = %g); K left unchanged", h[1]);
     }
     if ((rc = enqueue_step_back(prm, kx, ky, kz, k_prev, g_prev, w.info(), w, s)))
@@ -982,6 +983,7 @@ int sparkling_step(const spk_params *prm, void *kx, void *ky, void *kz, const vo
     for (int c = 0; c < 4; ++c)
         info->viol[c] = h[4 + c];
     info->bb_used = h[8] != 0.0;
+    info->bb_quotient = h[9];
     return SPK_OK;
 }
 

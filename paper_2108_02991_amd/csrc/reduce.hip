@@ -203,7 +203,8 @@ __global__ __launch_bounds__(EW) void axpy_save_kernel(T *kx, T *ky, T *kz, T *k
 
 // The step-size rule on the device, from the energy sums scal[0..1] and, in
 // the Barzilai-Borwein phase, the dots scal[2] = s.s and scal[3] = s.y; the
-// same operations, in the same order, as the host-side rule.
+// same operations, in the same order, as the host-side rule.  info[9] keeps
+// the quotient s.s/s.y before the clamp (NaN in the fixed-step phase).
 __global__ void step_policy_kernel(const double *scal, int64_t p, double eta_fixed, int bb,
                                    double *info)
 {
@@ -215,9 +216,11 @@ __global__ void step_policy_kernel(const double *scal, int64_t p, double eta_fix
     const double F = fa - fr;
     double eta = eta_fixed;
     double used = 0.0;
+    double quotient = __builtin_nan("");
     if (bb) {
         const double ss = scal[2], sy = scal[3];
         const double q = ss / sy;
+        quotient = q;
         if (sy > 0.0 && q - q == 0.0) {
             eta = q;
             eta = fmin(fmax(eta, 0.1 * eta_fixed), 10.0 * eta_fixed);
@@ -233,7 +236,7 @@ __global__ void step_policy_kernel(const double *scal, int64_t p, double eta_fix
     info[2] = fa;
     info[3] = fr;
     info[8] = used;
-    info[9] = 0.0;
+    info[9] = quotient;
 }
 
 // Dyadic linear up-sampling of shots (fine sample m at coarse position m/2;

@@ -5,10 +5,13 @@ with per-iteration JSON records.
     python -m paper_2108_02991_amd.driver --workload c5_loop --precision fp32_comp \\
         --iters 100 --out run.jsonl
 
-Every record holds F, F^a, F^r, the step size, whether the Barzilai-Borwein
-step was used, the constraint violations after projection and the wall time
-of the step (HIP-synchronised).  The initial trajectory is projected once
-before the first iteration.
+Every record holds F, F^a, F^r, the discrepancy D = F - (1/2) sum rho rho H
+(the density's self-energy is computed once), ||grad F||_2 at the step's input,
+the step size, whether the Barzilai-Borwein step was used and its quotient
+s.s/s.y before the clamp, the constraint violations after projection, the wall
+time of the step (HIP-synchronised) and the time of each kernel kind (HIP
+events).  The initial trajectory is projected once before the first
+iteration.
 """
 from __future__ import annotations
 
@@ -58,14 +61,22 @@ def run(workload: configs.Workload, precision: str, iters: int, device="cuda:0",
     records = []
     if graph:
         return _run_graph(K, rho, prm, state, eta, iters, precision, viol0, out, log_every)
+    self_energy = density_self_energy(K, rho, prm)
+    api.timing_enable(True)
     for it in range(iters):
         torch.cuda.synchronize(dev)
+        api.timing_reset()
         t0 = time.perf_counter()
         info = api.step_(K, rho, prm, state, it, eta)
         torch.cuda.synchronize(dev)
+        wall = time.perf_counter() - t0
         rec = {"iter": it, "precision": precision, "F": info["F"], "Fa": info["Fa"],
-               "Fr": info["Fr"], "eta": info["eta"], "bb_used": info["bb_used"],
-               "viol": [float(v) for v in info["viol"]], "s": time.perf_counter() - t0}
+               "Fr": info["Fr"], "D": info["F"] - self_energy,
+               "grad_norm": float(torch.linalg.vector_norm(state.g_prev.double())),
+               "eta": info["eta"], "bb_used": info["bb_used"],
+               "bb_quotient": info["bb_quotient"],
+               "viol": [float(v) for v in info["viol"]], "s": wall,
+               "kernel_ms": kernel_ms()}
         if it == 0:
             rec["viol_initial_projection"] = [float(v) for v in viol0]
         records.append(rec)
@@ -76,12 +87,30 @@ def run(workload: configs.Workload, precision: str, iters: int, device="cuda:0",
             print(f"[driver] {precision} iter {it}: F={info['F']:.12e} eta={info['eta']:.5g} "
                   f"viol={np.round(info['viol'], 4).tolist()} {rec['s']:.3f}s",
                   file=sys.stderr, flush=True)
+    api.timing_enable(False)
     F, _, _, _ = api.energy(K, rho, prm)
-    records.append({"final_F": F, "precision": precision})
+    records.append({"final_F": F, "final_D": F - self_energy, "precision": precision})
     if out is not None:
         out.write(json.dumps(records[-1]) + "\n")
         out.flush()
     return records, K
+
+
+KERNEL_KINDS = {"repulsion": api.KIND_REPULSION, "attraction": api.KIND_ATTRACTION,
+                "interpolation": api.KIND_INTERPOLATION, "projection": api.KIND_PROJECTION,
+                "other": api.KIND_OTHER}
+
+
+def kernel_ms() -> dict:
+    """Milliseconds per kernel kind since the last timing reset."""
+    return {name: api.timing_query(kind)[0] for name, kind in KERNEL_KINDS.items()}
+
+
+def density_self_energy(K, rho, prm) -> float:
+    """(1/2) sum_{u,v} rho_u rho_v H(x_u - x_v), the constant that separates the
+    objective F from the discrepancy D (one energy call with the discrepancy)."""
+    F, _, _, D = api.energy(K, rho, dataclasses.replace(prm, discrepancy=True))
+    return F - D
 
 
 def _run_graph(K, rho, prm, state, eta, iters, precision, viol0, out, log_every):
@@ -101,6 +130,7 @@ def _run_graph(K, rho, prm, state, eta, iters, precision, viol0, out, log_every)
             torch.cuda.synchronize(dev)
             info = api.info_dict(g.info)
             rec = {"iter": it, "precision": precision, "graph": True, "F": info["F"],
+                   "bb_quotient": info["bb_quotient"],
                    "Fa": info["Fa"], "Fr": info["Fr"], "eta": info["eta"],
                    "bb_used": info["bb_used"], "viol": [float(v) for v in info["viol"]],
                    "elapsed_s": time.perf_counter() - t0}
@@ -192,6 +222,7 @@ def multiresolution(K0: torch.Tensor, rho: torch.Tensor, prm_full: api.Params, l
             torch.cuda.synchronize(K.device)
             rec = {"level": d, "iter": it, "n_samples": Ns, "F": info["F"], "Fa": info["Fa"],
                    "Fr": info["Fr"], "eta": info["eta"], "bb_used": info["bb_used"],
+                   "bb_quotient": info["bb_quotient"],
                    "viol": [float(v) for v in info["viol"]], "s": time.perf_counter() - t0}
             records.append(rec)
             if out is not None:

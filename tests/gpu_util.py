@@ -44,6 +44,29 @@ def rel_l2(a, b):
     return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
 
 
+def row_rel_max(got, ref, floor_frac=1e-3):
+    """Largest per-row error |got_i - ref_i| / max(|ref_i|, floor) over the rows
+    (columns of a (3, n) array), floor = floor_frac x the rms row norm of ref: a
+    few wrong rows cannot hide inside a relative L2 norm, and rows whose
+    gradient nearly cancels (the echo-time samples at the origin) are measured
+    against the typical row instead of their own tiny norm."""
+    got, ref = np.asarray(got), np.asarray(ref)
+    nr = np.linalg.norm(ref, axis=0)
+    floor = floor_frac * np.sqrt(np.mean(nr * nr))
+    return float((np.linalg.norm(got - ref, axis=0) / np.maximum(nr, floor)).max())
+
+
+# Per-row bounds (row_rel_max) of the gradient against the FP64 oracle.
+ROW_TOL = {"plain_fp64": 1e-11, "fp32_comp": 1e-4, "fp32_acc64": 1e-4, "fp32_naive": 3e-2}
+
+
+def with_te_rows(t, n_shots, n_samples, count=8):
+    """Sampled targets plus the echo-time samples (sample 0) of `count` spread
+    shots, where n_shots samples coincide at the origin."""
+    te = (np.linspace(0, n_shots - 1, count).astype(np.int64)) * n_samples
+    return np.unique(np.concatenate([np.asarray(t, dtype=np.int64), te]))
+
+
 def bounds(w):
     return spk.alpha_beta(configs.GMAX, configs.SMAX, configs.RASTER_DT, configs.DWELL_DT, w.fov,
                           w.kmax, configs.GAMMA_BAR, w.half_width)

@@ -5,7 +5,12 @@ import pytest
 import torch
 
 from gpu_util import (ENERGY_TOL, GRAD_TOL, configs, device_problem, host64, inputs, oracle,
-                      params_for, rel_l2, say, spk)
+                      params_for, rel_l2, row_rel_max, say, spk, with_te_rows)
+
+# Order-6 far field at 8.4M samples against the FP64 oracle's exact sums:
+# relative L2 over the sampled rows, and the worst single row (row_rel_max).
+C3_FAR_L2 = 1e-5
+C3_FAR_ROW = 1e-3
 
 pytestmark = pytest.mark.gpu
 
@@ -99,12 +104,15 @@ def test_c3_far_field_sampled_against_oracle(gpu):
     spk.timing_enable(False)
     rep_ms = spk.timing_query(spk.KIND_REPULSION)[0]
     att_ms = spk.timing_query(spk.KIND_ATTRACTION)[0]
-    t = inputs.sample_targets(prm.p, 256, seed=43)
-    say(f"  c3 far-field repulsion {rep_ms:.1f} ms, attraction {att_ms:.1f} ms; oracle on 256 targets")
+    t = with_te_rows(inputs.sample_targets(prm.p, 256, seed=43), w.n_shots, w.n_samples)
+    say(f"  c3 far-field repulsion {rep_ms:.1f} ms, attraction {att_ms:.1f} ms; oracle on "
+        f"{t.size} targets")
     ref = oracle.grad(host64(Kd), host64(rd), w.grid, 0.5, 0.0, t)
     err = rel_l2(host64(g)[:, t], ref["dF"])
-    say(f"  c3 far field: grad rel L2 vs oracle {err:.3e}")
-    assert err <= 5e-5
+    row = row_rel_max(host64(g)[:, t], ref["dF"])
+    say(f"  c3 far field: grad rel L2 vs oracle {err:.3e}, worst row {row:.3e}")
+    assert err <= C3_FAR_L2
+    assert row <= C3_FAR_ROW
 
 
 def test_step_with_far_field_tracks_the_exact_step(gpu):
@@ -220,12 +228,14 @@ def test_adaptive_c3_sampled_against_oracle(gpu, R):
     torch.cuda.synchronize()
     spk.timing_enable(False)
     rep_ms = spk.timing_query(spk.KIND_REPULSION)[0]
-    t = inputs.sample_targets(prm.p, 256, seed=43)
+    t = with_te_rows(inputs.sample_targets(prm.p, 256, seed=43), w.n_shots, w.n_samples)
     ref = oracle.grad(host64(Kd), host64(rd), w.grid, 0.5, 0.0, t)
     err = rel_l2(host64(g)[:, t], ref["dF"])
+    row = row_rel_max(host64(g)[:, t], ref["dF"])
     say(f"  c3 adaptive (R = {R}) far field: repulsion {rep_ms:.1f} ms, grad rel L2 vs "
-        f"oracle {err:.3e}")
-    assert err <= 5e-5
+        f"oracle {err:.3e}, worst row {row:.3e}")
+    assert err <= C3_FAR_L2
+    assert row <= C3_FAR_ROW
 
 
 def test_adaptive_edge_cases(gpu):

@@ -13,6 +13,7 @@ def same_info(a, b):
     assert a["eta"] == b["eta"] and a["F"] == b["F"] and a["Fa"] == b["Fa"]
     assert a["Fr"] == b["Fr"] and a["bb_used"] == b["bb_used"]
     assert np.array_equal(a["viol"], b["viol"])
+    assert np.array_equal([a["bb_quotient"]], [b["bb_quotient"]], equal_nan=True)
 
 
 @pytest.mark.parametrize("wname,precision", [("c1_plain_fp64_loop", "plain_fp64"),

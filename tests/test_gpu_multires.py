@@ -24,8 +24,10 @@ def test_upsample_matches_oracle(gpu, precision):
 
 
 def test_multiresolution_plain_fp64_matches_oracle(gpu):
+    """Three levels of 22 iterations each: the 20 fixed steps and two
+    Barzilai-Borwein steps per level, step by step against the oracle."""
     w = configs.C1
-    Nc, Ns, levels, n_git, G = 6, 64, 2, 4, 8
+    Nc, Ns, levels, n_git, G = 6, 64, 2, 22, 8
     a, b = spk.alpha_beta(configs.GMAX, configs.SMAX, configs.RASTER_DT, configs.DWELL_DT, w.fov,
                           w.kmax, configs.GAMMA_BAR, 0.5)
     K0 = inputs.radial_spokes(Nc, Ns >> levels, 0.5, seed=3, jitter=0.02)
@@ -42,5 +44,8 @@ def test_multiresolution_plain_fp64_matches_oracle(gpu):
         assert r["level"] == o["level"] and r["iter"] == o["iter"]
         assert r["F"] == pytest.approx(o["F"], rel=1e-11)
         assert r["eta"] == pytest.approx(o["eta"], rel=1e-12)
+        assert r["bb_used"] == o["bb_used"] == (o["iter"] >= 20)
+        if o["iter"] >= 20:
+            assert r["bb_quotient"] == pytest.approx(o["bb_quotient"], rel=1e-9)
     assert Kg.shape == (3, Nc * Ns)
     assert np.abs(host64(Kg) - Ko).max() <= 1e-9

@@ -47,6 +47,9 @@ def test_barzilai_borwein_iterations(gpu):
                                         16.0)
         assert info["bb_used"] == oinfo["bb_used"]
         assert info["eta"] == pytest.approx(oinfo["eta"], rel=1e-9)
+        assert np.isnan(info["bb_quotient"]) == (it < 20)
+        if it >= 20:
+            assert info["bb_quotient"] == pytest.approx(oinfo["bb_quotient"], rel=1e-9)
         assert np.abs(host64(Kd) - Ko).max() <= 1e-9
         used += info["bb_used"]
     assert used >= 2
@@ -98,6 +101,8 @@ def test_barzilai_borwein_known_quotient(gpu, precision, c1, c2, want, used):
             info = spk.info_dict(dinfo)
         assert info["bb_used"] == used
         assert info["eta"] == pytest.approx(oinfo["eta"], rel=tol)
+        assert info["bb_quotient"] == pytest.approx(oinfo["bb_quotient"], rel=tol)
+        assert info["bb_quotient"] == pytest.approx(bb_expected(c1, c2), rel=tol)
         if used and 1.6 < want < 160.0:
             assert info["eta"] == pytest.approx(bb_expected(c1, c2), rel=tol)
         step = info["eta"] * np.abs(g).max()

@@ -617,11 +617,13 @@ def test_step_barzilai_borwein_known_quotient(c1, c2, want, used):
     K1, kp1, gp1, info = oracle.step(K, rho, 4, 16, 4, 0.5, a, b, 0, 50, kp, gp, 25, 3.0)
     assert info["bb_used"] == used
     assert info["eta"] == pytest.approx(want, rel=1e-14)
+    # the quotient before the clamp (or the fallback) is reported as is
+    assert info["bb_quotient"] == pytest.approx(bb_expected(c1, c2), rel=1e-14)
     assert np.array_equal(kp1, K) and np.array_equal(gp1, g)
     assert np.array_equal(K1, oracle.project(K - info["eta"] * g, 4, 16, 0.5, a, b, 0, 50))
     # below iteration 20 the same state takes the fixed step
     _, _, _, info = oracle.step(K, rho, 4, 16, 4, 0.5, a, b, 0, 50, kp, gp, 19, 3.0)
-    assert info["eta"] == 3.0 and not info["bb_used"]
+    assert info["eta"] == 3.0 and not info["bb_used"] and np.isnan(info["bb_quotient"])
 
 
 # --------------------------------------------------------------------------
