@@ -125,6 +125,15 @@ typedef struct {
                                    target then sums exactly over the 27 cells
                                    around it at its deepest level only
                                    (depth + R <= 7)                               */
+    void   *far_field_stream; /* hipStream_t, when depth > 0.  NULL: the far
+                                 field's exact near-field sums run on the call's
+                                 stream, after its translations.  Else a second
+                                 stream of the caller's (same device, default
+                                 priority, not the call's stream): the near-field
+                                 sums run there beside the translations, forked
+                                 from and joined back to the call's stream by
+                                 events, so the call stays ordered on its
+                                 stream.  The library creates no stream.      */
 } spk_params;
 
 /* Text of a status code (static storage). */

@@ -35,7 +35,7 @@ class SpkParams(ctypes.Structure):
                 ("te_index", _i32), ("half_width", _dbl), ("eps", _dbl), ("a_max", _dbl),
                 ("b_max", _dbl), ("n_pit", _i32), ("flags", _i32), ("attraction_field", _vp),
                 ("far_field_depth", _i32), ("far_field_order", _i32),
-                ("far_field_adaptive", _i32)]
+                ("far_field_adaptive", _i32), ("far_field_stream", _vp)]
 
 
 class SpkStepInfo(ctypes.Structure):
@@ -119,6 +119,7 @@ class Params:
     far_field_depth: int = 0                         # 0: exact repulsion; 2..7: octree depth
     far_field_order: int = 5                         # Chebyshev nodes per axis (3..6)
     far_field_adaptive: int = 0                      # refinement levels of dense cells (0..2)
+    far_field_overlap: bool = True                   # near-field sums on a second stream
     field_direct: bool = False                       # node field summed directly, not by FFT
     _c: SpkParams = field(default=None, repr=False, compare=False)
 
@@ -130,7 +131,9 @@ class Params:
     def dtype(self) -> torch.dtype:
         return torch.float64 if self.precision == "plain_fp64" else torch.float32
 
-    def c(self) -> SpkParams:
+    def c(self, device=None) -> SpkParams:
+        """The C struct; with a CUDA device and the far field on, it carries the
+        binding's second stream of that device for the far field's near-field sums."""
         f = self.attraction_field
         if f is not None and (not f.is_cuda or f.dtype != self.dtype or not f.is_contiguous()
                               or f.numel() != 4 * (self.grid + 2) ** 3):
@@ -145,7 +148,27 @@ class Params:
                          | (FLAG_FIELD_DIRECT if self.field_direct else 0),
                          _vp(f.data_ptr()) if f is not None else None,
                          self.far_field_depth, self.far_field_order if self.far_field_depth else 0,
-                         int(self.far_field_adaptive))
+                         int(self.far_field_adaptive),
+                         _far_field_stream(device)
+                         if self.far_field_depth and self.far_field_overlap else None)
+
+
+_SIDE_STREAMS: dict = {}
+
+
+def _far_field_stream(device):
+    """A second stream per device (default priority), created once by the
+    binding and passed to the library, which holds no stream of its own."""
+    if device is None:
+        return None
+    device = torch.device(device)
+    if device.type != "cuda":
+        return None
+    idx = device.index if device.index is not None else torch.cuda.current_device()
+    st = _SIDE_STREAMS.get(idx)
+    if st is None:
+        st = _SIDE_STREAMS[idx] = torch.cuda.Stream(device=idx)
+    return _vp(st.cuda_stream)
 
 
 def lipschitz_bound(p: int, eps: float, rho_mass: float = 1.0, kernel: str = "distance") -> float:
@@ -242,7 +265,7 @@ def energy(K: torch.Tensor, rho: torch.Tensor, prm: Params):
     _check_rho(rho, prm)
     ws = workspace(prm, K.device)
     out = (_dbl * 4)()
-    c = prm.c()
+    c = prm.c(K.device)
     _check(load_library().sparkling_energy(ctypes.byref(c), *_rows(K), _vp(rho.data_ptr()), out,
                                            _vp(ws.data_ptr()), ws.numel(), _stream(K)),
            "sparkling_energy")
@@ -270,7 +293,7 @@ def grad(K: torch.Tensor, rho: torch.Tensor, prm: Params, tgt=None, out: torch.T
         pr = torch.empty(nt, dtype=torch.float64, device=K.device)
     en = (_dbl * 3)() if with_energy else None
     ws = workspace(prm, K.device)
-    c = prm.c()
+    c = prm.c(K.device)
     _check(load_library().sparkling_grad(
         ctypes.byref(c), *_rows(K), _vp(rho.data_ptr()), *_rows(out), b, e,
         _vp(pa.data_ptr()) if pa is not None else None,
@@ -336,7 +359,7 @@ def step_(K: torch.Tensor, rho: torch.Tensor, prm: Params, state: StepState, it:
     info = SpkStepInfo()
     info.iter = it
     info.eta_fixed = eta_fixed
-    c = prm.c()
+    c = prm.c(K.device)
     rc = load_library().sparkling_step(ctypes.byref(c), *_rows(K), _vp(rho.data_ptr()),
                                        _vp(state.k_prev.data_ptr()), _vp(state.g_prev.data_ptr()),
                                        ctypes.byref(info), _vp(ws.data_ptr()), ws.numel(), _stream(K))
@@ -364,7 +387,7 @@ def step_async_(K: torch.Tensor, rho: torch.Tensor, prm: Params, state: StepStat
             or not info.is_contiguous()):
         raise ValueError("info must be a contiguous float64 device tensor of at least 10")
     ws = workspace(prm, K.device) if ws is None else ws
-    c = prm.c()
+    c = prm.c(K.device)
     _check(load_library().sparkling_step_async(
         ctypes.byref(c), *_rows(K), _vp(rho.data_ptr()), _vp(state.k_prev.data_ptr()),
         _vp(state.g_prev.data_ptr()), it, eta_fixed, _vp(info.data_ptr()), _vp(ws.data_ptr()),

@@ -458,6 +458,7 @@ int run_far_field(const spk_params *prm, const void *kx, const void *ky, const v
     f.acc = w.acc_r();
     f.ld = L.ld;
     f.near_tpb = near_targets_per_block(prm->precision);
+    f.side = static_cast<hipStream_t>(prm->far_field_stream);
     f.box_part = w.at<double>(L.fmm_box_part);
     f.box = w.at<double>(L.fmm_box);
     f.keys_in = w.at<uint32_t>(L.fmm_keys_in);

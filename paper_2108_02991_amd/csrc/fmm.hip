@@ -39,8 +39,6 @@
 #include <algorithm>
 #include <cfloat>
 #include <cmath>
-#include <mutex>
-#include <vector>
 
 #include <hipcub/hipcub.hpp>
 
@@ -1240,29 +1238,6 @@ Cheb make_cheb(int n)
 #define SPK_FMM_OVERLAP 1
 #endif
 
-// A second stream per device (default priority) for the near field, which
-// then runs beside the M2L: the two use the vector ALUs and the matrix cores.
-// The caller's stream forks to it after the upward pass (which then keeps the
-// whole chip) and joins it before the L2P adds the far field, so the pair
-// stays ordered on the caller's stream.
-hipError_t side_stream(hipStream_t *out)
-{
-    static std::mutex mu;
-    static std::vector<hipStream_t> streams;
-    int dev = 0;
-    hipError_t e;
-    if ((e = hipGetDevice(&dev)) != hipSuccess)
-        return e;
-    std::lock_guard<std::mutex> lock(mu);
-    if ((int)streams.size() <= dev)
-        streams.resize(dev + 1, nullptr);
-    if (!streams[dev] &&
-        (e = hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking)) != hipSuccess)
-        return e;
-    *out = streams[dev];
-    return hipSuccess;
-}
-
 template <int N, typename T>
 hipError_t run_typed(const FmmLaunch &f, hipStream_t s)
 {
@@ -1388,8 +1363,13 @@ hipError_t run_typed(const FmmLaunch &f, hipStream_t s)
     }
     plan.part = f.part;
     // near field (exact pair sums over the 27 cells around each target's cell
-    // at its final level), on the side stream beside the M2L, up to the L2P
-    hipStream_t ns = s;
+    // at its final level).  With the caller's second stream it runs there
+    // beside the M2L (the near field on the vector ALUs, the M2L on the matrix
+    // cores): the call's stream forks to it after the upward pass (which then
+    // keeps the whole chip) and joins it before the L2P adds the far field.
+    // Without one it runs on the call's stream.
+    const bool fork = SPK_FMM_OVERLAP && f.side != nullptr && f.side != s;
+    hipStream_t ns = fork ? f.side : s;
     struct Events {   // released on every path (a pending event may be destroyed)
         hipEvent_t fork = nullptr, join = nullptr;
         ~Events()
@@ -1400,9 +1380,8 @@ hipError_t run_typed(const FmmLaunch &f, hipStream_t s)
                 (void)hipEventDestroy(join);
         }
     } ev;
-    if (SPK_FMM_OVERLAP) {
-        if ((e = side_stream(&ns)) != hipSuccess ||
-            (e = hipEventCreateWithFlags(&ev.fork, hipEventDisableTiming)) != hipSuccess ||
+    if (fork) {
+        if ((e = hipEventCreateWithFlags(&ev.fork, hipEventDisableTiming)) != hipSuccess ||
             (e = hipEventCreateWithFlags(&ev.join, hipEventDisableTiming)) != hipSuccess ||
             (e = hipEventRecord(ev.fork, s)) != hipSuccess ||
             (e = hipStreamWaitEvent(ns, ev.fork, 0)) != hipSuccess)
@@ -1433,7 +1412,7 @@ hipError_t run_typed(const FmmLaunch &f, hipStream_t s)
         if ((e = launch_near(nl, ns)) != hipSuccess)
             return e;
     }
-    if (SPK_FMM_OVERLAP) {
+    if (fork) {
         if ((e = hipEventRecord(ev.join, ns)) != hipSuccess)
             return e;
     }
@@ -1452,7 +1431,7 @@ hipError_t run_typed(const FmmLaunch &f, hipStream_t s)
     if ((e = hipGetLastError()) != hipSuccess)
         return e;
     // the near field's sums are in acc before the far field is added
-    if (SPK_FMM_OVERLAP) {
+    if (fork) {
         if ((e = hipStreamWaitEvent(s, ev.join, 0)) != hipSuccess)
             return e;
     }

@@ -34,6 +34,7 @@ struct FmmLaunch {
     double *acc = nullptr;
     int64_t ld = 0;
     int near_tpb = 0;                     // targets per near-field block
+    hipStream_t side = nullptr;           // caller's second stream for the near field, or null
     // workspace
     double *box_part = nullptr;           // [kFmmBoxBlocks][6]
     double *box = nullptr;                // centre[3], half-width

@@ -54,6 +54,24 @@ def test_rerun_and_chunks_bitwise(gpu):
     assert torch.equal(torch.cat(parts, dim=1), full)
 
 
+def test_side_stream_or_none_same_bits(gpu):
+    """The near-field sums on the caller's second stream (beside the M2L) or on
+    the call's own stream give the same bits, uniform and adaptive trees."""
+    K = inputs.radial_spokes(64, 500, 0.5, seed=44, jitter=0.05)
+    rho = inputs.radial_density(8, 0.5, 0.0625, 2.0)
+    for R in (0, 2):
+        got = []
+        for overlap in (True, False):
+            prm = spk.Params(64, 500, 8, precision="fp32_comp", far_field_depth=3,
+                             far_field_order=5, far_field_adaptive=R, far_field_overlap=overlap)
+            Kd, rd = device_problem(K, rho, "fp32_comp", gpu)
+            g, (pa, pr), en = spk.grad(Kd, rd, prm, potentials=True, with_energy=True)
+            torch.cuda.synchronize()
+            got.append((g, pr, en))
+        assert torch.equal(got[0][0], got[1][0]) and torch.equal(got[0][1], got[1][1])
+        assert got[0][2] == got[1][2]
+
+
 def test_coincident_and_outside_the_box(gpu):
     # every sample at one point: all pairs are near, the far field is empty
     K = np.full((3, 700), 0.125)
