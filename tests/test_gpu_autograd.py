@@ -1,9 +1,20 @@
 """F as a torch.autograd.Function: backward is the gradient kernel, recomputed in chunks."""
+import json
+import os
+
 import numpy as np
 import pytest
 import torch
 
 from gpu_util import configs, device_problem, host64, inputs, oracle, rel_l2, say, spk
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def c4_fd_golden():
+    with open(os.path.join(GOLDEN, "c4_fd.json")) as f:
+        meta = json.load(f)
+    return meta, np.load(os.path.join(GOLDEN, "c4_fd.npy"))
 
 pytestmark = pytest.mark.gpu
 
@@ -63,7 +74,8 @@ def test_double_backward_unsupported(gpu):
 
 def test_c4_autograd_fp32(gpu):
     """p = 65,536 in FP32, chunks of 8192: forward vs oracle energy, backward vs the
-    oracle gradient, and 200 central finite differences of the FP64 oracle (h = 1e-4)."""
+    oracle gradient, and 200 central finite differences of the FP64 oracle along
+    dense Rademacher directions (h = 1e-4), error_k = |FD_k - <g, e_k>| / ||grad F||."""
     w = configs.C4
     K, rho = w.trajectory(), w.density()
     prm = spk.Params(w.n_shots, w.n_samples, w.grid, precision="fp32_comp")
@@ -85,25 +97,18 @@ def test_c4_autograd_fp32(gpu):
     say(f"  c4 backward rel L2 vs oracle = {err:.3e}")
     assert err <= 1e-5
 
-    h = 1e-4
-    rng = np.random.default_rng(2024)
+    # 200 dense Rademacher directions (h = 1e-4 per coordinate): the FP64
+    # oracle's central differences, stored by tests/golden/make_c4_fd.py
+    meta, fd = c4_fd_golden()
+    assert meta["K_digest"] == inputs.digest(K64) and meta["rho_digest"] == inputs.digest(r64)
+    scale = meta["grad_norm"]
     errs_gpu, errs_orc = [], []
-    n_dense = 2
-    for k in range(200):
-        e = inputs.rademacher(K.shape, 1000 + k)
-        if k >= n_dense:
-            mask = np.zeros(prm.p, dtype=bool)
-            mask[rng.choice(prm.p, 64, replace=False)] = True
-            e[:, ~mask] = 0.0
-            sup = mask
-        else:
-            sup = np.ones(prm.p, dtype=bool)
-        fd = oracle.fd_directional(K64, r64, w.grid, 0.5, e, h)
-        scale = np.linalg.norm(og[:, sup])
-        errs_gpu.append(abs(fd - float((g * e).sum())) / scale)
-        errs_orc.append(abs(fd - float((og * e).sum())) / scale)
+    for k in range(meta["directions"]):
+        e = inputs.rademacher(K.shape, meta["seed0"] + k)
+        errs_gpu.append(abs(fd[k, 0] - float((g * e).sum())) / scale)
+        errs_orc.append(abs(fd[k, 0] - float((og * e).sum())) / scale)
     errs_gpu, errs_orc = np.array(errs_gpu), np.array(errs_orc)
-    say(f"  c4 FD: max err GPU {errs_gpu.max():.3e}  oracle floor {errs_orc.max():.3e} "
-        f"median GPU {np.median(errs_gpu):.3e}")
+    say(f"  c4 FD ({meta['directions']} dense directions): max err GPU {errs_gpu.max():.3e}  "
+        f"oracle floor {errs_orc.max():.3e}  median GPU {np.median(errs_gpu):.3e}")
     assert errs_orc.max() <= 1e-4          # FD of the FP64 oracle agrees with its gradient
     assert errs_gpu.max() <= errs_orc.max() + 2e-5
