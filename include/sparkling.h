@@ -329,6 +329,28 @@ int sparkling_step_async(const spk_params *prm, void *kx, void *ky, void *kz, co
                          double *info_dev, void *ws, size_t ws_bytes, void *stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the step of
+ * sparkling_step_async, same kernels, same bits, with no workspace argument.
+ * Its workspace is a static device array of SPK_SCRATCH_BYTES held by the
+ * library on every device it runs on until the process ends; the call makes
+ * no allocation of any kind (no hipMalloc, no event, no stream) and its
+ * launches are not timed.  Every call on one device shares that device's
+ * array: calls that overlap on one device (several streams or threads) race
+ * and must be serialised by the caller.  No byte of the array needs to start
+ * at any value: every call writes what it reads.
+ * Errors: SPK_EWORKSPACE if spk_workspace_size(prm) exceeds SPK_SCRATCH_BYTES
+ * (on a 32^3 density: p up to about 300,000 samples), SPK_EUNSUPPORTED for
+ * far_field_depth > 0, otherwise as sparkling_step_async.
+ */
+#define SPK_SCRATCH_BYTES ((size_t)64 << 20)
+int sparkling_step_async_noalloc(const spk_params *prm, void *kx, void *ky, void *kz,
+                                 const void *rho, void *k_prev, void *g_prev, int64_t iter,
+                                 double eta_fixed, double *info_dev, void *stream);
+/* SPK_SCRATCH_BYTES, as built into the library. */
+size_t spk_noalloc_scratch_bytes(void);
+
+/*
  * Kernel timing.  While enabled, every kernel launch of the kinds below is
  * bracketed by HIP events on the stream it runs on; spk_timing_query()
  * waits for those events and returns, for one kind, the summed duration in

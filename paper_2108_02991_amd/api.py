@@ -80,6 +80,9 @@ def load_library(path: Path | str | None = None):
         "sparkling_step_async": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _dbl, _vp, _vp, _sz,
                                   _vp], ctypes.c_int),
         "sparkling_upsample": ([_vp] * 8, ctypes.c_int),
+        "sparkling_step_async_noalloc": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _dbl, _vp,
+                                          _vp], ctypes.c_int),
+        "spk_noalloc_scratch_bytes": ([], _sz),
         "spk_timing_enable": ([ctypes.c_int], ctypes.c_int),
         "spk_timing_query": ([ctypes.c_int, _vp, _vp, _vp], ctypes.c_int),
         "spk_timing_reset": ([], ctypes.c_int),
@@ -392,6 +395,29 @@ def step_async_(K: torch.Tensor, rho: torch.Tensor, prm: Params, state: StepStat
         ctypes.byref(c), *_rows(K), _vp(rho.data_ptr()), _vp(state.k_prev.data_ptr()),
         _vp(state.g_prev.data_ptr()), it, eta_fixed, _vp(info.data_ptr()), _vp(ws.data_ptr()),
         ws.numel(), _stream(K)), "sparkling_step_async")
+
+
+def step_async_noalloc_(K: torch.Tensor, rho: torch.Tensor, prm: Params, state: StepState,
+                        it: int, eta_fixed: float, info: torch.Tensor):
+    """step_async_ without a workspace: the library's static device scratch
+    (spk_noalloc_scratch_bytes()) serves instead; nothing is allocated.  Calls
+    that overlap on one device race on that scratch."""
+    _check_k(K, prm)
+    _check_rho(rho, prm)
+    _check_k(state.k_prev, prm, "k_prev")
+    _check_k(state.g_prev, prm, "g_prev")
+    if (not info.is_cuda or info.dtype != torch.float64 or info.numel() < 10
+            or not info.is_contiguous()):
+        raise ValueError("info must be a contiguous float64 device tensor of at least 10")
+    c = prm.c()
+    _check(load_library().sparkling_step_async_noalloc(
+        ctypes.byref(c), *_rows(K), _vp(rho.data_ptr()), _vp(state.k_prev.data_ptr()),
+        _vp(state.g_prev.data_ptr()), it, eta_fixed, _vp(info.data_ptr()), _stream(K)),
+        "sparkling_step_async_noalloc")
+
+
+def noalloc_scratch_bytes() -> int:
+    return int(load_library().spk_noalloc_scratch_bytes())
 
 
 def info_dict(info: torch.Tensor) -> dict:

@@ -56,6 +56,9 @@ struct TimedLaunch {
 
 std::mutex g_tmu;
 bool g_timing = false;
+// Set for the duration of an allocation-free call: its launches are not timed
+// (timing creates events).
+thread_local bool t_untimed = false;
 std::vector<TimedLaunch> g_pending;
 constexpr int kKinds = 5;
 double g_ms[kKinds] = {};
@@ -68,7 +71,7 @@ class Timed {
     Timed(int kind, double pairs, hipStream_t s) : kind_(kind), pairs_(pairs), s_(s)
     {
         std::lock_guard<std::mutex> lk(g_tmu);
-        if (!g_timing)
+        if (!g_timing || t_untimed)
             return;
         hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
         if (hipStreamIsCapturing(s_, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone)
@@ -1004,6 +1007,91 @@ int sparkling_step_async(const spk_params *prm, void *kx, void *ky, void *kz, co
                                  w, s)))
         return rc;
     return enqueue_step_back(prm, kx, ky, kz, k_prev, g_prev, info_dev, w, s);
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------------
+// The allocation-free step: sparkling_step_async with its workspace in a
+// static device array instead of a caller's buffer.
+// ------------------------------------------------------------------------
+namespace {
+
+constexpr size_t kScratchBytes = SPK_SCRATCH_BYTES;
+constexpr int kMaxScratchDevices = 64;
+
+// One copy per device, held by the code object until the process ends.  In
+// host code this name is a host-side stand-in, never a device address: host
+// code uses the per-device address from hipGetSymbolAddress only.
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+std::mutex g_scratch_mu;
+void *g_scratch_addr[kMaxScratchDevices] = {};
+
+// Device address of `scratch` on the current device, looked up once per
+// device (with that device current) and kept.
+int scratch_address(void **out)
+{
+    int dev = 0;
+    SPK_HIP(hipGetDevice(&dev), "current device");
+    if (dev < 0 || dev >= kMaxScratchDevices)
+        return fail(SPK_EDEVICE, "device %d beyond the %d the static scratch tracks", dev,
+                    kMaxScratchDevices);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_addr[dev]) {
+        void *ptr = nullptr;
+        SPK_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "static scratch address");
+        if (!ptr)
+            return fail(SPK_EDEVICE, "static scratch address is NULL on device %d", dev);
+        g_scratch_addr[dev] = ptr;
+    }
+    *out = g_scratch_addr[dev];
+    return SPK_OK;
+}
+
+struct Untimed {
+    bool prev;
+    Untimed() : prev(t_untimed) { t_untimed = true; }
+    ~Untimed() { t_untimed = prev; }
+};
+
+}  // namespace
+
+extern "C" {
+
+size_t spk_noalloc_scratch_bytes(void) { return kScratchBytes; }
+
+int sparkling_step_async_noalloc(const spk_params *prm, void *kx, void *ky, void *kz,
+                                 const void *rho, void *k_prev, void *g_prev, int64_t iter,
+                                 double eta_fixed, double *info_dev, void *stream)
+{
+    g_err.clear();
+    int rc = check_params(prm, true);
+    if (rc)
+        return rc;
+    // the arguments are checked before the scratch is looked up (no HIP call
+    // for a rejected call), then again, identically, by the step itself
+    const size_t al = elt_size(prm->precision);
+    if ((rc = check_k(prm, kx, ky, kz)) || (rc = check_ptr(rho, "rho", al)) ||
+        (rc = check_ptr(k_prev, "k_prev", al)) || (rc = check_ptr(g_prev, "g_prev", al)) ||
+        (rc = check_ptr(info_dev, "info_dev", 8)))
+        return rc;
+    if (iter < 0 || !(eta_fixed > 0.0) || !std::isfinite(eta_fixed))
+        return fail(SPK_EINVAL, "iter must be >= 0 and eta_fixed finite and > 0");
+    if (prm->far_field_depth)
+        return fail(SPK_EUNSUPPORTED, "the allocation-free step sums the repulsion exactly "
+                                      "(far_field_depth must be 0)");
+    const size_t need = make_layout(prm).total;
+    if (need > kScratchBytes)
+        return fail(SPK_EWORKSPACE, "the allocation-free step needs %zu bytes of scratch; its "
+                                    "static scratch holds %zu",
+                    need, kScratchBytes);
+    void *ws = nullptr;
+    if ((rc = scratch_address(&ws)))
+        return rc;
+    Untimed untimed;
+    return sparkling_step_async(prm, kx, ky, kz, rho, k_prev, g_prev, iter, eta_fixed, info_dev,
+                                ws, kScratchBytes, stream);
 }
 
 int sparkling_upsample(const spk_params *prm, const void *kx, const void *ky, const void *kz,

@@ -270,6 +270,32 @@ def test_energy_project_step_validation(lib):
                               v(FAKE), ctypes.byref(info), v(FAKE), n, None) == EINVAL
 
 
+def test_noalloc_step_validation(lib):
+    """The allocation-free step rejects bad arguments, problems whose workspace
+    exceeds its static scratch and the far field before any HIP call."""
+    v = ctypes.c_void_p
+    assert lib.spk_noalloc_scratch_bytes() == 64 << 20
+
+    def call(prm, ptrs=None, it=0, eta=1.0):
+        c = prm.c()
+        a = ptrs or [FAKE] * 7
+        return lib.sparkling_step_async_noalloc(ctypes.byref(c), *map(v, a[:6]), it, eta,
+                                                v(a[6]), None)
+    prm = good_params()
+    assert spk.workspace_size(prm) <= 64 << 20
+    assert call(prm, eta=0.0) == EINVAL
+    assert call(prm, it=-1) == EINVAL
+    for k in range(7):
+        bad = [FAKE] * 7
+        bad[k] = 0
+        assert call(prm, bad) == EINVAL, k
+    big = good_params(n_shots=1024, n_samples=512, grid=128)
+    assert spk.workspace_size(big) > 64 << 20
+    assert call(big) == EWORKSPACE
+    assert "static scratch" in lib.spk_last_error().decode()
+    assert call(good_params(far_field_depth=3, far_field_order=4)) == EUNSUPPORTED
+
+
 def test_timing_query_rejects_unknown_kind(lib):
     assert lib.spk_timing_query(9, None, None, None) == EINVAL
 
