@@ -134,6 +134,17 @@ typedef struct {
                                  from and joined back to the call's stream by
                                  events, so the call stays ordered on its
                                  stream.  The library creates no stream.      */
+    void   *proj_duals;   /* NULL: every projection (sparkling_project, the
+                             steps) starts its dual variables at 0, the cold
+                             start.  Else device doubles [n_shots][6][n_samples],
+                             caller-owned, in/out: per coordinate c, the speed
+                             duals q at [c][n] (n < N_s-1) then the slew duals r
+                             at [3+c][n] (n < N_s-2), other entries 0.  The
+                             projection starts from them and leaves its last
+                             dual iterate there (warm start across the steps;
+                             the converged projection is the same).  Zero it
+                             before the first call.  8-byte aligned; must not
+                             alias any other argument.                      */
 } spk_params;
 
 /* Text of a status code (static storage). */

@@ -70,11 +70,11 @@ def _load():
             "orc_rho_self_energy": [_i64, _dbl, _p, _dbl, _int, _p],
             "orc_alpha_beta": [_dbl] * 8 + [_p, _p],
             "orc_project": [_i64, _i64, _p, _p, _p, _dbl, _dbl, _dbl, _i64, ctypes.c_int,
-                            ctypes.c_int],
+                            ctypes.c_int, _p],
             "orc_constraint_check": [_i64, _i64, _p, _p, _p, _dbl, _dbl, _dbl, _i64, ctypes.c_int,
                                      _p],
             "orc_step": [_i64, _i64, _p, _i64, _dbl, _p, _dbl, _int, _dbl, _dbl, _i64, _int, _int,
-                         _p, _p, _i64, _dbl, _p],
+                         _p, _p, _i64, _dbl, _p, _p],
             "orc_fd_directional": [_i64, _p, _p, _p, _i64, _dbl, _p, _dbl, _int, _p, _dbl, _p],
             "orc_num_threads": [],
             "orc_upsample": [_i64, _i64, _p, _p],
@@ -163,12 +163,26 @@ def alpha_beta(gmax, smax, raster_dt, dwell_dt, fov, kmax, gamma_bar, half_width
     return float(a[0]), float(b[0])
 
 
+def _duals_ptr(duals, n_shots, n_samples):
+    """The warm-start dual state: None (cold start) or a C-contiguous float64
+    array of n_shots * 6 * n_samples, updated in place."""
+    if duals is None:
+        return None
+    if (not isinstance(duals, np.ndarray) or duals.dtype != np.float64
+            or not duals.flags.c_contiguous or duals.size != n_shots * 6 * n_samples):
+        raise ValueError("duals must be a C-contiguous float64 array of n_shots*6*n_samples")
+    return _ptr(duals)
+
+
 def project(K, n_shots: int, n_samples: int, L: float, a: float, b: float, te: int,
-            n_pit: int, rotation_variant: bool = False) -> np.ndarray:
-    """Per-shot projection of K (3, Nc*Ns); returns a new float64 array."""
+            n_pit: int, rotation_variant: bool = False, duals=None) -> np.ndarray:
+    """Per-shot projection of K (3, Nc*Ns); returns a new float64 array.  With
+    duals (shape (Nc, 6, Ns): q then r per coordinate) the dual iteration starts
+    from them and leaves its last iterate there."""
     K = _f64(K).copy()
     rc = _load().orc_project(n_shots, n_samples, _ptr(K[0]), _ptr(K[1]), _ptr(K[2]),
-                             L, a, b, te, n_pit, int(rotation_variant))
+                             L, a, b, te, n_pit, int(rotation_variant),
+                             _duals_ptr(duals, n_shots, n_samples))
     _check(rc, "project")
     return K
 
@@ -185,8 +199,10 @@ def constraint_check(K, n_shots: int, n_samples: int, L: float, a: float, b: flo
 
 
 def step(K, rho, n_shots, n_samples, G, L, a, b, te, n_pit, k_prev, g_prev, it, eta_fixed,
-         eps: float = 0.0, rotation_variant: bool = False, kernel: str = "distance"):
-    """One projected gradient step.  Returns (K_new, k_prev, g_prev, info dict)."""
+         eps: float = 0.0, rotation_variant: bool = False, kernel: str = "distance",
+         duals=None):
+    """One projected gradient step.  Returns (K_new, k_prev, g_prev, info dict).
+    duals: the projection's warm-start state (see project), updated in place."""
     K = _f64(K).copy()
     k_prev = _f64(k_prev).copy()
     g_prev = _f64(g_prev).copy()
@@ -194,7 +210,7 @@ def step(K, rho, n_shots, n_samples, G, L, a, b, te, n_pit, k_prev, g_prev, it, 
     info = np.empty(10)
     rc = _load().orc_step(n_shots, n_samples, _ptr(K), G, L, _ptr(rho), eps, _kern(kernel), a, b,
                           te, n_pit, int(rotation_variant), _ptr(k_prev), _ptr(g_prev), it, eta_fixed,
-                          _ptr(info))
+                          _ptr(info), _duals_ptr(duals, n_shots, n_samples))
     _check(rc, "step")
     d = {"eta": info[0], "F": info[1], "Fa": info[2], "Fr": info[3],
          "viol": info[4:8].copy(), "bb_used": bool(info[8]), "bb_quotient": info[9]}

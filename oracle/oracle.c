@@ -354,8 +354,12 @@ static void shrink_each(double z[3], double thr)
     }
 }
 
+/* duals: NULL (every dual variable starts at 0), or this shot's 6*Ns doubles,
+ * q then r, [c * Ns + n] each (q for n < Ns-1, r for n < Ns-2, the rest 0):
+ * the iteration starts from them (warm start) and leaves its last dual
+ * iterate there. */
 static void project_shot(int64_t Ns, double *xyz[3], double L, double a, double b,
-                         int64_t te, int n_pit, int rv, double *buf)
+                         int64_t te, int n_pit, int rv, double *buf, double *duals)
 {
     /* buf holds k[3][Ns], s[3][Ns], q,qh,qn[3][Ns], r,rh,rn[3][Ns] */
     double *k = buf, *s = k + 3 * Ns;
@@ -367,8 +371,13 @@ static void project_shot(int64_t Ns, double *xyz[3], double L, double a, double 
     for (int c = 0; c < 3; ++c)
         for (int64_t m = 0; m < Ns; ++m) {
             k[c * Ns + m] = xyz[c][m];
-            q[c * Ns + m] = qh[c * Ns + m] = 0.0;
-            r[c * Ns + m] = rh[c * Ns + m] = 0.0;
+            double q0 = 0.0, r0 = 0.0;
+            if (duals) {
+                q0 = (m + 1 < Ns) ? duals[c * Ns + m] : 0.0;
+                r0 = (m + 2 < Ns) ? duals[(3 + c) * Ns + m] : 0.0;
+            }
+            q[c * Ns + m] = qh[c * Ns + m] = q0;
+            r[c * Ns + m] = rh[c * Ns + m] = r0;
         }
     double t = 1.0;
     for (int it = 0; it < n_pit; ++it) {
@@ -426,12 +435,20 @@ static void project_shot(int64_t Ns, double *xyz[3], double L, double a, double 
     if (te >= 0)
         for (int c = 0; c < 3; ++c)
             xyz[c][te] = 0.0;
+    if (duals)
+        for (int c = 0; c < 3; ++c)
+            for (int64_t m = 0; m < Ns; ++m) {
+                duals[c * Ns + m] = (m + 1 < Ns) ? q[c * Ns + m] : 0.0;
+                duals[(3 + c) * Ns + m] = (m + 2 < Ns) ? r[c * Ns + m] : 0.0;
+            }
 }
 
 /* Project every shot of K (3 arrays of Nc*Ns, shot-lexicographic) in place.
- * rv = 0: rotation-invariant bounds on |.|_2 per sample; rv = 1: per-axis bounds. */
+ * rv = 0: rotation-invariant bounds on |.|_2 per sample; rv = 1: per-axis bounds.
+ * duals: NULL (cold start), or Nc * 6 * Ns doubles, shot c's at c * 6 * Ns
+ * (warm start in, last dual iterate out; see project_shot). */
 int orc_project(int64_t Nc, int64_t Ns, double *kx, double *ky, double *kz,
-                double L, double a, double b, int64_t te, int n_pit, int rv)
+                double L, double a, double b, int64_t te, int n_pit, int rv, double *duals)
 {
     if (Nc < 1 || Ns < 2 || !kx || !ky || !kz || !(L > 0) || !(a > 0) || !(b > 0) ||
         te < -1 || te >= Ns || n_pit < 0)
@@ -447,7 +464,8 @@ int orc_project(int64_t Nc, int64_t Ns, double *kx, double *ky, double *kz,
 #pragma omp for schedule(dynamic, 1)
             for (int64_t c = 0; c < Nc; ++c) {
                 double *xyz[3] = {kx + c * Ns, ky + c * Ns, kz + c * Ns};
-                project_shot(Ns, xyz, L, a, b, te, n_pit, rv, buf);
+                project_shot(Ns, xyz, L, a, b, te, n_pit, rv, buf,
+                             duals ? duals + c * 6 * Ns : NULL);
             }
             free(buf);
         }
@@ -526,7 +544,7 @@ int orc_constraint_check(int64_t Nc, int64_t Ns, const double *kx, const double 
 int orc_step(int64_t Nc, int64_t Ns, double *K, int64_t G, double L, const double *rho,
              double eps, int kern, double a, double b, int64_t te, int n_pit, int rv,
              double *k_prev, double *g_prev, int64_t iter, double eta_fixed,
-             double info_out[10])
+             double info_out[10], double *duals)
 {
     int64_t p = Nc * Ns;
     if (Nc < 1 || Ns < 2 || !K || !rho || !k_prev || !g_prev || !info_out || !(eta_fixed > 0) ||
@@ -577,7 +595,7 @@ int orc_step(int64_t Nc, int64_t Ns, double *K, int64_t G, double L, const doubl
         K[e] = K[e] - eta * g[e];
     }
     double viol[4];
-    rc = orc_project(Nc, Ns, K, K + p, K + 2 * p, L, a, b, te, n_pit, rv);
+    rc = orc_project(Nc, Ns, K, K + p, K + 2 * p, L, a, b, te, n_pit, rv, duals);
     if (!rc)
         rc = orc_constraint_check(Nc, Ns, K, K + p, K + 2 * p, L, a, b, te, rv, viol);
     info_out[0] = eta;

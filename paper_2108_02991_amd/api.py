@@ -35,7 +35,7 @@ class SpkParams(ctypes.Structure):
                 ("te_index", _i32), ("half_width", _dbl), ("eps", _dbl), ("a_max", _dbl),
                 ("b_max", _dbl), ("n_pit", _i32), ("flags", _i32), ("attraction_field", _vp),
                 ("far_field_depth", _i32), ("far_field_order", _i32),
-                ("far_field_adaptive", _i32), ("far_field_stream", _vp)]
+                ("far_field_adaptive", _i32), ("far_field_stream", _vp), ("proj_duals", _vp)]
 
 
 class SpkStepInfo(ctypes.Structure):
@@ -123,6 +123,7 @@ class Params:
     far_field_order: int = 5                         # Chebyshev nodes per axis (3..6)
     far_field_adaptive: int = 0                      # refinement levels of dense cells (0..2)
     far_field_overlap: bool = True                   # near-field sums on a second stream
+    proj_duals: "torch.Tensor | None" = None         # warm-start duals (new_duals()); None = cold
     field_direct: bool = False                       # node field summed directly, not by FFT
     _c: SpkParams = field(default=None, repr=False, compare=False)
 
@@ -142,6 +143,11 @@ class Params:
                               or f.numel() != 4 * (self.grid + 2) ** 3):
             raise ValueError("attraction_field must be a contiguous device tensor of "
                              f"4*(G+2)^3 {self.dtype} values")
+        d = self.proj_duals
+        if d is not None and (not d.is_cuda or d.dtype != torch.float64 or not d.is_contiguous()
+                              or d.numel() != 6 * self.p):
+            raise ValueError("proj_duals must be a contiguous float64 device tensor of "
+                             "n_shots*6*n_samples values")
         return SpkParams(self.n_shots, self.n_samples, self.grid, PRECISIONS[self.precision],
                          self.te_index, self.half_width, self.eps, self.a_max, self.b_max,
                          self.n_pit,
@@ -153,7 +159,8 @@ class Params:
                          self.far_field_depth, self.far_field_order if self.far_field_depth else 0,
                          int(self.far_field_adaptive),
                          _far_field_stream(device)
-                         if self.far_field_depth and self.far_field_overlap else None)
+                         if self.far_field_depth and self.far_field_overlap else None,
+                         _vp(d.data_ptr()) if d is not None else None)
 
 
 _SIDE_STREAMS: dict = {}
@@ -341,6 +348,11 @@ def upsample(K: torch.Tensor, prm: Params) -> torch.Tensor:
     _check(load_library().sparkling_upsample(ctypes.byref(c), *_rows(K), *_rows(out), _stream(K)),
            "sparkling_upsample")
     return out
+
+
+def new_duals(prm: Params, device) -> torch.Tensor:
+    """Zeroed warm-start dual state for prm.proj_duals: (n_shots, 6, n_samples) doubles."""
+    return torch.zeros((prm.n_shots, 6, prm.n_samples), dtype=torch.float64, device=device)
 
 
 class StepState:

@@ -182,6 +182,8 @@ int check_params(const spk_params *prm, bool need_projection)
             return fail(SPK_EINVAL, "a_max and b_max must be finite and > 0");
         if (prm->n_pit < 0)
             return fail(SPK_EINVAL, "n_pit must be >= 0");
+        if (reinterpret_cast<uintptr_t>(prm->proj_duals) % 8)
+            return fail(SPK_EINVAL, "proj_duals is not 8-byte aligned");
     }
     return SPK_OK;
 }
@@ -572,7 +574,8 @@ int project_in_place(const spk_params *prm, void *kx, void *ky, void *kz, hipStr
     Timed tm(SPK_KIND_PROJECTION, 0.0, s);
     SPK_HIP(launch_project(prm->precision, kx, ky, kz, prm->n_shots, prm->n_samples,
                            prm->half_width, prm->a_max, prm->b_max, prm->te_index, prm->n_pit,
-                           (prm->flags & SPK_FLAG_ROTATION_VARIANT) != 0, gate, s),
+                           (prm->flags & SPK_FLAG_ROTATION_VARIANT) != 0, gate,
+                           static_cast<double *>(prm->proj_duals), s),
             "projection");
     return SPK_OK;
 }

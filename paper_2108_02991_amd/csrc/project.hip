@@ -16,7 +16,11 @@
 //   s  = P0(k - D1^T qh - D2^T rh)       P0: clamp to [-L, L], then s[te] = 0
 //   q+ = shrink(qh + tau D1 s, tau a),  r+ = shrink(rh + tau D2 s, tau b)
 //   t+ = (1 + sqrt(1 + 4 t^2)) / 2,     qh = q+ + ((t - 1)/t+)(q+ - q), same for r
-// and the output is P0(k - D1^T q - D2^T r) of the last dual iterate.  With
+// and the output is P0(k - D1^T q - D2^T r) of the last dual iterate.  The
+// duals start at 0 (cold start), or from a caller's dual state, which then
+// receives the last dual iterate (warm start across successive projections:
+// the solution is the same, only the starting point of the iteration moves).
+// With
 // (D1 s)[n] = s[n+1] - s[n], (D2 s)[n] = s[n+2] - 2 s[n+1] + s[n] and
 // shrink(z, th) = z * max(0, 1 - th/|z|) per sample (group soft threshold of
 // the 3-vector), or per coordinate for per-axis bounds, where the dual prox
@@ -50,7 +54,8 @@ __device__ inline double shrink_one(double z, double thr)
 template <typename T, int NPT>
 __global__ __launch_bounds__(512) void project_kernel(T *kx, T *ky, T *kz, int64_t Ns, double L,
                                                      double a, double b, int64_t te, int n_pit,
-                                                     int per_axis, const double *gate)
+                                                     int per_axis, const double *gate,
+                                                     double *duals)
 {
 #pragma clang fp contract(off)
     static_assert(NPT >= 2, "two-sample halo needs NPT >= 2");
@@ -73,12 +78,19 @@ __global__ __launch_bounds__(512) void project_kernel(T *kx, T *ky, T *kz, int64
 
     // k is re-read from memory when needed (exact widening, same value every
     // time); only the dual state lives in registers.
+    // duals of this shot: q (speed, n < Ns-1) then r (slew, n < Ns-2), [c * Ns + n]
+    double *D = duals ? duals + (int64_t)blockIdx.x * 6 * Ns : nullptr;
     double q[3][NPT], qh[3][NPT], r[3][NPT], rh[3][NPT];
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
-        for (int i = 0; i < NPT; ++i)
-            q[c][i] = qh[c][i] = r[c][i] = rh[c][i] = 0.0;
+        for (int i = 0; i < NPT; ++i) {
+            const int64_t m = m0 + i;
+            const double q0 = (D && m <= Ns - 2) ? D[c * Ns + m] : 0.0;
+            const double r0 = (D && m <= Ns - 3) ? D[(3 + c) * Ns + m] : 0.0;
+            q[c][i] = qh[c][i] = q0;
+            r[c][i] = rh[c][i] = r0;
+        }
     auto kval = [&](int c, int i) -> double {
         const int64_t m = m0 + i;
         return m < Ns ? (double)K[c][m] : 0.0;
@@ -191,8 +203,13 @@ __global__ __launch_bounds__(512) void project_kernel(T *kx, T *ky, T *kz, int64
 #pragma unroll
         for (int i = 0; i < NPT; ++i) {
             const int64_t m = m0 + i;
-            if (m < Ns)
+            if (m < Ns) {
                 K[c][m] = (T)s[c][i];
+                if (D) {
+                    D[c * Ns + m] = m <= Ns - 2 ? q[c][i] : 0.0;
+                    D[(3 + c) * Ns + m] = m <= Ns - 3 ? r[c][i] : 0.0;
+                }
+            }
         }
 }
 
@@ -285,46 +302,46 @@ __global__ __launch_bounds__(CB) void check_final_kernel(const double *per_shot,
 template <typename T, int NPT>
 hipError_t launch_project_npt(T *kx, T *ky, T *kz, int64_t n_shots, int64_t Ns, double L,
                               double a, double b, int64_t te, int n_pit, int per_axis,
-                              const double *gate, hipStream_t s)
+                              const double *gate, double *duals, hipStream_t s)
 {
     int64_t nth = (Ns + NPT - 1) / NPT;
     nth = (nth + 63) / 64 * 64;
     const size_t lds = sizeof(double) * 15 * (size_t)nth;
     hipLaunchKernelGGL((project_kernel<T, NPT>), dim3((unsigned)n_shots), dim3((unsigned)nth), lds,
-                       s, kx, ky, kz, Ns, L, a, b, te, n_pit, per_axis, gate);
+                       s, kx, ky, kz, Ns, L, a, b, te, n_pit, per_axis, gate, duals);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_project_t(T *kx, T *ky, T *kz, int64_t n_shots, int64_t Ns, double L, double a,
                             double b, int64_t te, int n_pit, int per_axis, const double *gate,
-                            hipStream_t s)
+                            double *duals, hipStream_t s)
 {
     // at most 512 threads per shot: the halo buffers (15 doubles per thread)
     // stay under 64 KB of LDS
     if (Ns <= 2 * 512)
         return launch_project_npt<T, 2>(kx, ky, kz, n_shots, Ns, L, a, b, te, n_pit,
-                                            per_axis, gate, s);
+                                            per_axis, gate, duals, s);
     if (Ns <= 4 * 512)
         return launch_project_npt<T, 4>(kx, ky, kz, n_shots, Ns, L, a, b, te, n_pit,
-                                            per_axis, gate, s);
+                                            per_axis, gate, duals, s);
     return launch_project_npt<T, 8>(kx, ky, kz, n_shots, Ns, L, a, b, te, n_pit,
-                                            per_axis, gate, s);
+                                            per_axis, gate, duals, s);
 }
 
 }  // namespace
 
 hipError_t launch_project(int precision, void *kx, void *ky, void *kz, int64_t n_shots,
                           int64_t n_samples, double L, double a, double b, int64_t te, int n_pit,
-                          bool per_axis, const double *gate, hipStream_t s)
+                          bool per_axis, const double *gate, double *duals, hipStream_t s)
 {
     if (n_samples > kMaxProjectSamples)
         return hipErrorInvalidValue;
     if (precision == SPK_PLAIN_FP64)
         return launch_project_t((double *)kx, (double *)ky, (double *)kz, n_shots, n_samples, L,
-                                a, b, te, n_pit, per_axis ? 1 : 0, gate, s);
+                                a, b, te, n_pit, per_axis ? 1 : 0, gate, duals, s);
     return launch_project_t((float *)kx, (float *)ky, (float *)kz, n_shots, n_samples, L, a, b,
-                            te, n_pit, per_axis ? 1 : 0, gate, s);
+                            te, n_pit, per_axis ? 1 : 0, gate, duals, s);
 }
 
 hipError_t launch_constraint_check(int precision, const void *kx, const void *ky, const void *kz,

@@ -136,9 +136,11 @@ hipError_t launch_upsample(int precision, const void *kx, const void *ky, const 
 // Projection and constraint check (one block per shot).  per_axis selects the
 // per-axis maximum instead of the Euclidean norm in the speed and slew bounds.
 // gate (nullable, device): a NaN there skips the projection (a step not taken).
+// duals (nullable, device): [n_shots][6][n_samples] warm-start state, in/out.
 hipError_t launch_project(int precision, void *kx, void *ky, void *kz, int64_t n_shots,
                           int64_t n_samples, double L, double a, double b, int64_t te,
-                          int n_pit, bool per_axis, const double *gate, hipStream_t s);
+                          int n_pit, bool per_axis, const double *gate, double *duals,
+                          hipStream_t s);
 // per_shot: n_shots*4 doubles; out: 4 doubles.
 hipError_t launch_constraint_check(int precision, const void *kx, const void *ky, const void *kz,
                                    int64_t n_shots, int64_t n_samples, double L, double a,

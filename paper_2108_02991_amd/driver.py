@@ -38,12 +38,14 @@ def fixed_step(prm: api.Params, rho_mass: float, rule: str, eta_fixed: float) ->
 def run(workload: configs.Workload, precision: str, iters: int, device="cuda:0",
         out=None, log_every: int = 1, rotation_variant: bool = False, kernel: str = "distance",
         eps: float = 0.0, eta_rule: str = "fixed", graph: bool = False,
-        far_field: tuple = (0, 5, 0)):
+        far_field: tuple = (0, 5, 0), warm_duals: bool = False):
     """Runs `iters` projected gradient steps; returns the list of records.
 
     With graph=True the step runs as two captured HIP graphs (fixed-step and
     Barzilai-Borwein phases) with no host synchronisation between steps; a
-    record is then written only at the logged iterations and at the end."""
+    record is then written only at the logged iterations and at the end.
+    With warm_duals=True every projection starts from the previous one's dual
+    variables (spk_params.proj_duals) instead of from zero."""
     dev = torch.device(device)
     a, b = api.alpha_beta(configs.GMAX, configs.SMAX, configs.RASTER_DT, configs.DWELL_DT,
                           workload.fov, workload.kmax, configs.GAMMA_BAR, workload.half_width)
@@ -56,6 +58,8 @@ def run(workload: configs.Workload, precision: str, iters: int, device="cuda:0",
     K = torch.tensor(workload.trajectory(), dtype=prm.dtype, device=dev)
     rho = torch.tensor(rho_host, dtype=prm.dtype, device=dev)
     eta = fixed_step(prm, float(rho_host.sum()), eta_rule, workload.eta_fixed)
+    if warm_duals:
+        prm.proj_duals = api.new_duals(prm, dev)
     viol0 = api.project_(K, prm)
     state = api.StepState(prm, dev)
     records = []
@@ -179,7 +183,7 @@ def _level_depth(depth: int, d: int) -> int:
 
 def multiresolution(K0: torch.Tensor, rho: torch.Tensor, prm_full: api.Params, levels: int,
                     n_git: int, final_level: bool = True, eta_scale: float = 0.25, out=None,
-                    log_every: int = 0, eta_rule: str = "fixed"):
+                    log_every: int = 0, eta_rule: str = "fixed", warm_duals: bool = False):
     """Algorithm 1 (multi-resolution SPARKLING) on the GPU.
 
     K0 holds the coarsest shots, prm_full.n_samples >> levels samples each.  At
@@ -190,8 +194,9 @@ def multiresolution(K0: torch.Tensor, rho: torch.Tensor, prm_full: api.Params, l
     p), and the result is up-sampled to twice the samples as the warm start of
     the next level.  With final_level=True the full resolution (d = 0) is
     optimised as well.  eta_rule="lipschitz" takes the fixed step 1/L of the
-    regularised kernel at each level instead.  Returns the final K and the
-    per-iteration records.
+    regularised kernel at each level instead.  warm_duals=True carries the
+    projection's dual variables from step to step within a level.  Returns
+    the final K and the per-iteration records.
     """
     if prm_full.n_samples % (1 << levels):
         raise ValueError("n_samples must be divisible by 2^levels")
@@ -215,6 +220,8 @@ def multiresolution(K0: torch.Tensor, rho: torch.Tensor, prm_full: api.Params, l
         eta = fixed_step(prm, float(rho.sum().item()), eta_rule,
                          eta_scale * (2.0 * prm.half_width) * float(prm.p) ** (2.0 / 3.0))
         state = api.StepState(prm, K.device)
+        if warm_duals:      # the dual state is per level (its shape follows N_s)
+            prm.proj_duals = api.new_duals(prm, K.device)
         for it in range(n_git):
             torch.cuda.synchronize(K.device)
             t0 = time.perf_counter()
@@ -256,6 +263,8 @@ def main():
                     help="fixed step of the first iterations: the workload's, or 1/L")
     ap.add_argument("--graph", action="store_true",
                     help="run the single-level loop as captured HIP graphs")
+    ap.add_argument("--warm-duals", action="store_true",
+                    help="start every projection from the previous one's dual variables")
     ap.add_argument("--n-pit", type=int, default=None,
                     help="projection iterations (default: the workload's)")
     ap.add_argument("--far-field", default=None, metavar="DEPTH,ORDER[,adaptive[=R]]",
@@ -274,7 +283,8 @@ def main():
         if args.levels == 0 and not args.field:
             run(w, precision, iters, out=out, log_every=args.log_every,
                 rotation_variant=args.rotation_variant, kernel=args.kernel, eps=args.eps,
-                eta_rule=args.eta, graph=args.graph, far_field=(ffd, ffo, ffa))
+                eta_rule=args.eta, graph=args.graph, far_field=(ffd, ffo, ffa),
+                warm_duals=args.warm_duals)
         else:
             dev = torch.device("cuda:0")
             a, b = api.alpha_beta(configs.GMAX, configs.SMAX, configs.RASTER_DT,
@@ -297,7 +307,8 @@ def main():
                 print(f"[driver] node field in {time.perf_counter() - t0:.2f} s",
                       file=sys.stderr, flush=True)
             K, recs = multiresolution(K0, rho, prm, args.levels, iters, out=out,
-                                      log_every=args.log_every, eta_rule=args.eta)
+                                      log_every=args.log_every, eta_rule=args.eta,
+                                      warm_duals=args.warm_duals)
             torch.cuda.synchronize(dev)
             total = time.perf_counter() - t0
             F, _, _, _ = api.energy(K, rho, prm)

@@ -45,6 +45,59 @@ def test_projection_te_and_box_exact(gpu, te):
         assert np.all(got[:, te::Ns] == 0.0) and viol[3] == 0.0
 
 
+@pytest.mark.parametrize("Ns,precision", [(64, "plain_fp64"), (1025, "plain_fp64"),
+                                          (2048, "plain_fp64"), (300, "fp32_comp")])
+def test_warm_started_projection_bitwise(gpu, Ns, precision):
+    """Duals carried by the caller (spk_params.proj_duals): two projections in a
+    row from a nonzero start, output and dual state equal to the oracle's."""
+    Nc = 5
+    K = inputs.radial_spokes(Nc, Ns, 0.5, seed=Ns + 1, jitter=0.05)
+    a, b = bounds(configs.C5)
+    rng = np.random.default_rng(Ns)
+    d0 = rng.normal(scale=1e-3, size=(Nc, 6, Ns))
+    d0[:, :3, Ns - 1] = 0.0
+    d0[:, 3:, Ns - 2:] = 0.0
+    duals = torch.tensor(d0, device=gpu)
+    prm = spk.Params(Nc, Ns, 1, precision=precision, a_max=a, b_max=b, n_pit=150,
+                     proj_duals=duals)
+    Kd, _ = device_problem(K, [1.0], precision, gpu)
+    ref_d = d0.copy()
+    ref = host64(Kd)
+    for call in range(2):
+        say(f"  warm projection {precision} Ns={Ns} call {call}")
+        if call == 1:     # the next input: a small move of the projected shots
+            Kd += torch.tensor(rng.uniform(-1e-3, 1e-3, K.shape), dtype=Kd.dtype, device=gpu)
+            ref = host64(Kd)
+        viol = spk.project_(Kd, prm)
+        ref = oracle.project(ref, Nc, Ns, 0.5, a, b, 0, 150, duals=ref_d)
+        if precision != "plain_fp64":
+            ref = ref.astype(np.float32).astype(np.float64)
+        assert np.array_equal(host64(Kd), ref), np.abs(host64(Kd) - ref).max()
+        assert np.array_equal(host64(duals), ref_d)
+        assert np.array_equal(viol, oracle.constraint_check(host64(Kd), Nc, Ns, 0.5, a, b, 0))
+
+
+def test_warm_started_steps_match_the_oracle(gpu):
+    """Projected gradient steps with carried duals, in plain FP64, step by step
+    against the oracle's steps with the same dual state."""
+    w = configs.C1
+    K, rho = w.trajectory(), w.density()
+    a, b = bounds(w)
+    duals = spk.new_duals(spk.Params(w.n_shots, w.n_samples, w.grid), gpu)
+    prm = params_for(w, "plain_fp64", proj_duals=duals)
+    Kd, rd = device_problem(K, rho, "plain_fp64", gpu)
+    state = spk.StepState(prm, gpu)
+    Ko, kp, gp = K.copy(), np.zeros_like(K), np.zeros_like(K)
+    od = np.zeros((w.n_shots, 6, w.n_samples))
+    for it in range(4):
+        info = spk.step_(Kd, rd, prm, state, it, w.eta_fixed)
+        Ko, kp, gp, oinfo = oracle.step(Ko, rho, w.n_shots, w.n_samples, w.grid, 0.5, a, b, 0,
+                                        w.n_pit, kp, gp, it, w.eta_fixed, duals=od)
+        assert info["F"] == pytest.approx(oinfo["F"], rel=1e-12)
+        assert np.abs(host64(Kd) - Ko).max() <= 1e-10
+        assert np.abs(host64(duals) - od).max() <= 1e-9 * max(np.abs(od).max(), 1e-30)
+
+
 def test_projection_fp32_storage(gpu):
     """FP32 trajectories: FP64 iteration on the widened values, one rounding on output."""
     Nc, Ns = 8, 300

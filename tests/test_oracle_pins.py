@@ -466,6 +466,65 @@ def test_projection_variational_inequality():
                                         for _ in range(20))
 
 
+# Warm-started duals: the dual iteration starts from a caller's dual state.
+def test_projection_zero_duals_are_the_cold_start_bitwise():
+    rng = np.random.default_rng(12)
+    a, b, L, Nc, Ns = 0.05, 0.004, 0.5, 4, 30
+    K = rng.uniform(-0.3, 0.3, (3, Nc * Ns))
+    duals = np.zeros((Nc, 6, Ns))
+    s = oracle.project(K, Nc, Ns, L, a, b, 0, 150, duals=duals)
+    assert np.array_equal(s, oracle.project(K, Nc, Ns, L, a, b, 0, 150))
+    # the state left behind is the last dual iterate: unused entries stay 0
+    assert np.all(duals[:, :3, Ns - 1] == 0) and np.all(duals[:, 3:, Ns - 2:] == 0)
+    assert np.abs(duals).max() > 0
+
+
+def test_projection_warm_start_reaches_the_same_projection():
+    """The projection is unique, so from any starting duals the converged
+    iteration returns it: warm and cold starts agree at 1e5 iterations, and
+    the converged duals reproduce it with no further iteration."""
+    rng = np.random.default_rng(13)
+    a, b, L, Nc, Ns = 0.05, 0.004, 0.5, 2, 24
+    K = rng.uniform(-0.3, 0.3, (3, Nc * Ns))
+    cold = oracle.project(K, Nc, Ns, L, a, b, 0, 100000)
+    duals = rng.normal(scale=0.01, size=(Nc, 6, Ns))
+    warm = oracle.project(K, Nc, Ns, L, a, b, 0, 100000, duals=duals)
+    np.testing.assert_allclose(warm, cold, atol=1e-10)
+    again = oracle.project(K, Nc, Ns, L, a, b, 0, 0, duals=duals.copy())
+    np.testing.assert_allclose(again, cold, atol=1e-10)
+    # the two-sample closed form holds from a warm start as well
+    for seed in range(3):
+        k = np.random.default_rng(seed).uniform(-0.3, 0.3, (3, 2))
+        d = np.random.default_rng(seed + 10).normal(scale=0.1, size=(1, 6, 2))
+        s2 = oracle.project(k, 1, 2, L, 0.1, 0.05, 0, 10000, duals=d)
+        k1 = k[:, 1]
+        np.testing.assert_allclose(s2[:, 1], k1 * min(1.0, 0.1 / np.linalg.norm(k1)), atol=1e-10)
+
+
+def test_projection_warm_start_tracks_a_moving_input():
+    """Along projected gradient steps the projection's input moves a little per
+    step: duals carried from the previous projection leave the iterate at a
+    fixed small n_pit closer to the converged projection than a cold start."""
+    from paper_2108_02991_amd import configs
+    w = configs.C5
+    a, b = oracle.alpha_beta(configs.GMAX, configs.SMAX, configs.RASTER_DT, configs.DWELL_DT,
+                             w.fov, w.kmax, configs.GAMMA_BAR, w.half_width)
+    Nc, Ns, G = 8, 256, 8
+    rho = inputs.radial_density(G, 0.5, 0.0625, 2.0)
+    K = oracle.project(inputs.radial_spokes(Nc, Ns, 0.5, seed=14, jitter=0.05), Nc, Ns, 0.5,
+                       a, b, 0, 20000)
+    eta = 0.25 * (Nc * Ns) ** (2.0 / 3.0)
+    duals = np.zeros((Nc, 6, Ns))
+    for it in range(4):
+        half = K - eta * oracle.grad(K, rho, G, 0.5)["dF"]
+        if it > 0:
+            exact = oracle.project(half, Nc, Ns, 0.5, a, b, 0, 50000)
+            warm = oracle.project(half, Nc, Ns, 0.5, a, b, 0, 50, duals=duals.copy())
+            cold = oracle.project(half, Nc, Ns, 0.5, a, b, 0, 50)
+            assert np.abs(warm - exact).max() < 0.6 * np.abs(cold - exact).max(), it
+        K = oracle.project(half, Nc, Ns, 0.5, a, b, 0, 200, duals=duals)
+
+
 # Rotation-variant (per-axis) bounds: the constraint set is a product of one
 # polytope per axis, so each axis is an independent box-constrained QP.
 def test_projection_per_axis_two_samples_te0():
