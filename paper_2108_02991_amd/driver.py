@@ -61,6 +61,10 @@ def run(workload: configs.Workload, precision: str, iters: int, device="cuda:0",
     if warm_duals:
         prm.proj_duals = api.new_duals(prm, dev)
     viol0 = api.project_(K, prm)
+    if warm_duals:
+        # the duals of the jittered start's projection are far from what the
+        # nearly feasible iterates need: the loop's first projection starts cold
+        prm.proj_duals.zero_()
     state = api.StepState(prm, dev)
     records = []
     if graph:

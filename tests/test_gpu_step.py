@@ -196,3 +196,14 @@ def test_c3_step_sampled_shots(gpu):
     assert info["eta"] == w.eta_fixed
     assert diff <= 1e-6     # FP32 storage of K (about 3e-8 at |k| <= 0.5) plus FP32-comp rows
     assert np.all(got[:, [0, Ns]] == 0.0) and np.abs(got).max() <= 0.5
+    # Feasibility after n_pit = 200 from the jittered start (slew 540x over the
+    # bound): box and TE exact, speed within its bound, slew left above it at
+    # the levels measured with the oracle (2.20 on these two shots, 4.22 over
+    # all 4096; about 3000 iterations bring these shots within 1%).  Bounds
+    # that catch a regression of the projection or of the step before it.
+    v2 = oracle.constraint_check(got, 2, Ns, 0.5, a, b, 0)
+    say(f"  c3 step violations: all shots {np.round(info['viol'], 4).tolist()}, two shots "
+        f"{np.round(v2, 4).tolist()}")
+    assert info["viol"][2] <= 1.0 and info["viol"][3] == 0.0
+    assert info["viol"][0] <= 1.0 and info["viol"][1] <= 4.5
+    assert v2[0] <= 1.0 and v2[1] <= 2.3
