@@ -3,6 +3,7 @@
 // declared in sparkling.h.
 
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <algorithm>
 #include <cfloat>
@@ -64,6 +65,27 @@ constexpr int kKinds = 5;
 double g_ms[kKinds] = {};
 int64_t g_launches[kKinds] = {};
 double g_pairs[kKinds] = {};
+
+// A roctx range around one entry point (seen by rocprofv3 --marker-trace; a
+// no-op without a profiler).  None inside an allocation-free call.
+class Range {
+  public:
+    explicit Range(const char *name) : on_(!t_untimed)
+    {
+        if (on_)
+            roctxRangePushA(name);
+    }
+    ~Range()
+    {
+        if (on_)
+            roctxRangePop();
+    }
+    Range(const Range &) = delete;
+    Range &operator=(const Range &) = delete;
+
+  private:
+    bool on_;
+};
 
 // Brackets one launch with events when timing is on.
 class Timed {
@@ -738,6 +760,7 @@ int sparkling_grad(const spk_params *prm, const void *kx, const void *ky, const 
                    int64_t tgt_end, double *pot_a, double *pot_r, double *energy, void *ws,
                    size_t ws_bytes, void *stream)
 {
+    Range range("sparkling_grad");
     g_err.clear();
     int rc = check_params(prm, false);
     if (rc)
@@ -789,6 +812,7 @@ int sparkling_grad(const spk_params *prm, const void *kx, const void *ky, const 
 int sparkling_field(const spk_params *prm, const void *rho, void *field, void *ws,
                     size_t ws_bytes, void *stream)
 {
+    Range range("sparkling_field");
     g_err.clear();
     int rc = check_params(prm, false);
     if (rc)
@@ -842,6 +866,7 @@ int sparkling_field(const spk_params *prm, const void *rho, void *field, void *w
 int sparkling_energy(const spk_params *prm, const void *kx, const void *ky, const void *kz,
                      const void *rho, double out[4], void *ws, size_t ws_bytes, void *stream)
 {
+    Range range("sparkling_energy");
     g_err.clear();
     int rc = check_params(prm, false);
     if (rc)
@@ -912,6 +937,7 @@ int sparkling_constraint_check(const spk_params *prm, const void *kx, const void
                                const void *kz, double viol[4], void *ws, size_t ws_bytes,
                                void *stream)
 {
+    Range range("sparkling_constraint_check");
     g_err.clear();
     int rc = check_params(prm, true);
     if (rc)
@@ -932,6 +958,7 @@ int sparkling_constraint_check(const spk_params *prm, const void *kx, const void
 int sparkling_project(const spk_params *prm, void *kx, void *ky, void *kz, double *viol, void *ws,
                       size_t ws_bytes, void *stream)
 {
+    Range range("sparkling_project");
     g_err.clear();
     int rc = check_params(prm, true);
     if (rc)
@@ -955,6 +982,7 @@ int sparkling_step(const spk_params *prm, void *kx, void *ky, void *kz, const vo
                    void *k_prev, void *g_prev, spk_step_info *info, void *ws, size_t ws_bytes,
                    void *stream)
 {
+    Range range("sparkling_step");
     g_err.clear();
     if (!info)
         return fail(SPK_EINVAL, "info is NULL");
@@ -998,6 +1026,7 @@ int sparkling_step_async(const spk_params *prm, void *kx, void *ky, void *kz, co
                          void *k_prev, void *g_prev, int64_t iter, double eta_fixed,
                          double *info_dev, void *ws, size_t ws_bytes, void *stream)
 {
+    Range range("sparkling_step_async");
     g_err.clear();
     Ws w;
     int rc = check_step(prm, kx, ky, kz, rho, k_prev, g_prev, iter, eta_fixed, ws, ws_bytes, &w);
@@ -1100,6 +1129,7 @@ int sparkling_step_async_noalloc(const spk_params *prm, void *kx, void *ky, void
 int sparkling_upsample(const spk_params *prm, const void *kx, const void *ky, const void *kz,
                        void *fx, void *fy, void *fz, void *stream)
 {
+    Range range("sparkling_upsample");
     g_err.clear();
     int rc = check_params(prm, false);
     if (rc)
