@@ -20,7 +20,8 @@ timed (`steps`) beside the requested ones (`steps_requested`).
 Prints one JSON line.  `value` is pair interactions per second over the whole
 step (p^2 repulsion + p*G^3 attraction per step); the roofline object is for
 the dominant kernel (the repulsion sweep), timed live with HIP events on the
-stream it runs on.  The CPU baseline is the FP64 oracle timed on a bounded
+stream it runs on, against the FP32 vector peak and, under `ceiling`, against
+the measured issue rate of the pair's own instruction mix.  The CPU baseline is the FP64 oracle timed on a bounded
 sample of targets of the same workload.
 """
 from __future__ import annotations
@@ -186,6 +187,16 @@ def main():
     torch.cuda.synchronize()
     log("inputs resident, kernels loaded")
 
+    # issue bound of the repulsion pair on this device from measured component
+    # rates (register-only probes, untimed region): what the sweep's fraction
+    # is also read against
+    probe = None
+    if not ff_depth and args.kernel == "distance" and precision == "fp32_comp":
+        probe = spk.pair_issue_bound(device=dev)
+        log(f"pair issue bound: {probe['pairs_per_s']:.4g} pairs/s = "
+            f"{probe['tflops_at_17']:.2f} TFLOP/s at 17 flop/pair (reciprocal square root "
+            f"{probe['rsqrt_in_fma_slots']:.2f} FMA slots)")
+
     # Warm-up and timed steps each stop at a wall budget: an exact c3 step
     # takes about 26 s, so the requested counts may not fit.  Each step ends
     # with a host read of its info (sparkling_step synchronises the stream).
@@ -280,7 +291,18 @@ def main():
         },
         "roofline": ({"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS,
                       "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK_TFLOPS,
-                      "traffic": recorded_traffic(w.name, precision, args.kernel)}
+                      "traffic": recorded_traffic(w.name, precision, args.kernel),
+                      "ceiling": ({"kind": "issue bound of the pair from measured component "
+                                           "rates: its 10 FP32 instructions at their stream "
+                                           "rate plus one reciprocal square root at its cost "
+                                           "(spk_probe_pair_mix, registers only)",
+                                   "achieved": probe["tflops_at_17"],
+                                   "frac_of_peak": probe["tflops_at_17"] / FP32_VECTOR_PEAK_TFLOPS,
+                                   "kernel_frac_of_ceiling": achieved / probe["tflops_at_17"],
+                                   "rsqrt_in_fma_slots": probe["rsqrt_in_fma_slots"],
+                                   "fixed_order_mix_pairs_per_s":
+                                       probe["fixed_order_mix_pairs_per_s"]}
+                                  if probe else None)}
                      if not ff_depth else None),
         "last_step": {k: (v.tolist() if isinstance(v, np.ndarray) else v)
                       for k, v in infos[-1].items()},

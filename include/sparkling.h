@@ -362,6 +362,22 @@ int sparkling_step_async_noalloc(const spk_params *prm, void *kx, void *ky, void
 size_t spk_noalloc_scratch_bytes(void);
 
 /*
+ * Calibration, not an operation of the paper: issue rates of the repulsion
+ * pair's instruction mix on the current device.  One launch of `blocks`
+ * blocks of 256 threads runs, per thread and iteration, 4 sources against 2
+ * targets with the sweep's per-pair instructions (variant 0: 3 subtractions,
+ * 3 FMAs for |d|^2, v_rsq_f32, 4 FMAs, in one fixed order), the same without
+ * the reciprocal square root (1), or the reciprocal square roots with one FMA
+ * each (2), in registers only.  pairs (out) = blocks * 256 * iters * 8;
+ * ms (out) = the launch's duration by HIP events.  scratch: device,
+ * >= blocks * 256 * 4 bytes (one result per thread, so nothing is removed).
+ * Synchronises `stream`.  SPK_EINVAL for a bad variant, blocks outside
+ * [1, 2^20] or iters < 1; SPK_EWORKSPACE for a short scratch.
+ */
+int spk_probe_pair_mix(int variant, int64_t blocks, int32_t iters, void *scratch,
+                       size_t scratch_bytes, double *pairs, double *ms, void *stream);
+
+/*
  * Kernel timing.  While enabled, every kernel launch of the kinds below is
  * bracketed by HIP events on the stream it runs on; spk_timing_query()
  * waits for those events and returns, for one kind, the summed duration in

@@ -83,6 +83,8 @@ def load_library(path: Path | str | None = None):
         "sparkling_step_async_noalloc": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _dbl, _vp,
                                           _vp], ctypes.c_int),
         "spk_noalloc_scratch_bytes": ([], _sz),
+        "spk_probe_pair_mix": ([ctypes.c_int, _i64, _i32, _vp, _sz, _vp, _vp, _vp],
+                               ctypes.c_int),
         "spk_timing_enable": ([ctypes.c_int], ctypes.c_int),
         "spk_timing_query": ([ctypes.c_int, _vp, _vp, _vp], ctypes.c_int),
         "spk_timing_reset": ([], ctypes.c_int),
@@ -430,6 +432,46 @@ def step_async_noalloc_(K: torch.Tensor, rho: torch.Tensor, prm: Params, state: 
 
 def noalloc_scratch_bytes() -> int:
     return int(load_library().spk_noalloc_scratch_bytes())
+
+
+PROBE_VARIANTS = {"pair": 0, "pair_without_rsqrt": 1, "rsqrt": 2}
+
+
+def probe_pair_mix(variant: str = "pair", blocks: int = 32768, iters: int = 1024,
+                   reps: int = 3, device="cuda:0") -> dict:
+    """Issue rate of the repulsion pair's instruction mix (spk_probe_pair_mix):
+    the best of `reps` launches, as pairs/s and, for the full pair, TFLOP/s at
+    the sweep's 17 flop/pair."""
+    v = PROBE_VARIANTS[variant]
+    scratch = torch.empty(blocks * 256, dtype=torch.float32, device=device)
+    pairs, ms = _dbl(), _dbl()
+    best = None
+    for _ in range(max(reps, 1)):
+        _check(load_library().spk_probe_pair_mix(
+            v, blocks, iters, _vp(scratch.data_ptr()), scratch.numel() * 4, ctypes.byref(pairs),
+            ctypes.byref(ms), _stream(scratch)), "spk_probe_pair_mix")
+        best = ms.value if best is None else min(best, ms.value)
+    rate = pairs.value / (best * 1e-3)
+    return {"variant": variant, "blocks": blocks, "iters": iters, "pairs": pairs.value,
+            "ms": best, "pairs_per_s": rate, "tflops_at_17": 17.0 * rate / 1e12}
+
+
+def pair_issue_bound(device="cuda:0") -> dict:
+    """Issue bound of the repulsion pair from measured component rates: the
+    pair's 10 FP32 instructions at the rate they stream at (probe variant 1)
+    plus one reciprocal square root at its cost (variant 2 minus its FMA, one
+    tenth of variant 1's pair).  Also the whole mix in one fixed order
+    (variant 0), for comparison."""
+    fma = probe_pair_mix("pair_without_rsqrt", device=device)
+    rsq = probe_pair_mix("rsqrt", device=device)
+    mix = probe_pair_mix("pair", device=device)
+    t_fma10 = 1.0 / fma["pairs_per_s"]
+    t_rsq = 1.0 / rsq["pairs_per_s"] - t_fma10 / 10.0
+    rate = 1.0 / (t_fma10 + t_rsq)
+    return {"pairs_per_s": rate, "tflops_at_17": 17.0 * rate / 1e12,
+            "rsqrt_in_fma_slots": t_rsq / (t_fma10 / 10.0),
+            "fma_stream_lane_ops_per_s": 10.0 * fma["pairs_per_s"],
+            "fixed_order_mix_pairs_per_s": mix["pairs_per_s"]}
 
 
 def info_dict(info: torch.Tensor) -> dict:

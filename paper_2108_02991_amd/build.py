@@ -18,7 +18,7 @@ BUILD_DIR = ROOT / "_build"
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["sweep.hip", "reduce.hip", "project.hip", "field.hip", "fftfield.hip", "fmm.hip",
-           "api.cpp"]
+           "probe.hip", "api.cpp"]
 
 # Packed FP32 instructions are disabled: scalar and float2 code must not be
 # turned into v_pk_* FP32 operations on this target.

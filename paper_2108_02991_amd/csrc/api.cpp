@@ -1148,6 +1148,48 @@ int sparkling_upsample(const spk_params *prm, const void *kx, const void *ky, co
     return SPK_OK;
 }
 
+int spk_probe_pair_mix(int variant, int64_t blocks, int32_t iters, void *scratch,
+                       size_t scratch_bytes, double *pairs, double *ms, void *stream)
+{
+    g_err.clear();
+    if (variant < 0 || variant > 2)
+        return fail(SPK_EINVAL, "probe variant must be 0, 1 or 2 (got %d)", variant);
+    if (blocks < 1 || blocks > (int64_t(1) << 20) || iters < 1)
+        return fail(SPK_EINVAL, "probe needs 1 <= blocks <= 2^20 and iters >= 1");
+    if (!pairs || !ms)
+        return fail(SPK_EINVAL, "pairs and ms must not be NULL");
+    int rc;
+    if ((rc = check_ptr(scratch, "scratch", 4)))
+        return rc;
+    const size_t need = sizeof(float) * (size_t)probe_out_elements(blocks);
+    if (scratch_bytes < need)
+        return fail(SPK_EWORKSPACE, "probe scratch needs %zu bytes (got %zu)", need,
+                    scratch_bytes);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    struct Ev {
+        hipEvent_t a = nullptr, b = nullptr;
+        ~Ev()
+        {
+            if (a)
+                (void)hipEventDestroy(a);
+            if (b)
+                (void)hipEventDestroy(b);
+        }
+    } ev;
+    SPK_HIP(hipEventCreate(&ev.a), "probe event");
+    SPK_HIP(hipEventCreate(&ev.b), "probe event");
+    SPK_HIP(hipEventRecord(ev.a, s), "probe event record");
+    SPK_HIP(launch_pair_mix_probe(variant, static_cast<float *>(scratch), blocks, iters, s),
+            "probe launch");
+    SPK_HIP(hipEventRecord(ev.b, s), "probe event record");
+    SPK_HIP(hipEventSynchronize(ev.b), "probe synchronize");
+    float t = 0.f;
+    SPK_HIP(hipEventElapsedTime(&t, ev.a, ev.b), "probe elapsed time");
+    *ms = t;
+    *pairs = (double)probe_pairs(blocks, iters);
+    return SPK_OK;
+}
+
 int spk_timing_enable(int on)
 {
     std::lock_guard<std::mutex> lk(g_tmu);

@@ -147,4 +147,13 @@ hipError_t launch_constraint_check(int precision, const void *kx, const void *ky
                                    double b, int64_t te, bool per_axis, double *per_shot,
                                    double *out, hipStream_t s);
 
+// Issue-rate probe of the repulsion pair's instruction mix (probe.hip).
+// variant 0: the pair's 10 FP32 instructions + v_rsq_f32; 1: without the
+// reciprocal square root; 2: reciprocal square roots (and one add each) alone.
+// out: probe_out_elements(blocks) floats; each launch runs probe_pairs() pairs.
+int64_t probe_out_elements(int64_t blocks);
+int64_t probe_pairs(int64_t blocks, int iters);
+hipError_t launch_pair_mix_probe(int variant, float *out, int64_t blocks, int iters,
+                                 hipStream_t s);
+
 }  // namespace spk

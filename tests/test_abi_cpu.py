@@ -296,6 +296,20 @@ def test_noalloc_step_validation(lib):
     assert call(good_params(far_field_depth=3, far_field_order=4)) == EUNSUPPORTED
 
 
+def test_probe_validation(lib):
+    v = ctypes.c_void_p
+    pairs, ms = ctypes.c_double(), ctypes.c_double()
+
+    def call(variant=0, blocks=4, iters=1, scratch=FAKE, nbytes=1 << 20, p=True):
+        return lib.spk_probe_pair_mix(variant, blocks, iters, v(scratch), nbytes,
+                                      ctypes.byref(pairs) if p else None, ctypes.byref(ms), None)
+    assert call(variant=3) == EINVAL and call(variant=-1) == EINVAL
+    assert call(blocks=0) == EINVAL and call(blocks=(1 << 20) + 1) == EINVAL
+    assert call(iters=0) == EINVAL and call(p=False) == EINVAL
+    assert call(scratch=0) == EINVAL
+    assert call(blocks=4, nbytes=4 * 256 * 4 - 1) == EWORKSPACE
+
+
 def test_timing_query_rejects_unknown_kind(lib):
     assert lib.spk_timing_query(9, None, None, None) == EINVAL
 
