@@ -91,7 +91,7 @@ def test_c4_autograd_fp32(gpu):
 
     say("  c4 oracle energy and gradient")
     oF = oracle.energy(K64, r64, w.grid, 0.5)[0]
-    assert float(F) == pytest.approx(oF, rel=1e-6)
+    assert float(F.detach()) == pytest.approx(oF, rel=1e-6)
     og = oracle.grad(K64, r64, w.grid, 0.5)["dF"]
     err = rel_l2(g, og)
     say(f"  c4 backward rel L2 vs oracle = {err:.3e}")
