@@ -47,6 +47,8 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3
 # log kernel swaps the reciprocal square root for a reciprocal and the energy
 # FMA for a log2 and an add: the same count.
 FLOP_PER_PAIR_REPULSION = 17
+# Without the per-pair energy term (--energy-from-force: F^r from the forces).
+FLOP_PER_PAIR_REPULSION_NO_ENERGY = 15
 FLOP_PER_PAIR_ATTRACTION = 18
 
 
@@ -117,6 +119,9 @@ def main():
     ap.add_argument("--warmup-budget", type=float, default=30.0,
                     help="wall seconds of warm-up steps, by the same rule (at least one step "
                          "when --warmup > 0)")
+    ap.add_argument("--energy-from-force", action="store_true",
+                    help="F^r from the repulsion forces (Euler's theorem for H = |d|): the "
+                         "sweep skips its per-pair energy term (15 flop/pair)")
     ap.add_argument("--init-pit", type=int, default=3000,
                     help="projection iterations of the one untimed projection of the initial "
                          "trajectory before the warm-up, as the optimisation loop starts from "
@@ -148,7 +153,8 @@ def main():
     prm = spk.Params(w.n_shots, w.n_samples, w.grid, precision=precision,
                      half_width=w.half_width, eps=eps, a_max=a, b_max=b, te_index=0,
                      n_pit=w.n_pit, kernel=args.kernel, far_field_depth=ff_depth,
-                     far_field_order=ff_order, far_field_adaptive=ff_adaptive)
+                     far_field_order=ff_order, far_field_adaptive=ff_adaptive,
+                     energy_from_force=args.energy_from_force)
     p, M = prm.p, w.n_voxels
 
     log(f"workload {w.name}: p={p} G={w.grid} precision={precision} kernel={args.kernel} "
@@ -191,7 +197,8 @@ def main():
     # rates (register-only probes, untimed region): what the sweep's fraction
     # is also read against
     probe = None
-    if not ff_depth and args.kernel == "distance" and precision == "fp32_comp":
+    if (not ff_depth and args.kernel == "distance" and precision == "fp32_comp"
+            and not args.energy_from_force):
         probe = spk.pair_issue_bound(device=dev)
         log(f"pair issue bound: {probe['pairs_per_s']:.4g} pairs/s = "
             f"{probe['tflops_at_17']:.2f} TFLOP/s at 17 flop/pair (reciprocal square root "
@@ -247,7 +254,9 @@ def main():
     rep = kern["repulsion"]
     rep_avg_ms = rep["ms"] / max(rep["launches"], 1)
     rep_pairs_per_launch = rep["pairs"] / max(rep["launches"], 1)
-    achieved = FLOP_PER_PAIR_REPULSION * rep_pairs_per_launch / (rep_avg_ms * 1e-3) / 1e12
+    flop_rep = (FLOP_PER_PAIR_REPULSION_NO_ENERGY if args.energy_from_force
+                else FLOP_PER_PAIR_REPULSION)
+    achieved = flop_rep * rep_pairs_per_launch / (rep_avg_ms * 1e-3) / 1e12
     att = kern["attraction"]
     att_tflops = (FLOP_PER_PAIR_ATTRACTION * att["pairs"] / (att["ms"] * 1e-3) / 1e12
                   if att["ms"] > 0 else None)

@@ -90,9 +90,19 @@ enum {
                                         with eps^2 a normal number of the form's type,
                                         and the plain_fp64 or fp32_comp form
                                         (SPK_EUNSUPPORTED otherwise)                   */
-    SPK_FLAG_FIELD_DIRECT = 8        /* sparkling_field sums the node field directly
+    SPK_FLAG_FIELD_DIRECT = 8,       /* sparkling_field sums the node field directly
                                         over the cells in the precision form instead
                                         of by FP64 FFT convolution                      */
+    SPK_FLAG_ENERGY_FROM_FORCE = 16  /* F^r from the repulsion forces: with H = |d|,
+                                        F^r is homogeneous of degree 1 in K (every
+                                        distance scales with K), so by Euler's theorem
+                                        F^r = sum_i K[i] . dF^r/dK[i]; the repulsion
+                                        sweep then skips its per-pair distance term.
+                                        Distance kernel with eps = 0 and the exact
+                                        repulsion only (SPK_EINVAL with eps > 0, the log
+                                        kernel or far_field_depth > 0); per-target
+                                        repulsion potentials are then not available
+                                        (sparkling_grad with pot_r: SPK_EINVAL)        */
 };
 
 typedef struct {

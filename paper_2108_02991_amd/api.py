@@ -24,6 +24,7 @@ FLAG_DISCREPANCY = 1
 FLAG_ROTATION_VARIANT = 2
 FLAG_LOG_KERNEL = 4
 FLAG_FIELD_DIRECT = 8
+FLAG_ENERGY_FROM_FORCE = 16
 KERNELS = {"distance": 0, "log": FLAG_LOG_KERNEL}
 KIND_REPULSION, KIND_ATTRACTION, KIND_PROJECTION, KIND_OTHER, KIND_INTERPOLATION = 0, 1, 2, 3, 4
 
@@ -126,6 +127,7 @@ class Params:
     far_field_adaptive: int = 0                      # refinement levels of dense cells (0..2)
     far_field_overlap: bool = True                   # near-field sums on a second stream
     proj_duals: "torch.Tensor | None" = None         # warm-start duals (new_duals()); None = cold
+    energy_from_force: bool = False                  # F^r = sum_i K[i] . dF^r/dK[i] (H = |d|)
     field_direct: bool = False                       # node field summed directly, not by FFT
     _c: SpkParams = field(default=None, repr=False, compare=False)
 
@@ -156,7 +158,8 @@ class Params:
                          (FLAG_DISCREPANCY if self.discrepancy else 0)
                          | (FLAG_ROTATION_VARIANT if self.rotation_variant else 0)
                          | KERNELS[self.kernel]
-                         | (FLAG_FIELD_DIRECT if self.field_direct else 0),
+                         | (FLAG_FIELD_DIRECT if self.field_direct else 0)
+                         | (FLAG_ENERGY_FROM_FORCE if self.energy_from_force else 0),
                          _vp(f.data_ptr()) if f is not None else None,
                          self.far_field_depth, self.far_field_order if self.far_field_depth else 0,
                          int(self.far_field_adaptive),

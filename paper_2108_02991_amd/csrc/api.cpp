@@ -162,8 +162,12 @@ int check_params(const spk_params *prm, bool need_projection)
     if (prm->te_index < -1 || prm->te_index >= prm->n_samples)
         return fail(SPK_EINVAL, "te_index must be -1 or in [0, n_samples)");
     if (prm->flags & ~(SPK_FLAG_DISCREPANCY | SPK_FLAG_ROTATION_VARIANT | SPK_FLAG_LOG_KERNEL |
-                       SPK_FLAG_FIELD_DIRECT))
+                       SPK_FLAG_FIELD_DIRECT | SPK_FLAG_ENERGY_FROM_FORCE))
         return fail(SPK_EINVAL, "unknown flags 0x%x", prm->flags);
+    if ((prm->flags & SPK_FLAG_ENERGY_FROM_FORCE) &&
+        (prm->eps != 0.0 || (prm->flags & SPK_FLAG_LOG_KERNEL) || prm->far_field_depth != 0))
+        return fail(SPK_EINVAL, "the energy from the forces needs the distance kernel with "
+                                "eps = 0 and the exact repulsion");
     if (prm->flags & SPK_FLAG_LOG_KERNEL) {
         if (prm->precision != SPK_PLAIN_FP64 && prm->precision != SPK_FP32_COMP)
             return fail(SPK_EUNSUPPORTED, "the log kernel runs in the plain_fp64 and fp32_comp "
@@ -533,12 +537,21 @@ int run_gradient_sums(const spk_params *prm, const void *kx, const void *ky, con
                       hipStream_t s)
 {
     const int64_t p = prm->n_shots * prm->n_samples;
+    // with the energy from the forces the sweep skips its per-pair distances,
+    // and each target's repulsion potential row holds 2 K[i] . G[i], whose sum
+    // over all targets is the sum over all pairs of |K[i] - K[j]|
+    const bool from_force = energy && (prm->flags & SPK_FLAG_ENERGY_FROM_FORCE);
     int rc = prm->far_field_depth > 0
                  ? run_far_field(prm, kx, ky, kz, t0, nt, energy, w, s)
-                 : run_sweep(prm, false, kx, ky, kz, t0, nt, p, kx, ky, kz, nullptr, energy, w,
-                             w.acc_r(), s);
+                 : run_sweep(prm, false, kx, ky, kz, t0, nt, p, kx, ky, kz, nullptr,
+                             energy && !from_force, w, w.acc_r(), s);
     if (rc)
         return rc;
+    if (from_force) {
+        Timed tm(SPK_KIND_OTHER, 0.0, s);
+        SPK_HIP(launch_force_potential(prm->precision, kx, ky, kz, t0, nt, w.acc_r(), w.L.ld, s),
+                "energy from the forces");
+    }
     if (prm->attraction_field) {
         Timed tm(SPK_KIND_INTERPOLATION, (double)nt, s);
         SPK_HIP(launch_interpolate(prm->precision, kx, ky, kz, t0, nt, prm->grid, prm->half_width,
@@ -779,6 +792,9 @@ int sparkling_grad(const spk_params *prm, const void *kx, const void *ky, const 
         return rc;
     if ((pot_a && (rc = check_ptr(pot_a, "pot_a", 8))) || (pot_r && (rc = check_ptr(pot_r, "pot_r", 8))))
         return rc;
+    if (pot_r && (prm->flags & SPK_FLAG_ENERGY_FROM_FORCE))
+        return fail(SPK_EINVAL, "per-target repulsion potentials are not available with the "
+                                "energy from the forces");
     if (energy && (tgt_begin != 0 || tgt_end != p))
         return fail(SPK_EINVAL, "energy needs the full target range [0, p)");
     Ws w;

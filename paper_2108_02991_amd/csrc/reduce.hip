@@ -385,4 +385,36 @@ hipError_t launch_step_policy(const double *scal, int64_t p, double eta_fixed, b
     return hipGetLastError();
 }
 
+namespace {
+// 2 K[t] . G[t] per target, in double with contraction off (one fixed order).
+template <typename T>
+__global__ __launch_bounds__(EW) void force_potential_kernel(const T *kx, const T *ky,
+                                                             const T *kz, int64_t t0, int64_t nt,
+                                                             double *acc, int64_t ld)
+{
+#pragma clang fp contract(off)
+    const int64_t t = (int64_t)blockIdx.x * EW + threadIdx.x;
+    if (t >= nt)
+        return;
+    const double x = (double)kx[t0 + t], y = (double)ky[t0 + t], z = (double)kz[t0 + t];
+    acc[3 * ld + t] = 2.0 * ((x * acc[t] + y * acc[ld + t]) + z * acc[2 * ld + t]);
+}
+}  // namespace
+
+hipError_t launch_force_potential(int precision, const void *kx, const void *ky, const void *kz,
+                                  int64_t t0, int64_t nt, double *acc, int64_t ld, hipStream_t s)
+{
+    if (nt <= 0)
+        return hipSuccess;
+    if (precision == SPK_PLAIN_FP64)
+        hipLaunchKernelGGL(force_potential_kernel<double>, dim3(ew_blocks(nt)), dim3(EW), 0, s,
+                           (const double *)kx, (const double *)ky, (const double *)kz, t0, nt,
+                           acc, ld);
+    else
+        hipLaunchKernelGGL(force_potential_kernel<float>, dim3(ew_blocks(nt)), dim3(EW), 0, s,
+                           (const float *)kx, (const float *)ky, (const float *)kz, t0, nt,
+                           acc, ld);
+    return hipGetLastError();
+}
+
 }  // namespace spk

@@ -156,4 +156,11 @@ int64_t probe_pairs(int64_t blocks, int iters);
 hipError_t launch_pair_mix_probe(int variant, float *out, int64_t blocks, int iters,
                                  hipStream_t s);
 
+// Repulsion potential rows from the forces: acc[3*ld + t] = 2 K[t0+t] . acc[0..2][t]
+// for t in [0, nt) (in double; their sum over all targets is the pair sum of
+// |K[i] - K[j]| when H = |d|).
+hipError_t launch_force_potential(int precision, const void *kx, const void *ky, const void *kz,
+                                  int64_t t0, int64_t nt, double *acc, int64_t ld,
+                                  hipStream_t s);
+
 }  // namespace spk

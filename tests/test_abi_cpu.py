@@ -118,9 +118,27 @@ def test_unknown_precision_and_flags(lib):
     n = ctypes.c_size_t()
     assert lib.spk_workspace_size(ctypes.byref(c), ctypes.byref(n)) == EINVAL
     c = good_params().c()
-    c.flags = 16
+    c.flags = 32
     assert lib.spk_workspace_size(ctypes.byref(c), ctypes.byref(n)) == EINVAL
     assert lib.spk_workspace_size(None, ctypes.byref(n)) == EINVAL
+
+
+def test_energy_from_force_validation(lib):
+    """The energy from the forces needs H = |d|: eps = 0, the distance kernel,
+    the exact repulsion; and no per-target repulsion potentials."""
+    n = ctypes.c_size_t()
+    ok = good_params(energy_from_force=True)
+    assert lib.spk_workspace_size(ctypes.byref(ok.c()), ctypes.byref(n)) == 0
+    for kw in (dict(eps=0.01), dict(kernel="log", eps=0.01),
+               dict(far_field_depth=3, far_field_order=4)):
+        c = good_params(energy_from_force=True, **kw).c()
+        assert lib.spk_workspace_size(ctypes.byref(c), ctypes.byref(n)) == EINVAL, kw
+    v = ctypes.c_void_p
+    c = ok.c()
+    args = [v(FAKE)] * 7
+    assert lib.sparkling_grad(ctypes.byref(c), *args, 0, ok.p, None, v(FAKE), None, v(FAKE),
+                              spk.workspace_size(ok), None) == EINVAL
+    assert "potentials" in lib.spk_last_error().decode()
 
 
 def test_far_field_validation_and_workspace(lib):

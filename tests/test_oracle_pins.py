@@ -627,6 +627,29 @@ def test_constraint_check_simple_values():
 
 
 # --------------------------------------------------------------------------
+# Repulsion energy from the forces (homogeneity)
+# --------------------------------------------------------------------------
+def test_repulsion_energy_is_k_dot_its_gradient():
+    """With H = |d| every pair distance scales with K, so F^r is homogeneous of
+    degree 1 and Euler's theorem gives F^r = sum_i K[i] . dF^r/dK[i], on
+    jittered spokes whose echo-time samples coincide and on uniform points."""
+    for K in (inputs.radial_spokes(9, 40, 0.5, seed=31, jitter=0.05),
+              inputs.uniform_points(300, 0.5, seed=32)):
+        r = oracle.grad(K, [1.0], 1, 0.5)
+        Fr = oracle.energy(K, [1.0], 1, 0.5)[2]
+        assert float((K * r["dFr"]).sum()) == pytest.approx(Fr, rel=1e-13)
+
+
+def test_energy_from_force_fails_for_the_regularised_kernel():
+    """The identity needs homogeneity: with eps > 0 it is off by the eps terms
+    (a check that the pin above can fail)."""
+    K = inputs.uniform_points(300, 0.5, seed=32)
+    r = oracle.grad(K, [1.0], 1, 0.5, 0.05)
+    Fr = oracle.energy(K, [1.0], 1, 0.5, 0.05)[2]
+    assert abs(float((K * r["dFr"]).sum()) - Fr) > 1e-3 * Fr
+
+
+# --------------------------------------------------------------------------
 # Step-size policy
 # --------------------------------------------------------------------------
 def _small_problem():
