@@ -359,7 +359,10 @@ int sparkling_step_async(const spk_params *prm, void *kx, void *ky, void *kz, co
  * launches are not timed.  Every call on one device shares that device's
  * array: calls that overlap on one device (several streams or threads) race
  * and must be serialised by the caller.  No byte of the array needs to start
- * at any value: every call writes what it reads.
+ * at any value: every call writes what it reads.  The first call on a device
+ * looks up the array's device address (hipGetSymbolAddress, which may load
+ * the code object): make it outside graph capture; later calls only enqueue
+ * kernels and may be captured.
  * Errors: SPK_EWORKSPACE if spk_workspace_size(prm) exceeds SPK_SCRATCH_BYTES
  * (on a 32^3 density: p up to about 300,000 samples), SPK_EUNSUPPORTED for
  * far_field_depth > 0, otherwise as sparkling_step_async.
