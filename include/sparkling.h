@@ -382,13 +382,13 @@ size_t spk_noalloc_scratch_bytes(void);
  * 3 FMAs for |d|^2, v_rsq_f32, 4 FMAs, in one fixed order), the same without
  * the reciprocal square root (1), or the reciprocal square roots with one FMA
  * each (2), in registers only.  pairs (out) = blocks * 256 * iters * 8;
- * ms (out) = the launch's duration by HIP events.  scratch: device,
+ * ms (out) = the launch's duration by HIP events.  out: device,
  * >= blocks * 256 * 4 bytes (one result per thread, so nothing is removed).
  * Synchronises `stream`.  SPK_EINVAL for a bad variant, blocks outside
- * [1, 2^20] or iters < 1; SPK_EWORKSPACE for a short scratch.
+ * [1, 2^20] or iters < 1; SPK_EWORKSPACE for a short output buffer.
  */
-int spk_probe_pair_mix(int variant, int64_t blocks, int32_t iters, void *scratch,
-                       size_t scratch_bytes, double *pairs, double *ms, void *stream);
+int spk_probe_pair_mix(int variant, int64_t blocks, int32_t iters, void *out,
+                       size_t out_bytes, double *pairs, double *ms, void *stream);
 
 /*
  * Kernel timing.  While enabled, every kernel launch of the kinds below is

@@ -446,13 +446,13 @@ def probe_pair_mix(variant: str = "pair", blocks: int = 32768, iters: int = 1024
     the best of `reps` launches, as pairs/s and, for the full pair, TFLOP/s at
     the sweep's 17 flop/pair."""
     v = PROBE_VARIANTS[variant]
-    scratch = torch.empty(blocks * 256, dtype=torch.float32, device=device)
+    out = torch.empty(blocks * 256, dtype=torch.float32, device=device)
     pairs, ms = _dbl(), _dbl()
     best = None
     for _ in range(max(reps, 1)):
         _check(load_library().spk_probe_pair_mix(
-            v, blocks, iters, _vp(scratch.data_ptr()), scratch.numel() * 4, ctypes.byref(pairs),
-            ctypes.byref(ms), _stream(scratch)), "spk_probe_pair_mix")
+            v, blocks, iters, _vp(out.data_ptr()), out.numel() * 4, ctypes.byref(pairs),
+            ctypes.byref(ms), _stream(out)), "spk_probe_pair_mix")
         best = ms.value if best is None else min(best, ms.value)
     rate = pairs.value / (best * 1e-3)
     return {"variant": variant, "blocks": blocks, "iters": iters, "pairs": pairs.value,

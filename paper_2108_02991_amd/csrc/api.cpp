@@ -1164,8 +1164,8 @@ int sparkling_upsample(const spk_params *prm, const void *kx, const void *ky, co
     return SPK_OK;
 }
 
-int spk_probe_pair_mix(int variant, int64_t blocks, int32_t iters, void *scratch,
-                       size_t scratch_bytes, double *pairs, double *ms, void *stream)
+int spk_probe_pair_mix(int variant, int64_t blocks, int32_t iters, void *out,
+                       size_t out_bytes, double *pairs, double *ms, void *stream)
 {
     g_err.clear();
     if (variant < 0 || variant > 2)
@@ -1175,12 +1175,12 @@ int spk_probe_pair_mix(int variant, int64_t blocks, int32_t iters, void *scratch
     if (!pairs || !ms)
         return fail(SPK_EINVAL, "pairs and ms must not be NULL");
     int rc;
-    if ((rc = check_ptr(scratch, "scratch", 4)))
+    if ((rc = check_ptr(out, "out", 4)))
         return rc;
     const size_t need = sizeof(float) * (size_t)probe_out_elements(blocks);
-    if (scratch_bytes < need)
-        return fail(SPK_EWORKSPACE, "probe scratch needs %zu bytes (got %zu)", need,
-                    scratch_bytes);
+    if (out_bytes < need)
+        return fail(SPK_EWORKSPACE, "probe output needs %zu bytes (got %zu)", need,
+                    out_bytes);
     hipStream_t s = static_cast<hipStream_t>(stream);
     struct Ev {
         hipEvent_t a = nullptr, b = nullptr;
@@ -1195,7 +1195,7 @@ int spk_probe_pair_mix(int variant, int64_t blocks, int32_t iters, void *scratch
     SPK_HIP(hipEventCreate(&ev.a), "probe event");
     SPK_HIP(hipEventCreate(&ev.b), "probe event");
     SPK_HIP(hipEventRecord(ev.a, s), "probe event record");
-    SPK_HIP(launch_pair_mix_probe(variant, static_cast<float *>(scratch), blocks, iters, s),
+    SPK_HIP(launch_pair_mix_probe(variant, static_cast<float *>(out), blocks, iters, s),
             "probe launch");
     SPK_HIP(hipEventRecord(ev.b, s), "probe event record");
     SPK_HIP(hipEventSynchronize(ev.b), "probe synchronize");
