@@ -199,10 +199,13 @@ def main():
     probe = None
     if (not ff_depth and args.kernel == "distance" and precision == "fp32_comp"
             and not args.energy_from_force):
-        probe = spk.pair_issue_bound(device=dev)
-        log(f"pair issue bound: {probe['pairs_per_s']:.4g} pairs/s = "
-            f"{probe['tflops_at_17']:.2f} TFLOP/s at 17 flop/pair (reciprocal square root "
-            f"{probe['rsqrt_in_fma_slots']:.2f} FMA slots)")
+        try:
+            probe = spk.pair_issue_bound(device=dev)
+            log(f"pair issue bound: {probe['pairs_per_s']:.4g} pairs/s = "
+                f"{probe['tflops_at_17']:.2f} TFLOP/s at 17 flop/pair (reciprocal square root "
+                f"{probe['rsqrt_in_fma_slots']:.2f} FMA slots)")
+        except Exception as e:   # noqa: BLE001  (a calibration; the line is kept without it)
+            log(f"pair issue bound not measured: {type(e).__name__}: {e}")
 
     # Warm-up and timed steps each stop at a wall budget: an exact c3 step
     # takes about 26 s, so the requested counts may not fit.  Each step ends
