@@ -79,3 +79,16 @@ def test_c2_energy_from_force(gpu):
     say(f"  c2: F^r per pair {e[0][0]:.12e} ({e[0][1]:.1f} ms), from force {e[1][0]:.12e} "
         f"({e[1][1]:.1f} ms)")
     assert e[1][0] == pytest.approx(e[0][0], rel=1e-7)
+
+
+def test_discrepancy_with_energy_from_force(gpu):
+    """D = F - (1/2) sum rho rho H with F^r from the forces, against the oracle."""
+    K = inputs.radial_spokes(12, 40, 0.5, seed=73, jitter=0.05)
+    rho = inputs.radial_density(8, 0.5, 0.0625, 2.0)
+    prm = spk.Params(12, 40, 8, precision="plain_fp64", energy_from_force=True,
+                     discrepancy=True)
+    Kd, rd = device_problem(K, rho, "plain_fp64", gpu)
+    F, Fa, Fr, D = spk.energy(Kd, rd, prm)
+    oF = oracle.energy(K, rho, 8, 0.5)[0]
+    oD = oF - oracle.rho_self_energy(rho, 8, 0.5)
+    assert F == pytest.approx(oF, rel=1e-12) and D == pytest.approx(oD, rel=1e-9, abs=1e-15)

@@ -77,6 +77,28 @@ def test_warm_started_projection_bitwise(gpu, Ns, precision):
         assert np.array_equal(viol, oracle.constraint_check(host64(Kd), Nc, Ns, 0.5, a, b, 0))
 
 
+def test_warm_started_per_axis_projection_bitwise(gpu):
+    """Warm-started duals with per-axis (rotation-variant) bounds: two
+    projections in a row, output and dual state equal to the oracle's."""
+    Nc, Ns = 4, 333
+    K = inputs.radial_spokes(Nc, Ns, 0.5, seed=81, jitter=0.05)
+    a, b = bounds(configs.C5)
+    duals = torch.zeros((Nc, 6, Ns), dtype=torch.float64, device=gpu)
+    prm = spk.Params(Nc, Ns, 1, precision="plain_fp64", a_max=a, b_max=b, n_pit=120,
+                     rotation_variant=True, proj_duals=duals)
+    Kd, _ = device_problem(K, [1.0], "plain_fp64", gpu)
+    ref, ref_d = host64(Kd), np.zeros((Nc, 6, Ns))
+    rng = np.random.default_rng(82)
+    for call in range(2):
+        if call == 1:
+            Kd += torch.tensor(rng.uniform(-1e-3, 1e-3, K.shape), dtype=Kd.dtype, device=gpu)
+            ref = host64(Kd)
+        spk.project_(Kd, prm)
+        ref = oracle.project(ref, Nc, Ns, 0.5, a, b, 0, 120, rotation_variant=True, duals=ref_d)
+        assert np.array_equal(host64(Kd), ref)
+        assert np.array_equal(host64(duals), ref_d)
+
+
 def test_warm_started_steps_match_the_oracle(gpu):
     """Projected gradient steps with carried duals, in plain FP64, step by step
     against the oracle's steps with the same dual state."""
