@@ -36,7 +36,8 @@
  *    (8 for double), and must not alias each other except where an argument
  *    is documented as in/out.  The caller owns every buffer, including the
  *    workspace sized by spk_workspace_size(); the library allocates no device
- *    memory.
+ *    memory at run time and creates no stream (the static scratch of
+ *    sparkling_step_async_noalloc is part of its code object).
  *  - `stream` is a hipStream_t (NULL = the default stream).  Calls enqueue
  *    their kernels on it and return without waiting, except that any call
  *    writing a host output (a double* documented as "host") synchronises the
