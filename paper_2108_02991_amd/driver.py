@@ -175,11 +175,22 @@ def parse_far_field(spec):
     return int(f[0]), int(f[1]), R
 
 
-def _level_depth(depth: int, d: int) -> int:
-    """Octree depth of the far field at decimation level d: 8^depth leaves for
-    p / 2^d samples keep about as many samples per leaf when the depth drops by
-    one every three halvings; below depth 2 the sum is exact."""
-    if depth == 0:
+# Largest level (samples in all shots) whose repulsion is summed exactly when
+# the far field is on: the far field has a floor of about 10 ms per gradient
+# (tree, tables and the M2L's dependent chain) while the exact sweep takes
+# p^2 / 4.4e12 s, so the two cross near 2e5 samples.  On c3's shots a whole
+# step at 131,072 samples takes 4.9 ms exact against 9.9 ms with the far
+# field; at 262,144 the exact repulsion alone (15.6 ms) exceeds the far-field
+# step (10.9 ms).
+EXACT_MAX_P = 1 << 17
+
+
+def _level_depth(depth: int, d: int, p: int, exact_max_p: int = EXACT_MAX_P) -> int:
+    """Octree depth of the far field at decimation level d with p samples:
+    8^depth leaves for p / 2^d samples keep about as many samples per leaf when
+    the depth drops by one every three halvings; below depth 2, or at most
+    exact_max_p samples, the sum is exact."""
+    if depth == 0 or p <= exact_max_p:
         return 0
     dd = depth - (d + 1) // 3
     return dd if dd >= 2 else 0
@@ -187,7 +198,8 @@ def _level_depth(depth: int, d: int) -> int:
 
 def multiresolution(K0: torch.Tensor, rho: torch.Tensor, prm_full: api.Params, levels: int,
                     n_git: int, final_level: bool = True, eta_scale: float = 0.25, out=None,
-                    log_every: int = 0, eta_rule: str = "fixed", warm_duals: bool = False):
+                    log_every: int = 0, eta_rule: str = "fixed", warm_duals: bool = False,
+                    exact_max_p: int = EXACT_MAX_P):
     """Algorithm 1 (multi-resolution SPARKLING) on the GPU.
 
     K0 holds the coarsest shots, prm_full.n_samples >> levels samples each.  At
@@ -199,8 +211,9 @@ def multiresolution(K0: torch.Tensor, rho: torch.Tensor, prm_full: api.Params, l
     the next level.  With final_level=True the full resolution (d = 0) is
     optimised as well.  eta_rule="lipschitz" takes the fixed step 1/L of the
     regularised kernel at each level instead.  warm_duals=True carries the
-    projection's dual variables from step to step within a level.  Returns
-    the final K and the per-iteration records.
+    projection's dual variables from step to step within a level.  With the
+    far field on, levels of at most exact_max_p samples are summed exactly.
+    Returns the final K and the per-iteration records.
     """
     if prm_full.n_samples % (1 << levels):
         raise ValueError("n_samples must be divisible by 2^levels")
@@ -208,17 +221,16 @@ def multiresolution(K0: torch.Tensor, rho: torch.Tensor, prm_full: api.Params, l
     K = K0
     records = []
     for d in range(levels, -1 if final_level else 0, -1):
+        depth = _level_depth(prm_full.far_field_depth, d, prm_full.n_shots * Ns, exact_max_p)
         prm = api.Params(prm_full.n_shots, Ns, prm_full.grid, precision=prm_full.precision,
                          half_width=prm_full.half_width, eps=prm_full.eps,
                          a_max=prm_full.a_max * 2.0 ** d, b_max=prm_full.b_max * 2.0 ** d,
                          te_index=prm_full.te_index, n_pit=prm_full.n_pit,
                          rotation_variant=prm_full.rotation_variant, kernel=prm_full.kernel,
                          attraction_field=prm_full.attraction_field,
-                         far_field_depth=_level_depth(prm_full.far_field_depth, d),
+                         far_field_depth=depth,
                          far_field_order=prm_full.far_field_order,
-                         far_field_adaptive=(prm_full.far_field_adaptive
-                                             if _level_depth(prm_full.far_field_depth, d) > 0
-                                             else 0))
+                         far_field_adaptive=prm_full.far_field_adaptive if depth > 0 else 0)
         if K.shape[1] != prm.p:
             raise ValueError(f"level {d}: K has {K.shape[1]} samples, expected {prm.p}")
         eta = fixed_step(prm, float(rho.sum().item()), eta_rule,
@@ -274,6 +286,9 @@ def main():
     ap.add_argument("--far-field", default=None, metavar="DEPTH,ORDER[,adaptive[=R]]",
                     help="repulsion by the Chebyshev fast multipole method (e.g. 5,6 or "
                          "5,6,adaptive=2)")
+    ap.add_argument("--exact-max-p", type=int, default=EXACT_MAX_P,
+                    help="with --levels and --far-field: levels of at most this many samples "
+                         "are summed exactly")
     args = ap.parse_args()
     w = configs.WORKLOADS[args.workload]
     if args.n_pit is not None:
@@ -312,13 +327,14 @@ def main():
                       file=sys.stderr, flush=True)
             K, recs = multiresolution(K0, rho, prm, args.levels, iters, out=out,
                                       log_every=args.log_every, eta_rule=args.eta,
-                                      warm_duals=args.warm_duals)
+                                      warm_duals=args.warm_duals, exact_max_p=args.exact_max_p)
             torch.cuda.synchronize(dev)
             total = time.perf_counter() - t0
             F, _, _, _ = api.energy(K, rho, prm)
             summary = {"workload": w.name, "levels": args.levels, "n_git": iters,
                        "n_pit": w.n_pit, "precision": precision,
-                       "field": args.field, "total_s": total, "final_F": F,
+                       "field": args.field, "far_field": args.far_field,
+                       "exact_max_p": args.exact_max_p, "total_s": total, "final_F": F,
                        "s_per_level": {str(d): sum(r["s"] for r in recs if r["level"] == d)
                                        for d in range(args.levels, -1, -1)}}
             print(json.dumps(summary), flush=True)
