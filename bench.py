@@ -31,6 +31,7 @@ import dataclasses
 import json
 import os
 import sys
+import threading
 import time
 
 import numpy as np
@@ -59,6 +60,93 @@ SWEEP_SOURCES = [os.path.join(ROOT, "paper_2108_02991_amd", "csrc", f)
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+class EngineClock:
+    """The GPU's shader (GFX) clock, sampled through amd-smi's metrics every
+    `period_s` while the timed steps run (the published peaks assume 2.4 GHz).
+    `result()` gives the median, mean, minimum and maximum in MHz over the
+    samples (each the mean of the per-XCD clocks), or None when the library or
+    the device's metrics are not reachable (`error` then says why) or the timed
+    region ended before the first sample."""
+
+    def __init__(self, period_s: float = 0.1):
+        self.period = period_s
+        self.samples: list[float] = []
+        self.error = None
+        self._stop = threading.Event()
+        self._thread = None
+        self._smi = None
+        self._handle = None
+
+    def start(self, device_index: int = 0) -> "EngineClock":
+        try:
+            import amdsmi
+            import torch
+            amdsmi.amdsmi_init()
+            self._smi = amdsmi
+            handles = amdsmi.amdsmi_get_processor_handles()
+            bus = getattr(torch.cuda.get_device_properties(device_index), "pci_bus_id", None)
+            match = [h for h in handles if bus is not None
+                     and int(amdsmi.amdsmi_get_gpu_device_bdf(h).split(":")[1], 16) == bus]
+            if len(match) != 1:
+                match = handles if len(handles) == 1 else []
+            if not match:
+                raise RuntimeError(f"no unique amd-smi device for PCI bus {bus}")
+            self._handle = match[0]
+            self._read()    # reachable? (taken before the work starts: not a sample)
+        except Exception as e:   # noqa: BLE001  (reported, never fatal)
+            self.error = f"{type(e).__name__}: {e}"
+            self._close()
+            return self
+        self._thread = threading.Thread(target=self._run, daemon=True)
+        self._thread.start()
+        return self
+
+    def _read(self) -> float:
+        m = self._smi.amdsmi_get_gpu_metrics_info(self._handle)
+        clocks = m.get("current_gfxclks")
+        valid = [float(c) for c in (clocks if isinstance(clocks, list) else [])
+                 if isinstance(c, (int, float)) and 0 < c < 10000]
+        if valid:
+            return sum(valid) / len(valid)
+        c = m.get("current_gfxclk")
+        if isinstance(c, (int, float)) and 0 < c < 10000:
+            return float(c)
+        raise RuntimeError("no GFX clock in the device metrics")
+
+    def _run(self):
+        while not self._stop.wait(self.period):
+            try:
+                self.samples.append(self._read())
+            except Exception:   # noqa: BLE001  (a missed sample)
+                pass
+
+    def _close(self):
+        if self._smi is not None:
+            try:
+                self._smi.amdsmi_shut_down()
+            except Exception:   # noqa: BLE001
+                pass
+            self._smi = None
+
+    def stop(self):
+        self._stop.set()
+        if self._thread is not None:
+            self._thread.join()
+        self._close()
+
+    def result(self):
+        if not self.samples:
+            return None
+        mean = sum(self.samples) / len(self.samples)
+        return {"mhz_median": float(np.median(self.samples)), "mhz_mean": mean,
+                "mhz_min": min(self.samples), "mhz_max": max(self.samples),
+                "samples": len(self.samples), "period_s": self.period,
+                "source": "amd-smi gpu metrics (mean of the per-XCD GFX clocks) during the "
+                          "timed steps",
+                "fp32_peak_at_median_clock_tflops":
+                    FP32_VECTOR_PEAK_TFLOPS * float(np.median(self.samples)) / 2400.0}
 
 
 def sweep_source_hash() -> str:
@@ -226,6 +314,7 @@ def main():
     spk.timing_reset()
     spk.timing_enable(True)
     infos = []
+    clock = EngineClock().start(0)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     while len(infos) < args.steps:
@@ -237,7 +326,10 @@ def main():
             break
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    clock.stop()
     spk.timing_enable(False)
+    if clock.error:
+        log(f"engine clock not sampled: {clock.error}")
     steps = len(infos)
     if steps < args.steps:
         log(f"timed {steps} of {args.steps} requested steps within the {args.time_budget:.0f} s "
@@ -316,6 +408,7 @@ def main():
                                        probe["fixed_order_mix_pairs_per_s"]}
                                   if probe else None)}
                      if not ff_depth else None),
+        "engine_clock": clock.result(),
         "last_step": {k: (v.tolist() if isinstance(v, np.ndarray) else v)
                       for k, v in infos[-1].items()},
         "initial_projection": ({"n_pit": args.init_pit, "viol": init_viol.tolist()}
