@@ -65,6 +65,8 @@ def log(msg):
 class EngineClock:
     """The GPU's shader (GFX) clock, sampled through amd-smi's metrics every
     `period_s` while the timed steps run (the published peaks assume 2.4 GHz).
+    All amd-smi calls run on a daemon thread, so the benchmark never waits on
+    the library: `stop()` waits at most a few seconds for the thread.
     `result()` gives the median, mean, minimum and maximum in MHz over the
     samples (each the mean of the per-XCD clocks), or None when the library or
     the device's metrics are not reachable (`error` then says why) or the timed
@@ -76,35 +78,21 @@ class EngineClock:
         self.error = None
         self._stop = threading.Event()
         self._thread = None
-        self._smi = None
-        self._handle = None
 
     def start(self, device_index: int = 0) -> "EngineClock":
         try:
-            import amdsmi
             import torch
-            amdsmi.amdsmi_init()
-            self._smi = amdsmi
-            handles = amdsmi.amdsmi_get_processor_handles()
             bus = getattr(torch.cuda.get_device_properties(device_index), "pci_bus_id", None)
-            match = [h for h in handles if bus is not None
-                     and int(amdsmi.amdsmi_get_gpu_device_bdf(h).split(":")[1], 16) == bus]
-            if len(match) != 1:
-                match = handles if len(handles) == 1 else []
-            if not match:
-                raise RuntimeError(f"no unique amd-smi device for PCI bus {bus}")
-            self._handle = match[0]
-            self._read()    # reachable? (taken before the work starts: not a sample)
         except Exception as e:   # noqa: BLE001  (reported, never fatal)
             self.error = f"{type(e).__name__}: {e}"
-            self._close()
             return self
-        self._thread = threading.Thread(target=self._run, daemon=True)
+        self._thread = threading.Thread(target=self._run, args=(bus,), daemon=True)
         self._thread.start()
         return self
 
-    def _read(self) -> float:
-        m = self._smi.amdsmi_get_gpu_metrics_info(self._handle)
+    @staticmethod
+    def _read(smi, handle) -> float:
+        m = smi.amdsmi_get_gpu_metrics_info(handle)
         clocks = m.get("current_gfxclks")
         valid = [float(c) for c in (clocks if isinstance(clocks, list) else [])
                  if isinstance(c, (int, float)) and 0 < c < 10000]
@@ -115,38 +103,54 @@ class EngineClock:
             return float(c)
         raise RuntimeError("no GFX clock in the device metrics")
 
-    def _run(self):
-        while not self._stop.wait(self.period):
+    def _run(self, bus):
+        try:
+            import amdsmi
+            amdsmi.amdsmi_init()
+        except Exception as e:   # noqa: BLE001
+            self.error = f"{type(e).__name__}: {e}"
+            return
+        try:
+            handles = amdsmi.amdsmi_get_processor_handles()
+            match = [h for h in handles if bus is not None
+                     and int(amdsmi.amdsmi_get_gpu_device_bdf(h).split(":")[1], 16) == bus]
+            if len(match) != 1:
+                match = handles if len(handles) == 1 else []
+            if not match:
+                raise RuntimeError(f"no unique amd-smi device for PCI bus {bus}")
+            self._read(amdsmi, match[0])    # reachable? (before the work starts: not a sample)
+            while not self._stop.wait(self.period):
+                try:
+                    self.samples.append(self._read(amdsmi, match[0]))
+                except Exception:   # noqa: BLE001  (a missed sample)
+                    pass
+        except Exception as e:   # noqa: BLE001
+            self.error = f"{type(e).__name__}: {e}"
+        finally:
             try:
-                self.samples.append(self._read())
-            except Exception:   # noqa: BLE001  (a missed sample)
-                pass
-
-    def _close(self):
-        if self._smi is not None:
-            try:
-                self._smi.amdsmi_shut_down()
+                amdsmi.amdsmi_shut_down()
             except Exception:   # noqa: BLE001
                 pass
-            self._smi = None
 
-    def stop(self):
+    def stop(self, wait_s: float = 5.0):
         self._stop.set()
         if self._thread is not None:
-            self._thread.join()
-        self._close()
+            self._thread.join(wait_s)
+            if self._thread.is_alive():
+                self.error = self.error or "clock sampler still busy after the timed region"
 
     def result(self):
-        if not self.samples:
+        samples = list(self.samples)
+        if not samples:
             return None
-        mean = sum(self.samples) / len(self.samples)
-        return {"mhz_median": float(np.median(self.samples)), "mhz_mean": mean,
-                "mhz_min": min(self.samples), "mhz_max": max(self.samples),
-                "samples": len(self.samples), "period_s": self.period,
+        mean = sum(samples) / len(samples)
+        return {"mhz_median": float(np.median(samples)), "mhz_mean": mean,
+                "mhz_min": min(samples), "mhz_max": max(samples),
+                "samples": len(samples), "period_s": self.period,
                 "source": "amd-smi gpu metrics (mean of the per-XCD GFX clocks) during the "
                           "timed steps",
                 "fp32_peak_at_median_clock_tflops":
-                    FP32_VECTOR_PEAK_TFLOPS * float(np.median(self.samples)) / 2400.0}
+                    FP32_VECTOR_PEAK_TFLOPS * float(np.median(samples)) / 2400.0}
 
 
 def sweep_source_hash() -> str:
@@ -158,10 +162,12 @@ def sweep_source_hash() -> str:
     return h.hexdigest()
 
 
-def recorded_traffic(workload: str, precision: str, kernel: str = "distance"):
+def recorded_traffic(workload: str, precision: str, kernel: str = "distance",
+                     energy: bool = True):
     """HBM bytes per repulsion launch from the committed counter summary, or None
-    when the summary is missing, is for another workload, or the sweep sources
-    changed since the counters were taken."""
+    when the summary is missing, is for another workload or another variant of
+    the sweep (kernel, per-pair energy on or off), or the sweep sources changed
+    since the counters were taken."""
     try:
         with open(TRAFFIC_RECORD) as f:
             rec = dict(line[2:].split(": ", 1) for line in f.read().splitlines()
@@ -169,7 +175,8 @@ def recorded_traffic(workload: str, precision: str, kernel: str = "distance"):
     except OSError:
         return None
     if (rec.get("source_sha256") != sweep_source_hash() or rec.get("workload") != workload
-            or rec.get("precision") != precision or rec.get("kernel", "distance") != kernel):
+            or rec.get("precision") != precision or rec.get("kernel", "distance") != kernel
+            or rec.get("energy") != ("true" if energy else "false")):
         return None
     return float(rec["traffic_bytes_per_launch"])
 
@@ -395,7 +402,8 @@ def main():
         },
         "roofline": ({"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS,
                       "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK_TFLOPS,
-                      "traffic": recorded_traffic(w.name, precision, args.kernel),
+                      "traffic": recorded_traffic(w.name, precision, args.kernel,
+                                                  not args.energy_from_force),
                       "ceiling": ({"kind": "issue bound of the pair from measured component "
                                            "rates: its 10 FP32 instructions at their stream "
                                            "rate plus one reciprocal square root at its cost "
