@@ -43,6 +43,19 @@ def test_ragged_multi_tile_all_targets(gpu, precision):
         assert abs(got - want) <= ENERGY_TOL[precision] * abs(want)
 
 
+@pytest.mark.parametrize("G", [3, 4, 8, 20, 21])
+def test_cell_sweep_row_lengths(gpu, G):
+    """FP32-comp cell sweep on rows of 3 (no whole group of four cells), 4 (one group),
+    8, 20 (an odd number of groups) and 21 cells (groups and a remainder): every row
+    length the read-ahead distinguishes, against the oracle on every target."""
+    K = inputs.radial_spokes(9, 70, 0.5, seed=23, jitter=0.05)
+    rho = inputs.radial_density(G, 0.5, 0.0625, 2.0)
+    prm, Kd, rd, g, pa, pr, en, ref = run_case(gpu, K, rho, G, "fp32_comp")
+    assert rel_l2(g, ref["dF"]) <= GRAD_TOL["fp32_comp"]
+    assert rel_l2(pa, ref["ua"]) <= ENERGY_TOL["fp32_comp"]
+    assert row_rel_max(g, ref["dF"]) <= ROW_TOL["fp32_comp"]
+
+
 def test_c1_plain_fp64_every_target(gpu):
     w = configs.C1
     K, rho = w.trajectory(), w.density()
