@@ -76,9 +76,8 @@ template <int NPT> constexpr int project_waves() { return NPT == 2 ? 4 : 1; }
 
 template <typename T, int NPT, bool PER_AXIS>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(project_waves<NPT>())))
-void project_kernel(T *kx, T *ky, T *kz, int64_t Ns, double L,
-                                                     double a, double b, int64_t te, int n_pit,
-                                                     const double *gate, double *duals)
+void project_kernel(T *kx, T *ky, T *kz, int64_t Ns, double L, double a, double b, int64_t te,
+                    int n_pit, const double *gate, double *duals)
 {
 #pragma clang fp contract(off)
     static_assert(NPT >= 2, "two-sample halo needs NPT >= 2");
