@@ -77,6 +77,33 @@ def test_warm_started_projection_bitwise(gpu, Ns, precision):
         assert np.array_equal(viol, oracle.constraint_check(host64(Kd), Nc, Ns, 0.5, a, b, 0))
 
 
+@pytest.mark.parametrize("Ns", [64, 1025, 2048])
+def test_warm_start_ignores_entries_past_the_ranges(gpu, Ns):
+    """Dual slots past their ranges (q[Ns-1], r[Ns-2], r[Ns-1]) hold NaN on entry:
+    the projection reads them as 0 and writes 0 there, like the oracle, and the
+    output equals the oracle's bit for bit."""
+    Nc = 3
+    K = inputs.radial_spokes(Nc, Ns, 0.5, seed=Ns + 7, jitter=0.05)
+    a, b = bounds(configs.C5)
+    rng = np.random.default_rng(Ns + 7)
+    d0 = rng.normal(scale=1e-3, size=(Nc, 6, Ns))
+    d0[:, :3, Ns - 1] = np.nan
+    d0[:, 3:, Ns - 2:] = np.nan
+    duals = torch.tensor(d0, device=gpu)
+    prm = spk.Params(Nc, Ns, 1, precision="plain_fp64", a_max=a, b_max=b, n_pit=80,
+                     proj_duals=duals)
+    Kd, _ = device_problem(K, [1.0], "plain_fp64", gpu)
+    ref_d = d0.copy()
+    ref = oracle.project(host64(Kd), Nc, Ns, 0.5, a, b, 0, 80, duals=ref_d)
+    say(f"  warm projection with NaN past the ranges, Ns={Ns}")
+    spk.project_(Kd, prm)
+    assert np.array_equal(host64(Kd), ref), np.abs(host64(Kd) - ref).max()
+    got_d = host64(duals)
+    assert np.array_equal(got_d, ref_d)
+    assert not np.isnan(got_d).any()
+    assert np.all(got_d[:, :3, Ns - 1] == 0.0) and np.all(got_d[:, 3:, Ns - 2:] == 0.0)
+
+
 def test_warm_started_per_axis_projection_bitwise(gpu):
     """Warm-started duals with per-axis (rotation-variant) bounds: two
     projections in a row, output and dual state equal to the oracle's."""
