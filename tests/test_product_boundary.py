@@ -34,3 +34,26 @@ def test_library_build_flags_disable_packed_fp32():
     from paper_2108_02991_amd import build
     flags = " ".join(build.FLAGS)
     assert "-packed-fp32-ops" in flags and "gfx950" in flags
+
+
+def test_bench_clock_sampler_never_holds_the_run():
+    """Without a reachable device the shader-clock sampler reports why and gives
+    no figure; stop() returns at once."""
+    import time
+    sys.path.insert(0, ROOT)
+    import bench
+    c = bench.EngineClock(period_s=0.01).start(0)
+    t0 = time.perf_counter()
+    c.stop(wait_s=5.0)
+    assert time.perf_counter() - t0 < 5.0
+    if c.result() is None:
+        assert c.error
+
+
+def test_bench_traffic_record_is_tied_to_the_sweep_variant():
+    sys.path.insert(0, ROOT)
+    import bench
+    w, prec = "c3_fp32_comp_8p4M", "fp32_comp"
+    assert bench.recorded_traffic(w, prec, energy=False) is None
+    assert bench.recorded_traffic(w, prec, kernel="log") is None
+    assert bench.recorded_traffic("c5_loop", prec) is None
