@@ -163,11 +163,12 @@ def sweep_source_hash() -> str:
 
 
 def recorded_traffic(workload: str, precision: str, kernel: str = "distance",
-                     energy: bool = True):
+                     energy: bool = True, pairs_per_launch: float | None = None):
     """HBM bytes per repulsion launch from the committed counter summary, or None
     when the summary is missing, is for another workload or another variant of
-    the sweep (kernel, per-pair energy on or off), or the sweep sources changed
-    since the counters were taken."""
+    the sweep (kernel, per-pair energy on or off), for launches of another size
+    (pairs_per_launch, when given), or the sweep sources changed since the
+    counters were taken."""
     try:
         with open(TRAFFIC_RECORD) as f:
             rec = dict(line[2:].split(": ", 1) for line in f.read().splitlines()
@@ -177,6 +178,10 @@ def recorded_traffic(workload: str, precision: str, kernel: str = "distance",
     if (rec.get("source_sha256") != sweep_source_hash() or rec.get("workload") != workload
             or rec.get("precision") != precision or rec.get("kernel", "distance") != kernel
             or rec.get("energy") != ("true" if energy else "false")):
+        return None
+    if pairs_per_launch is not None and (
+            "pairs_per_launch" not in rec
+            or abs(float(rec["pairs_per_launch"]) - pairs_per_launch) > 1e-6 * pairs_per_launch):
         return None
     return float(rec["traffic_bytes_per_launch"])
 
@@ -403,7 +408,8 @@ def main():
         "roofline": ({"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS,
                       "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK_TFLOPS,
                       "traffic": recorded_traffic(w.name, precision, args.kernel,
-                                                  not args.energy_from_force),
+                                                  not args.energy_from_force,
+                                                  rep_pairs_per_launch),
                       "ceiling": ({"kind": "issue bound of the pair from measured component "
                                            "rates: its 10 FP32 instructions at their stream "
                                            "rate plus one reciprocal square root at its cost "

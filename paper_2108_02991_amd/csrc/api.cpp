@@ -233,8 +233,12 @@ struct Plan {
     int64_t unit = 1;        // pair interactions per source and target
 };
 
-// Pair interactions one launch may carry at most (~0.3-0.6 s at full rate).
-constexpr double kMaxPairsPerLaunch = 1099511627776.0;   // 2^40
+// Pair interactions of one slab at most (~0.25-0.5 s at full rate), and of one
+// launch, whose grid's y extent holds several slabs: each launch ends with a
+// few milliseconds in which its last blocks drain, so four slabs per launch
+// save most of that against one (the partials then hold four slabs).
+constexpr double kMaxPairsPerSlab = 1099511627776.0;   // 2^40
+constexpr double kMaxPairsPerLaunch = 4.0 * kMaxPairsPerSlab;
 // Blocks a launch should have to fill 256 CUs several times over.
 constexpr int64_t kWantBlocks = 2048;
 // Slabs one launch may carry (the grid's y extent).
@@ -249,7 +253,9 @@ Plan make_plan(int precision, bool cells, int64_t p_total, int64_t n_src, int64_
     const int64_t gran = cells ? std::max<int64_t>(1, (precision == SPK_PLAIN_FP64 ? kCellTileF64
                                                                                   : kCellTileF32) / G)
                                : kSampleTile;
-    const double max_pairs = precision == SPK_PLAIN_FP64 ? kMaxPairsPerLaunch / 2 : kMaxPairsPerLaunch;
+    const double max_pairs = precision == SPK_PLAIN_FP64 ? kMaxPairsPerSlab / 2 : kMaxPairsPerSlab;
+    const double max_launch =
+        precision == SPK_PLAIN_FP64 ? kMaxPairsPerLaunch / 2 : kMaxPairsPerLaunch;
     const int64_t nslab_par = std::max<int64_t>(1, (kWantBlocks + tb - 1) / tb);
     int64_t slab = (n_src + nslab_par - 1) / nslab_par;
     const double per_src = (double)p_total * (double)pl.unit;
@@ -259,7 +265,7 @@ Plan make_plan(int precision, bool cells, int64_t p_total, int64_t n_src, int64_
     slab = std::max<int64_t>(slab, gran);
     pl.slab = slab;
     pl.nslab = (n_src + slab - 1) / slab;
-    const int64_t fit = (int64_t)(max_pairs / (per_src * (double)slab));
+    const int64_t fit = (int64_t)(max_launch / (per_src * (double)slab));
     pl.per_launch = std::max<int64_t>(1, std::min({pl.nslab, fit, kMaxSlabsPerLaunch}));
     return pl;
 }

@@ -57,3 +57,4 @@ def test_bench_traffic_record_is_tied_to_the_sweep_variant():
     assert bench.recorded_traffic(w, prec, energy=False) is None
     assert bench.recorded_traffic(w, prec, kernel="log") is None
     assert bench.recorded_traffic("c5_loop", prec) is None
+    assert bench.recorded_traffic(w, prec, pairs_per_launch=12345.0) is None
