@@ -239,6 +239,10 @@ struct Plan {
 // save most of that against one (the partials then hold four slabs).
 constexpr double kMaxPairsPerSlab = 1099511627776.0;   // 2^40
 constexpr double kMaxPairsPerLaunch = 4.0 * kMaxPairsPerSlab;
+// Slabs are grouped only while one launch's partials (32 B per target and
+// slab) stay within this, so that very large problems keep one slab per
+// launch and a workspace of about 100 B per sample.
+constexpr double kMaxGroupedPartialBytes = 1073741824.0;   // 2^30
 // Blocks a launch should have to fill 256 CUs several times over.
 constexpr int64_t kWantBlocks = 2048;
 // Slabs one launch may carry (the grid's y extent).
@@ -266,7 +270,8 @@ Plan make_plan(int precision, bool cells, int64_t p_total, int64_t n_src, int64_
     pl.slab = slab;
     pl.nslab = (n_src + slab - 1) / slab;
     const int64_t fit = (int64_t)(max_launch / (per_src * (double)slab));
-    pl.per_launch = std::max<int64_t>(1, std::min({pl.nslab, fit, kMaxSlabsPerLaunch}));
+    const int64_t room = (int64_t)(kMaxGroupedPartialBytes / (32.0 * (double)p_total));
+    pl.per_launch = std::max<int64_t>(1, std::min({pl.nslab, fit, room, kMaxSlabsPerLaunch}));
     return pl;
 }
 
